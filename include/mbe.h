@@ -1,0 +1,151 @@
+/*
+ * mbe.h -- C interface of the MI355X maximal biclique enumeration library (libmbe.so).
+ *
+ * The library enumerates the maximal bicliques of a bipartite graph G = (U u V, E): the
+ * pairs (A, B) with A a non-empty subset of U, B a non-empty subset of V, every a in A
+ * adjacent to every b in B, and neither side extendable (B = N(A) and A = N(B), with N(X)
+ * the common neighbours of X).  This is the set defined in section II-A of "Accelerating
+ * Maximal Biclique Enumeration on GPUs" (Hsieh, Chang, Cheng, Kuo, arXiv 2401.05039), and
+ * the search that produces it is the MBEA branch-and-bound of Algorithm 1 (section II-B),
+ * run as a depth-first search on an explicit per-wave stack inside HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point:
+ *   - Vertex ids are int32, 0-based.  |E| fits in int32.
+ *   - Results are exact integers; there is no floating point anywhere in the search.
+ *   - Every call is synchronous on the stream given in mbe_options (NULL: the null stream)
+ *     and returns 0 (MBE_OK) or a negative MBE_ERR_* code; mbe_strerror names the code.
+ *   - Input arrays are owned by the caller and never written or freed by the library.
+ *   - The library allocates device memory for its own working state and keeps it cached per
+ *     device between calls.  Calls on one device are serialised by an internal lock.
+ */
+#ifndef MBE_H
+#define MBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------- error codes */
+#define MBE_OK                    0
+#define MBE_ERR_INVALID_ARG      -1  /* null pointer where one is required, negative size */
+#define MBE_ERR_INVALID_GRAPH    -2  /* bad offsets, unsorted/duplicate row, id out of range,
+                                        or the two CSR arrays are not transposes */
+#define MBE_ERR_BUFFER_TOO_SMALL -3  /* records did not fit; the mbe_result is still complete */
+#define MBE_ERR_OUT_OF_MEMORY    -4  /* device allocation failed */
+#define MBE_ERR_DEVICE           -5  /* a HIP runtime call failed */
+#define MBE_ERR_UNSUPPORTED      -6  /* a top-level candidate's degree exceeds MBE_MAX_DEGREE */
+
+/* Largest degree a top-level candidate may have: its neighbour set is held as a bit mask of
+ * at most this many bits. */
+#define MBE_MAX_DEGREE 1024
+
+/* ------------------------------------------------------------------------- graph */
+/*
+ * The bipartite graph as two compressed-sparse-row arrays that must be exact transposes.
+ *   u_off[n_u + 1]: u_off[0] = 0, non-decreasing, u_off[n_u] = n_edges.
+ *   u_adj[n_edges]: row u = u_adj[u_off[u] .. u_off[u+1]) lists N(u) (ids in V), strictly
+ *                   ascending.
+ *   v_off[n_v + 1], v_adj[n_edges]: the same for V, listing ids in U.
+ * on_device = 0: the four arrays are host memory (copied to the device by the call);
+ * on_device = 1: they are device memory of the current HIP device (e.g. torch data_ptr()).
+ */
+typedef struct mbe_graph {
+    int32_t n_u, n_v;
+    int32_t n_edges;
+    const int32_t *u_off, *u_adj;
+    const int32_t *v_off, *v_adj;
+    int32_t on_device;
+} mbe_graph;
+
+/* ------------------------------------------------------------------------- result */
+/*
+ * count      number of maximal bicliques found
+ * hash       sum over them of h(A, B), mod 2^64, with
+ *              mix(z) = SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014),
+ *              K = 0x9E3779B97F4A7C15, hu(a) = mix(K (2a+1)), hv(b) = mix(K (2b+2)),
+ *              h(A, B) = mix(sum_{a in A} hu(a) + mix(sum_{b in B} hv(b) + K)).
+ *            It does not depend on the order of bicliques or of vertices inside them.
+ * out_ints   sum over bicliques of 2 + |A| + |B| (the ints mbe_enumerate needs)
+ * nodes, nonmaximal, max_depth, bytes_alg
+ *            search-tree diagnostics, filled when mbe_options.diagnostics = 1, else 0:
+ *            candidates taken, candidates whose maximality check failed, deepest level
+ *            (top level = 1), and the algorithmic bytes of the tree (4 bytes per id read or
+ *            written by the reverse-scanning method of section III-E, see the design notes).
+ * side       candidate side used: 1 = U, 2 = V
+ * kernel_ms  device time of the search kernel(s) of this call, from HIP events
+ */
+typedef struct mbe_result {
+    uint64_t count;
+    uint64_t hash;
+    uint64_t out_ints;
+    uint64_t nodes;
+    uint64_t nonmaximal;
+    uint64_t bytes_alg;
+    uint32_t max_depth;
+    uint32_t side;
+    double kernel_ms;
+} mbe_result;
+
+/* ------------------------------------------------------------------------- options */
+/*
+ * Zero-initialised fields mean "default"; a NULL mbe_options pointer means all defaults.
+ *   side         0: the smaller side holds the candidates (U on a tie); 1: U; 2: V.
+ *                The answer does not depend on it; records are always reported as (A in U,
+ *                B in V).
+ *   wg_waves     64-lane waves per workgroup (1..8; default 8).
+ *   grid         workgroups of the persistent search kernel (default: 2 per compute unit).
+ *   diagnostics  1: also compute nodes / nonmaximal / max_depth / bytes_alg.
+ *   no_validate  1: skip the O(|E|) check of the CSR pair (the caller vouches for it).
+ *   root_lo, root_hi
+ *                restrict the search to the top-level candidates whose rank lies in
+ *                [root_lo, root_hi) (rank = position in ascending (degree, id) order among
+ *                candidates of degree > 0); root_hi <= 0 means "to the end".  Results over
+ *                disjoint rank ranges add up to the whole result.
+ *   stream       hipStream_t to run on, or NULL.
+ */
+typedef struct mbe_options {
+    int32_t side;
+    int32_t wg_waves;
+    int32_t grid;
+    int32_t diagnostics;
+    int32_t no_validate;
+    int32_t reserved0;
+    int64_t root_lo;
+    int64_t root_hi;
+    void *stream;
+} mbe_options;
+
+/*
+ * Count the maximal bicliques of g and hash them (algorithm: MBEA, Algorithm 1, with the
+ * reverse-scanning count of section III-E).  out receives the mbe_result described above.
+ * Errors: MBE_ERR_INVALID_ARG (g or out NULL, negative sizes, missing arrays),
+ * MBE_ERR_INVALID_GRAPH, MBE_ERR_UNSUPPORTED, MBE_ERR_OUT_OF_MEMORY, MBE_ERR_DEVICE.
+ * An empty side or zero edges gives count = hash = 0.
+ */
+int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out);
+
+/*
+ * As mbe_count, and also write the bicliques to buf as records
+ *     [|A|, |B|, a_1 < ... < a_|A|, b_1 < ... < b_|B|]     (A in U, B in V)
+ * sorted by A lexicographically (a total order: A determines B).  buf holds buf_cap_ints
+ * int32 values; buf_on_device = 1 if it is device memory, 0 if host memory.  When the
+ * records need more than buf_cap_ints ints the call returns MBE_ERR_BUFFER_TOO_SMALL with
+ * out fully filled (out->out_ints is the size needed) and buf's contents unspecified.
+ */
+int mbe_enumerate(const mbe_graph *g, const mbe_options *opt, mbe_result *out,
+                  int32_t *buf, uint64_t buf_cap_ints, int32_t buf_on_device);
+
+/* Human-readable name of a return code (static storage; never NULL). */
+const char *mbe_strerror(int code);
+
+/* Library version as "major.minor.patch" (static storage). */
+const char *mbe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBE_H */

@@ -1,0 +1,204 @@
+"""MI355X maximal biclique enumeration: Python binding of ``libmbe.so``.
+
+The functions here only marshal arguments to the C interface declared in
+``include/mbe.h``; every step of the enumeration runs in the library's HIP kernels.
+Graphs are passed as two sorted CSR arrays (see ``include/mbe.h``); host arrays (numpy)
+are copied by the library, device arrays (torch tensors on a HIP device) are used in place.
+
+The library must be built first (``python -m paper_2401_05039_amd.build`` or
+``__graft_entry__.build()``); importing the binding fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Any, Dict, List, Optional, Tuple
+
+import numpy as np
+
+__all__ = ["mbe_count", "mbe_enumerate", "mbe_strerror", "mbe_version", "MbeError", "Options",
+           "lib_path", "load"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmbe.so")
+_lib = None
+
+MBE_OK = 0
+MBE_ERR_INVALID_ARG = -1
+MBE_ERR_INVALID_GRAPH = -2
+MBE_ERR_BUFFER_TOO_SMALL = -3
+MBE_ERR_OUT_OF_MEMORY = -4
+MBE_ERR_DEVICE = -5
+MBE_ERR_UNSUPPORTED = -6
+MBE_MAX_DEGREE = 1024
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n_u", ctypes.c_int32), ("n_v", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("u_off", ctypes.c_void_p), ("u_adj", ctypes.c_void_p),
+                ("v_off", ctypes.c_void_p), ("v_adj", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("hash", ctypes.c_uint64), ("out_ints", ctypes.c_uint64),
+                ("nodes", ctypes.c_uint64), ("nonmaximal", ctypes.c_uint64),
+                ("bytes_alg", ctypes.c_uint64), ("max_depth", ctypes.c_uint32),
+                ("side", ctypes.c_uint32), ("kernel_ms", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("side", ctypes.c_int32), ("wg_waves", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("diagnostics", ctypes.c_int32), ("no_validate", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("root_lo", ctypes.c_int64),
+                ("root_hi", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+
+
+@dataclasses.dataclass
+class Options:
+    """Mirror of ``mbe_options``; zero means default."""
+    side: int = 0
+    wg_waves: int = 0
+    grid: int = 0
+    diagnostics: bool = False
+    no_validate: bool = False
+    root_lo: int = 0
+    root_hi: int = 0
+    stream: Optional[int] = None  # hipStream_t as an integer; None = torch's current stream
+
+
+class MbeError(RuntimeError):
+    def __init__(self, code: int, result: Optional[Dict[str, Any]] = None):
+        super().__init__(f"mbe error {code}: {mbe_strerror(code)}")
+        self.code = code
+        self.result = result
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libmbe.so (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2401_05039_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.mbe_count.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
+    lib.mbe_count.restype = ctypes.c_int
+    lib.mbe_enumerate.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result),
+                                  ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32]
+    lib.mbe_enumerate.restype = ctypes.c_int
+    lib.mbe_strerror.argtypes = [ctypes.c_int]
+    lib.mbe_strerror.restype = ctypes.c_char_p
+    lib.mbe_version.argtypes = []
+    lib.mbe_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def mbe_strerror(code: int) -> str:
+    return load().mbe_strerror(int(code)).decode()
+
+
+def mbe_version() -> str:
+    return load().mbe_version().decode()
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _marshal_graph(g) -> Tuple[_Graph, List[Any]]:
+    """Build the C struct; keeps references to the arrays alive in the returned list."""
+    arrs = [g.u_off, g.u_adj, g.v_off, g.v_adj]
+    on_dev = all(_is_torch(a) and a.is_cuda for a in arrs)
+    keep: List[Any] = []
+    ptrs = []
+    if on_dev:
+        import torch
+        for a in arrs:
+            if a.dtype != torch.int32 or not a.is_contiguous():
+                a = a.to(torch.int32).contiguous()
+            keep.append(a)
+            ptrs.append(a.data_ptr())
+    else:
+        for a in arrs:
+            if _is_torch(a):
+                a = a.cpu().numpy()
+            a = np.ascontiguousarray(a, dtype=np.int32)
+            keep.append(a)
+            ptrs.append(a.ctypes.data)
+    n_edges = int(keep[1].shape[0]) if hasattr(keep[1], "shape") else len(keep[1])
+    cg = _Graph(int(g.n_u), int(g.n_v), n_edges, *[ctypes.c_void_p(p) for p in ptrs], 1 if on_dev else 0)
+    return cg, keep
+
+
+def _marshal_opts(opt: Optional[Options], on_device: bool) -> _Options:
+    opt = opt or Options()
+    stream = opt.stream
+    if stream is None and on_device:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    return _Options(opt.side, opt.wg_waves, opt.grid, int(bool(opt.diagnostics)), int(bool(opt.no_validate)),
+                    0, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0))
+
+
+def _result_dict(r: _Result) -> Dict[str, Any]:
+    return {k: getattr(r, k) for k, _ in _Result._fields_}
+
+
+def mbe_count(g, opt: Optional[Options] = None) -> Dict[str, Any]:
+    """Count and hash the maximal bicliques of g; returns the fields of ``mbe_result``."""
+    lib = load()
+    cg, keep = _marshal_graph(g)
+    co = _marshal_opts(opt, bool(cg.on_device))
+    res = _Result()
+    rc = lib.mbe_count(ctypes.byref(cg), ctypes.byref(co), ctypes.byref(res))
+    if rc != MBE_OK:
+        raise MbeError(rc, _result_dict(res))
+    return _result_dict(res)
+
+
+def mbe_enumerate(g, opt: Optional[Options] = None, cap_ints: Optional[int] = None,
+                  out=None) -> Tuple[Dict[str, Any], Any]:
+    """Enumerate the maximal bicliques of g as canonical records.
+
+    out may be a torch int32 device tensor (records are written there) or None (a host numpy
+    buffer of cap_ints ints is used; when cap_ints is None the count is taken first to size
+    it exactly).  Returns (result dict, record array trimmed to out_ints)."""
+    lib = load()
+    cg, keep = _marshal_graph(g)
+    co = _marshal_opts(opt, bool(cg.on_device))
+    res = _Result()
+    if out is not None:
+        ptr, cap, on_dev = out.data_ptr(), int(out.numel()), 1
+        buf = out
+    else:
+        if cap_ints is None:
+            rc = lib.mbe_count(ctypes.byref(cg), ctypes.byref(co), ctypes.byref(res))
+            if rc != MBE_OK:
+                raise MbeError(rc, _result_dict(res))
+            cap_ints = int(res.out_ints)
+        buf = np.zeros(max(1, cap_ints), dtype=np.int32)
+        ptr, cap, on_dev = buf.ctypes.data, int(cap_ints), 0
+    rc = lib.mbe_enumerate(ctypes.byref(cg), ctypes.byref(co), ctypes.byref(res), ctypes.c_void_p(ptr),
+                           ctypes.c_uint64(cap), on_dev)
+    if rc != MBE_OK:
+        raise MbeError(rc, _result_dict(res))
+    return _result_dict(res), buf[:res.out_ints]
+
+
+def decode_records(flat) -> List[Tuple[Tuple[int, ...], Tuple[int, ...]]]:
+    """Split a flat record array into (A, B) tuples."""
+    flat = flat.tolist() if hasattr(flat, "tolist") else list(flat)
+    out = []
+    i = 0
+    while i < len(flat):
+        na, nb = flat[i], flat[i + 1]
+        out.append((tuple(flat[i + 2:i + 2 + na]), tuple(flat[i + 2 + na:i + 2 + na + nb])))
+        i += 2 + na + nb
+    return out

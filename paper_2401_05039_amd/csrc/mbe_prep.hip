@@ -1,0 +1,123 @@
+// Graph preparation on the device: CSR validation, candidate ranking.
+//
+// Ranking follows the candidate order of sections II-C / III-E at the top level of the
+// search: candidates of degree > 0 in ascending (degree, id).  Degree-0 vertices are left
+// out because they belong to no biclique with two non-empty sides.
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "mbe_internal.h"
+
+namespace mbe {
+
+namespace {
+
+// Offsets: off[0] = 0, non-decreasing, off[n] = n_edges.  Rows: ids in [0, n_cols), strictly
+// ascending.  Transpose: every (r, c) in this CSR appears as (c, r) in the other one (with
+// equal edge counts and duplicate-free rows on both sides this makes them transposes).
+__global__ void validate_kernel(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *off,
+                                const int32_t *adj, const int32_t *t_off, const int32_t *t_adj,
+                                unsigned int *flags) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += stride) {
+        const int32_t b = off[r], e = off[r + 1];
+        bool bad = (r == 0 && b != 0) || (r == n_rows - 1 && e != n_edges) || b > e || b < 0 || e > n_edges;
+        if (!bad) {
+            int32_t prev = -1;
+            for (int32_t p = b; p < e && !bad; ++p) {
+                const int32_t cidx = adj[p];
+                if (cidx <= prev || cidx >= n_cols) {
+                    bad = true;
+                    break;
+                }
+                prev = cidx;
+                // binary search r in the transposed row of cidx
+                int32_t lo = t_off[cidx], hi = t_off[cidx + 1];
+                if (lo < 0 || hi > n_edges || lo > hi) {
+                    bad = true;
+                    break;
+                }
+                while (lo < hi) {
+                    const int32_t mid = lo + (hi - lo) / 2;
+                    if (t_adj[mid] < r) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo >= t_off[cidx + 1] || t_adj[lo] != r) bad = true;
+            }
+        }
+        if (bad) atomicOr(flags, (unsigned int)FLAG_BAD_GRAPH);
+    }
+}
+
+// keys[v] = (deg << 32) | v; stats[0] = number of degree-0 vertices, stats[1 + c] = number of
+// candidates in mask class c (degree <= 64 << c), stats[8] = max degree.
+__global__ void rank_keys_kernel(int32_t nc, const int32_t *c_off, unsigned long long *keys,
+                                 unsigned long long *stats) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nc; v += stride) {
+        const uint32_t d = (uint32_t)(c_off[v + 1] - c_off[v]);
+        keys[v] = ((unsigned long long)d << 32) | (unsigned long long)(uint32_t)v;
+        if (d == 0) {
+            atomicAdd(&stats[0], 1ull);
+        } else {
+            int cls = 0;
+            while (cls < 6 && d > (64u << cls)) ++cls;
+            atomicAdd(&stats[1 + cls], 1ull);
+            atomicMax(&stats[8], (unsigned long long)d);
+        }
+    }
+}
+
+__global__ void rank_scatter_kernel(int32_t nc, int32_t nzero, const unsigned long long *sorted,
+                                    int32_t *order, int32_t *rank) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        const int32_t v = (int32_t)(sorted[i] & 0xFFFFFFFFull);
+        if (i < nzero) {
+            rank[v] = -1;
+        } else {
+            order[i - nzero] = v;
+            rank[v] = (int32_t)(i - nzero);
+        }
+    }
+}
+
+int grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_validate(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *off,
+                           const int32_t *adj, const int32_t *t_off, const int32_t *t_adj,
+                           unsigned int *flags, hipStream_t s) {
+    if (n_rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(validate_kernel, dim3(grid_for(n_rows, 256)), dim3(256), 0, s, n_rows, n_cols,
+                       n_edges, off, adj, t_off, t_adj, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_keys(int32_t nc, const int32_t *c_off, unsigned long long *keys,
+                            unsigned long long *stats, hipStream_t s) {
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(rank_keys_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, c_off, keys, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_scatter(int32_t nc, int32_t nzero, const unsigned long long *sorted,
+                               int32_t *order, int32_t *rank, hipStream_t s) {
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(rank_scatter_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, nzero, sorted,
+                       order, rank);
+    return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(void *temp, size_t *temp_bytes, const unsigned long long *in,
+                          unsigned long long *out, int32_t n, int end_bit, hipStream_t s) {
+    return rocprim::radix_sort_keys(temp, *temp_bytes, in, out, (unsigned int)n, 0, end_bit, s);
+}
+
+}  // namespace mbe

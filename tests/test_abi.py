@@ -1,0 +1,87 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point include/mbe.h declares,
+and rejects bad arguments and malformed host graphs before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mbe.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*\**\s*(mbe_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2401_05039_amd as m
+    return m, m.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    _, so = lib
+    names = _declared()
+    assert {"mbe_count", "mbe_enumerate", "mbe_strerror", "mbe_version"} <= set(names)
+    for n in names:
+        assert hasattr(so, n), n
+
+
+def test_strerror_and_version(lib):
+    m, _ = lib
+    assert m.mbe_strerror(0) == "ok"
+    for code in range(-6, 0):
+        assert m.mbe_strerror(code) and m.mbe_strerror(code) != "unknown error"
+    assert m.mbe_strerror(-99) == "unknown error"
+    assert re.match(r"^\d+\.\d+\.\d+$", m.mbe_version())
+
+
+def test_null_arguments(lib):
+    _, so = lib
+    res = ctypes.c_void_p(None)
+    assert so.mbe_count(None, None, None) == -1
+    g, keep = __import__("paper_2401_05039_amd")._marshal_graph(gg.complete(2, 2))
+    assert so.mbe_count(ctypes.byref(g), None, None) == -1
+
+
+def _bad(g, **kw):
+    import paper_2401_05039_amd as m
+    with pytest.raises(m.MbeError) as e:
+        m.mbe_count(g, m.Options(**kw))
+    return e.value.code
+
+
+def _mk(n_u, n_v, u_off, u_adj, v_off, v_adj):
+    return gg.BiGraph(n_u, n_v, np.array(u_off, np.int32), np.array(u_adj, np.int32),
+                      np.array(v_off, np.int32), np.array(v_adj, np.int32))
+
+
+def test_invalid_graphs_rejected_on_host():
+    good = gg.complete(2, 3)
+    # unsorted row
+    assert _bad(_mk(2, 3, [0, 3, 6], [0, 2, 1, 0, 1, 2], good.v_off, good.v_adj)) == -2
+    # duplicate in a row
+    assert _bad(_mk(2, 3, [0, 3, 6], [0, 1, 1, 0, 1, 2], good.v_off, good.v_adj)) == -2
+    # id out of range
+    assert _bad(_mk(2, 3, [0, 3, 6], [0, 1, 3, 0, 1, 2], good.v_off, good.v_adj)) == -2
+    # offsets not ending at n_edges
+    assert _bad(_mk(2, 3, [0, 3, 5], [0, 1, 2, 0, 1, 2], good.v_off, good.v_adj)) == -2
+    # not transposes: drop (1, 2) from the V side only
+    assert _bad(_mk(2, 3, good.u_off, good.u_adj, [0, 2, 4, 5], [0, 1, 0, 1, 0])) == -2
+
+
+def test_bad_options_rejected():
+    g = gg.complete(2, 2)
+    assert _bad(g, side=3) == -1
+    assert _bad(g, wg_waves=9) == -1
+
+
+def test_empty_graphs_need_no_device():
+    import paper_2401_05039_amd as m
+    for g in (gg.edgeless(4, 5), gg.edgeless(0, 3), gg.edgeless(3, 0)):
+        r = m.mbe_count(g)
+        assert r["count"] == 0 and r["hash"] == 0

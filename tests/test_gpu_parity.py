@@ -1,0 +1,195 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Integer work throughout, so the bar is bit-exact: count, 64-bit hash, record lists and the
+search-tree diagnostics (nodes, non-maximal nodes, depth, algorithmic bytes) must equal the
+oracle's.  Sizes grow from tiny to the full workloads; every case prints its name before the
+device work starts.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MASK = (1 << 64) - 1
+DIAG_KEYS = ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "max_depth", "side")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _check(mbe, orc, g, name, diag=True, side=0, **kw):
+    _say(name, g.n_u, g.n_v, g.n_edges)
+    want = orc.mbea(g, side=side)
+    got = mbe.mbe_count(g, mbe.Options(diagnostics=diag, side=side, **kw))
+    keys = DIAG_KEYS if diag else ("count", "hash", "out_ints", "side")
+    for k in keys:
+        assert got[k] == want[k], (name, k, got[k], want[k])
+    return got
+
+
+def test_tiny_closed_forms(mbe, orc):
+    for g in (gg.complete(1, 1), gg.complete(3, 4), gg.perfect_matching(5), gg.crown(4), gg.chain(6),
+              gg.complete_minus_edge(3, 3)):
+        _check(mbe, orc, g, g.name)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_small(mbe, orc, seed):
+    rng = np.random.default_rng(seed)
+    for k in range(25):
+        nu, nv = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+        g = gg.random_small(nu, nv, float(rng.uniform(0.05, 0.7)), seed * 100 + k)
+        _check(mbe, orc, g, g.name)
+
+
+def test_workload1_full_list(mbe, orc):
+    g = gg.config1()
+    _say("workload1 list")
+    want = orc.mbea(g, want_list=True)
+    res, flat = mbe.mbe_enumerate(g, mbe.Options(diagnostics=True))
+    for k in DIAG_KEYS:
+        assert res[k] == want[k], k
+    got = mbe.decode_records(flat)
+    assert got == want["list"]
+    assert len(flat) == want["out_ints"]
+
+
+def test_workload1_golden(mbe):
+    gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["config1"]
+    _say("workload1 golden")
+    r = mbe.mbe_count(gg.config1(), mbe.Options(diagnostics=True))
+    for k in ("count", "hash", "nodes", "nonmaximal", "bytes_alg", "max_depth"):
+        assert r[k] == gold[k], k
+
+
+@pytest.mark.parametrize("n", [10, 14, 16])
+def test_crown_closed_form(mbe, n):
+    _say("crown", n)
+    r = mbe.mbe_count(gg.crown(n))
+    assert r["count"] == 2 ** n - 2
+
+
+@pytest.mark.parametrize("m,n", [(5, 64), (7, 65), (40, 500), (200, 1024), (1, 1000)])
+def test_complete_closed_form(mbe, orc, m, n):
+    g = gg.complete(m, n)
+    _say("complete", m, n)
+    r = mbe.mbe_count(g, mbe.Options(diagnostics=True))
+    assert r["count"] == 1
+    assert r["hash"] == orc.hash_pair(list(range(m)), list(range(n)))
+
+
+def test_matching_and_chain_closed_forms(mbe, orc):
+    for g, cnt in ((gg.perfect_matching(3000), 3000), (gg.chain(300), 300)):
+        _check(mbe, orc, g, g.name)
+        assert mbe.mbe_count(g)["count"] == cnt
+
+
+@pytest.mark.parametrize("side", [1, 2])
+def test_side_choice(mbe, orc, side):
+    g = gg.random_small(60, 45, 0.2, 77)
+    r = _check(mbe, orc, g, f"side{side}", side=side)
+    assert r["side"] == side
+
+
+def test_transpose_gives_same_set(mbe, orc):
+    g = gg.random_small(50, 70, 0.15, 78)
+    a = mbe.mbe_enumerate(g)[1]
+    b = mbe.mbe_enumerate(gg.transpose(g))[1]
+    la = mbe.decode_records(a)
+    lb = mbe.decode_records(b)
+    assert sorted((y, x) for x, y in la) == lb
+
+
+@pytest.mark.parametrize("deg", [60, 130, 250, 500, 1000])
+def test_mask_width_classes(mbe, orc, deg):
+    # candidate degrees near deg put the top-level candidates in every mask-width class
+    nu, nv = 40, deg + 30
+    g = gg.random_small(nu, nv, deg / nv, 900 + deg)
+    _check(mbe, orc, g, f"width{deg}")
+
+
+@pytest.mark.parametrize("waves,grid", [(1, 1), (2, 3), (4, 17), (8, 0)])
+def test_launch_shapes_agree(mbe, orc, waves, grid):
+    g = gg.random_small(120, 150, 0.08, 31)
+    _check(mbe, orc, g, f"shape{waves}x{grid}", wg_waves=waves, grid=grid)
+
+
+def test_device_pointers(mbe, orc):
+    import torch
+    g = gg.random_small(80, 90, 0.1, 55)
+    _say("device pointers")
+    dg = gg.BiGraph(g.n_u, g.n_v, *[torch.from_numpy(np.asarray(a)).cuda() for a in
+                                    (g.u_off, g.u_adj, g.v_off, g.v_adj)])
+    r = mbe.mbe_count(dg, mbe.Options(diagnostics=True))
+    want = orc.mbea(g)
+    for k in DIAG_KEYS:
+        assert r[k] == want[k], k
+    out = torch.zeros(want["out_ints"], dtype=torch.int32, device="cuda")
+    res, flat = mbe.mbe_enumerate(dg, out=out)
+    assert mbe.decode_records(flat.cpu().numpy()) == orc.mbea(g, want_list=True)["list"]
+
+
+def test_top_level_ranges_add_up(mbe, orc):
+    g = gg.config1()
+    n = orc.num_roots(g)
+    _say("ranges")
+    whole = mbe.mbe_count(g, mbe.Options(diagnostics=True))
+    cuts = [0, 1, 77, n // 2, n - 1, n]
+    tot = {"count": 0, "hash": 0, "nodes": 0, "bytes_alg": 0}
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        r = mbe.mbe_count(g, mbe.Options(diagnostics=True, root_lo=lo, root_hi=hi))
+        o = orc.mbea(g, rank_lo=lo, rank_hi=hi)
+        assert (r["count"], r["hash"], r["nodes"], r["bytes_alg"]) == (o["count"], o["hash"], o["nodes"], o["bytes_alg"])
+        for k in tot:
+            tot[k] += r[k]
+    assert tot["count"] == whole["count"] and tot["hash"] & MASK == whole["hash"]
+
+
+def test_enumerate_small_buffer(mbe, orc):
+    g = gg.random_small(30, 30, 0.3, 5)
+    _say("small buffer")
+    want = orc.mbea(g)
+    with pytest.raises(mbe.MbeError) as e:
+        mbe.mbe_enumerate(g, cap_ints=want["out_ints"] - 1)
+    assert e.value.code == -3
+    assert e.value.result["count"] == want["count"] and e.value.result["out_ints"] == want["out_ints"]
+
+
+def test_invalid_device_graph(mbe):
+    import torch
+    _say("invalid device graph")
+    g = gg.complete(2, 3)
+    bad_u = torch.tensor([0, 2, 1, 0, 1, 2], dtype=torch.int32, device="cuda")
+    dg = gg.BiGraph(2, 3, torch.from_numpy(g.u_off).cuda(), bad_u, torch.from_numpy(g.v_off).cuda(),
+                    torch.from_numpy(g.v_adj).cuda())
+    with pytest.raises(mbe.MbeError) as e:
+        mbe.mbe_count(dg)
+    assert e.value.code == -2
+
+
+def test_workload2_full(mbe):
+    gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["config2"]
+    g = gg.config2()
+    _say("workload2 full", gold["count"])
+    r = mbe.mbe_count(g, mbe.Options(diagnostics=True))
+    for k in ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "max_depth"):
+        assert r[k] == gold[k], k
+    fast = mbe.mbe_count(g)
+    assert fast["count"] == gold["count"] and fast["hash"] == gold["hash"]
+
+
+def test_workload3_samples(mbe):
+    gold = json.load(open(os.path.join(GOLDEN, "workloads.json")))["config3_samples"]
+    g = gg.config3()
+    for s in gold["samples"]:
+        _say("workload3 rank", s["rank_lo"])
+        r = mbe.mbe_count(g, mbe.Options(diagnostics=True, root_lo=s["rank_lo"], root_hi=s["rank_hi"]))
+        for k in ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "max_depth"):
+            assert r[k] == s[k], (s["rank_lo"], k)
