@@ -81,6 +81,8 @@ template <int W>
 struct Frame {
     const uint32_t *S;  // candidate list: [0, nq) Q part, [nq, n) P part in processing order
     int32_t n, nq, pos, level;
+    int32_t end;        // candidates [pos, end) of the list are still to be taken here
+    int32_t top;        // first free stack entry above this frame's list
     int32_t nL;         // |L| of the nodes below this frame
     uint64_t sL;        // sum of the L-side hash terms of L
     uint64_t fw;        // sum over S of (2 + deg v), byte tally only
@@ -338,6 +340,7 @@ __device__ bool process_node(const Ctx<W> &c, const Frame<W> &F, int i, Frame<W>
     C.n = qn + pn;
     C.nq = qn;
     C.pos = qn;
+    C.end = qn + pn;
     C.level = F.level + 1;
     C.nL = nL;
     C.sL = sL;
@@ -645,36 +648,40 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             const int bits = d - 64 * w;
             F1.R[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : ((1ull << bits) - 1ull));
         }
+        F1.end = F1.n;
+        F1.top = 0;
         while (!aborted) {
             int i = 0;
             if (ln == 0) i = atomicAdd(&sh->claim, 1);
             i = __shfl(i, 0) + nq0;
             if (i >= F1.n) break;
-            Frame<W> cur;
-            cur.S = stk;
-            if (!process_node<W, DIAG, ENUM>(c, F1, i, cur, acc)) continue;
+            // the claimed child is a one-candidate range of the shared top-level list
+            Frame<W> cur = F1;
+            cur.pos = i;
+            cur.end = i + 1;
             int depth = 0;
             for (;;) {
-                if (cur.pos >= cur.n) {
+                if (cur.pos >= cur.end) {
                     if (depth == 0) break;
                     --depth;
                     cur = hdr[depth];
                     continue;
                 }
                 const int ii = cur.pos++;
-                Frame<W> ch;
-                ch.S = cur.S + cur.n;
-                if ((size_t)(ch.S - stk) + (size_t)cur.n > (size_t)a.scap) {
+                if ((size_t)cur.top + (size_t)cur.n > (size_t)a.scap) {
                     if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_STACK_OVERFLOW);
                     aborted = true;
                     break;
                 }
+                Frame<W> ch;
+                ch.S = stk + cur.top;
                 if (process_node<W, DIAG, ENUM>(c, cur, ii, ch, acc)) {
                     if (depth >= a.maxdepth) {
                         if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
                         aborted = true;
                         break;
                     }
+                    ch.top = cur.top + ch.n;
                     hdr[depth] = cur;  // every lane stores the same header
                     __threadfence_block();
                     ++depth;

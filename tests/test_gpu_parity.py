@@ -109,10 +109,17 @@ def test_transpose_gives_same_set(mbe, orc):
 
 @pytest.mark.parametrize("deg", [60, 130, 250, 500, 1000])
 def test_mask_width_classes(mbe, orc, deg):
-    # candidate degrees near deg put the top-level candidates in every mask-width class
-    nu, nv = 40, deg + 30
+    # 40 candidates of degree about deg put the top-level candidates in every mask-width
+    # class; the other side is 20x larger so that common neighbourhoods stay small
+    nu, nv = 40, 20 * deg
     g = gg.random_small(nu, nv, deg / nv, 900 + deg)
     _check(mbe, orc, g, f"width{deg}")
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_dense_small_deep_trees(mbe, orc, seed):
+    g = gg.random_small(14, 60, 0.6, 300 + seed)
+    _check(mbe, orc, g, f"dense{seed}")
 
 
 @pytest.mark.parametrize("waves,grid", [(1, 1), (2, 3), (4, 17), (8, 0)])
