@@ -6,7 +6,8 @@ CSR validation, candidate ranking and the persistent depth-first search, through
 call mbe_count.  The graph is the Chung-Lu power-law bipartite workload (|U| = 100k,
 |V| = 50k, 1M edges, exponent 2.1 on both sides, seeded).  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload power-law|er-small|skewed-sample]
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+                  [--workload power-law|er-small|skewed-sample|batch] [--batch-n N]
 """
 import argparse
 import json
@@ -66,6 +67,54 @@ def cpu_baseline(g, rng_range, threads, budget_s=25.0):
                       f"{cnt} bicliques in {dt:.2f} s wall on {threads} threads"}
 
 
+def bench_batch(args, mbe):
+    """Batched form: n independent graphs (|U|, |V| log-uniform in [50, 2000], density uniform
+    in [0.01, 0.1], ER or Chung-Lu) in one mbe_count_batch call, against one mbe_count call
+    per graph.  Both take host graphs, so both include the upload and the preparation."""
+    import graphgen as gg
+    t0 = time.time()
+    gs = [gg.config4_graph(i) for i in range(args.batch_n)]
+    log(f"generated {len(gs)} graphs, {sum(g.n_edges for g in gs)} edges, in {time.time() - t0:.1f} s")
+    opt = mbe.Options(wg_waves=args.waves, grid=args.grid)
+    mbe.mbe_count_batch(gs[:64], opt)
+    for g in gs[:8]:
+        mbe.mbe_count(g, opt)
+    t0 = time.perf_counter()
+    plain = [mbe.mbe_count(g, opt) for g in gs]
+    t_plain = time.perf_counter() - t0
+    log(f"plain: {t_plain:.3f} s")
+    times = []
+    for _ in range(max(1, args.steps)):
+        t0 = time.perf_counter()
+        res = mbe.mbe_count_batch(gs, opt)
+        times.append(time.perf_counter() - t0)
+    t_batch = min(times)
+    for i, (a, b) in enumerate(zip(plain, res)):
+        assert (a["count"], a["hash"]) == (b["count"], b["hash"]), i
+    total = sum(r["count"] for r in res)
+    out = {
+        "metric": "graphs/s batched vs plain",
+        "value": len(gs) / t_batch,
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": len(times),
+        "warmup": 1,
+        "ms_per_step": t_batch * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(gs)} ER / Chung-Lu bipartite graphs, sides log-uniform [50, 2000], "
+                               f"density U[0.01, 0.1]", "graphs": len(gs), "edges": sum(g.n_edges for g in gs),
+                   "bicliques": total},
+        "plain_graphs_per_s": len(gs) / t_plain,
+        "batched_over_plain": t_plain / t_batch,
+        "batch_kernel_ms": res[0]["kernel_ms"] if res else 0.0,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +124,7 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-n", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -88,6 +138,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("no HIP device")
     mbe.load()
+    if args.workload == "batch":
+        return bench_batch(args, mbe)
     g, desc, rng_range = make_workload(args.workload)
     log("graph", desc)
     dev = torch.device("cuda:0")

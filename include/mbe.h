@@ -138,6 +138,54 @@ int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out);
 int mbe_enumerate(const mbe_graph *g, const mbe_options *opt, mbe_result *out,
                   int32_t *buf, uint64_t buf_cap_ints, int32_t buf_on_device);
 
+/*
+ * Count and hash the maximal bicliques of each of n independent graphs in one pass (the
+ * batched form of mbe_count).  The graphs are packed as a disjoint union, each keeping its
+ * own candidate side (mbe_options.side applies to all of them), ranked per graph on the
+ * device, and searched by one persistent kernel per mask-width class over a shared work
+ * list ordered by mask class and then by decreasing candidate degree.  outs[i] receives
+ * graph i's mbe_result, equal to what mbe_count would return for it; kernel_ms is the device
+ * time of the whole batch.  Host graphs only (on_device = 0); root_lo / root_hi are ignored.
+ * Errors as mbe_count; on MBE_ERR_INVALID_GRAPH no graph is searched.
+ */
+int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_result *outs);
+
+/* ------------------------------------------------------------------------- serving */
+/*
+ * A server runs enumeration requests with continuous batching.  Each of its slots (a host
+ * thread with its own HIP stream and a device workspace that stays allocated between
+ * batches) takes the queued requests in arrival order while their estimated device
+ * footprint (CSR, preparation arrays, and the search arena of the largest local universe)
+ * fits the slot's share of hbm_budget_bytes, and runs them as one mbe_count_batch pass.
+ * With slots >= 2 a new batch starts while another is still on the device.  A request's
+ * result is the one mbe_count returns for its graph alone.
+ *   hbm_budget_bytes  device memory the slots may plan for (0: half of the free memory)
+ *   slots             concurrent batches (1..8; default 2)
+ *   max_batch         most requests per batch (default 4096)
+ *   search            per-search options (side, wg_waves, grid, diagnostics, no_validate)
+ */
+typedef struct mbe_server mbe_server;
+typedef struct mbe_server_options {
+    size_t hbm_budget_bytes;
+    int32_t slots;
+    int32_t max_batch;
+    mbe_options search;
+} mbe_server_options;
+
+/* Start a server on the current device (opt may be NULL).  *out receives the handle. */
+int mbe_server_create(const mbe_server_options *opt, mbe_server **out);
+
+/* Queue a host graph (copied before the call returns); *ticket identifies the request. */
+int mbe_server_submit(mbe_server *s, const mbe_graph *g, uint64_t *ticket);
+
+/* Block until the request is done; out receives its result and latency_ms (may be NULL)
+ * the time from submission to completion.  Returns the request's status.  A ticket can be
+ * waited for once. */
+int mbe_server_wait(mbe_server *s, uint64_t ticket, mbe_result *out, double *latency_ms);
+
+/* Finish the queued requests, stop the slots and free their device memory. */
+int mbe_server_destroy(mbe_server *s);
+
 /* Human-readable name of a return code (static storage; never NULL). */
 const char *mbe_strerror(int code);
 

@@ -17,8 +17,8 @@ from typing import Any, Dict, List, Optional, Tuple
 
 import numpy as np
 
-__all__ = ["mbe_count", "mbe_enumerate", "mbe_strerror", "mbe_version", "MbeError", "Options",
-           "lib_path", "load"]
+__all__ = ["mbe_count", "mbe_count_batch", "mbe_enumerate", "mbe_strerror", "mbe_version", "MbeError",
+           "Options", "Server", "lib_path", "load"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmbe.so")
@@ -68,6 +68,11 @@ class Options:
     stream: Optional[int] = None  # hipStream_t as an integer; None = torch's current stream
 
 
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("search", _Options)]
+
+
 class MbeError(RuntimeError):
     def __init__(self, code: int, result: Optional[Dict[str, Any]] = None):
         super().__init__(f"mbe error {code}: {mbe_strerror(code)}")
@@ -92,6 +97,18 @@ def load():
     lib.mbe_enumerate.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result),
                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32]
     lib.mbe_enumerate.restype = ctypes.c_int
+    lib.mbe_count_batch.argtypes = [ctypes.POINTER(_Graph), ctypes.c_int32, ctypes.POINTER(_Options),
+                                     ctypes.POINTER(_Result)]
+    lib.mbe_count_batch.restype = ctypes.c_int
+    lib.mbe_server_create.argtypes = [ctypes.POINTER(_ServerOptions), ctypes.POINTER(ctypes.c_void_p)]
+    lib.mbe_server_create.restype = ctypes.c_int
+    lib.mbe_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Graph), ctypes.POINTER(ctypes.c_uint64)]
+    lib.mbe_server_submit.restype = ctypes.c_int
+    lib.mbe_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(_Result),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.mbe_server_wait.restype = ctypes.c_int
+    lib.mbe_server_destroy.argtypes = [ctypes.c_void_p]
+    lib.mbe_server_destroy.restype = ctypes.c_int
     lib.mbe_strerror.argtypes = [ctypes.c_int]
     lib.mbe_strerror.restype = ctypes.c_char_p
     lib.mbe_version.argtypes = []
@@ -161,6 +178,70 @@ def mbe_count(g, opt: Optional[Options] = None) -> Dict[str, Any]:
     if rc != MBE_OK:
         raise MbeError(rc, _result_dict(res))
     return _result_dict(res)
+
+
+def mbe_count_batch(graphs, opt: Optional[Options] = None) -> List[Dict[str, Any]]:
+    """Count and hash the maximal bicliques of many host graphs in one batched pass; returns
+    one result dict per graph (kernel_ms is the time of the whole batch)."""
+    lib = load()
+    n = len(graphs)
+    arr = (_Graph * max(1, n))()
+    keep: List[Any] = []
+    for i, g in enumerate(graphs):
+        cg, k = _marshal_graph(g)
+        if cg.on_device:
+            raise ValueError("mbe_count_batch takes host graphs")
+        arr[i] = cg
+        keep.append(k)
+    co = _marshal_opts(opt, False)
+    res = (_Result * max(1, n))()
+    rc = lib.mbe_count_batch(arr, n, ctypes.byref(co), res)
+    if rc != MBE_OK:
+        raise MbeError(rc)
+    return [_result_dict(res[i]) for i in range(n)]
+
+
+class Server:
+    """Continuous-batching request server (``mbe_server_*``): submit host graphs from any
+    thread, wait for each result; results equal those of ``mbe_count`` on the graph alone."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, slots: int = 2, max_batch: int = 0,
+                 opt: Optional[Options] = None):
+        lib = load()
+        so = _ServerOptions(hbm_budget_bytes, slots, max_batch, _marshal_opts(opt, False))
+        h = ctypes.c_void_p()
+        rc = lib.mbe_server_create(ctypes.byref(so), ctypes.byref(h))
+        if rc != MBE_OK:
+            raise MbeError(rc)
+        self._h = h
+
+    def submit(self, g) -> int:
+        cg, keep = _marshal_graph(g)
+        t = ctypes.c_uint64()
+        rc = load().mbe_server_submit(self._h, ctypes.byref(cg), ctypes.byref(t))
+        if rc != MBE_OK:
+            raise MbeError(rc)
+        return int(t.value)
+
+    def wait(self, ticket: int) -> Tuple[Dict[str, Any], float]:
+        """(result dict, latency in ms from submission to completion)."""
+        res = _Result()
+        lat = ctypes.c_double()
+        rc = load().mbe_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(res), ctypes.byref(lat))
+        if rc != MBE_OK:
+            raise MbeError(rc, _result_dict(res))
+        return _result_dict(res), float(lat.value)
+
+    def close(self) -> None:
+        if self._h:
+            load().mbe_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def mbe_enumerate(g, opt: Optional[Options] = None, cap_ints: Optional[int] = None,

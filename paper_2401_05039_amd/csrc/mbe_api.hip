@@ -8,8 +8,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <memory>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mbe.h"
@@ -86,40 +92,6 @@ int map_err(hipError_t e) {
         if (_e != hipSuccess) return map_err(_e);      \
     } while (0)
 
-ArenaLayout make_layout(int32_t ucap, int32_t nwords, int Wmax, int waves, int32_t scap, int32_t maxdepth) {
-    ArenaLayout L{};
-    size_t o = 0;
-    auto take = [&](size_t bytes) {
-        size_t at = o;
-        o = align_up(o + bytes, 256);
-        return at;
-    };
-    L.off_bitmap = take((size_t)nwords * 8);
-    L.off_bpre = take(((size_t)nwords + 1) * 4);
-    L.off_M = take((size_t)ucap * Wmax * 8);
-    L.off_gid = take((size_t)ucap * 4);
-    L.off_cnt = take((size_t)ucap * 4);
-    L.off_hv = take((size_t)64 * Wmax * 8);
-    L.off_deg = take((size_t)64 * Wmax * 4);
-    L.off_S1 = take((size_t)ucap * 4);
-    L.off_t1v = take((size_t)ucap * 4);
-    L.off_t1c = take((size_t)ucap * 4);
-    L.off_waves = o;
-    size_t w = 0;
-    auto wtake = [&](size_t bytes) {
-        size_t at = w;
-        w = align_up(w + bytes, 256);
-        return at;
-    };
-    L.off_w_stack = wtake((size_t)scap * 4);
-    L.off_w_tv = wtake((size_t)ucap * 4);
-    L.off_w_tc = wtake((size_t)ucap * 4);
-    L.off_w_hdr = wtake((size_t)maxdepth * frame_header_bytes(Wmax));
-    L.wave_bytes = w;
-    L.wg_bytes = align_up(o + (size_t)waves * w, 4096);
-    return L;
-}
-
 // Host-side check of one CSR direction against its transpose (same rules as the device
 // validator): offsets start at 0, never decrease and end at n_edges; rows strictly ascend
 // with ids in range; every (r, c) appears as (c, r) in the other direction.
@@ -162,6 +134,11 @@ Opts read_opts(const mbe_options *o) {
     r.stream = static_cast<hipStream_t>(o->stream);
     return r;
 }
+
+int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
+               bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
+               unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
+               unsigned long long *graph_acc, size_t graph_acc_bytes);
 
 int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t *ubuf, uint64_t ucap_ints,
         int ubuf_on_device, bool enumerate) {
@@ -215,7 +192,6 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     MBE_TRY(st->small.ensure(4096));
     unsigned long long *acc = st->small.as<unsigned long long>(0);
     unsigned int *flags = st->small.as<unsigned int>(256);
-    unsigned int *counters = st->small.as<unsigned int>(512);
     unsigned long long *stats = st->small.as<unsigned long long>(1024);
 
     if (!opt.no_validate && g->on_device) {
@@ -241,7 +217,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     int32_t *order = st->prep.as<int32_t>(2 * b_keys);
     int32_t *rank = st->prep.as<int32_t>(2 * b_keys + b_i32);
     MBE_TRY(hipMemsetAsync(stats, 0, 16 * 8, s));
-    MBE_TRY(launch_rank_keys(nc, c_off, keys, stats, s));
+    MBE_TRY(launch_rank_keys(nc, c_off, c_adj, o_off, keys, stats, s));
     int end_bit = 32;
     while (end_bit < 64 && ((unsigned long long)no >> (end_bit - 32)) != 0ull) ++end_bit;
     size_t tmp_bytes = 0;
@@ -273,9 +249,14 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
 
     const int waves = opt.waves;
     const int grid = opt.grid > 0 ? opt.grid : 2 * st->cus;
-    const int32_t nwords = (ncand + 63) / 64;
-    int32_t scap = 2 * ncand + 1024;
-    int32_t maxdepth = 64 * Wmax + 2;
+    SearchDims dims{};
+    dims.nwords = (ncand + 63) / 64;
+    dims.Wmax = Wmax;
+    dims.waves = waves;
+    dims.ucap = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ncand, (int64_t)hstats[9]));
+    dims.post_cap = std::max<int64_t>(64, (int64_t)hstats[9]);
+    dims.scap = 2 * (int64_t)dims.ucap + 16384;
+    dims.maxdepth = 64 * Wmax + 2;
 
     // record arena for mbe_enumerate
     unsigned long long rec_cap = 0, offs_cap = 0;
@@ -286,20 +267,27 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         MBE_TRY(st->rec_offs.ensure((size_t)offs_cap * 8));
     }
 
+    // one graph descriptor, in the small device block
+    GraphDesc gd{};
+    gd.order = order;
+    gd.acc = acc;
+    gd.total_fw = 2ull * (unsigned long long)ncand + (unsigned long long)ne;
+    gd.ncand = ncand;
+    gd.nwords = dims.nwords;
+    gd.c_is_v = c_is_v ? 1 : 0;
+    gd.cbase = 0;
+    gd.obase = 0;
+    GraphDesc *d_gd = st->small.as<GraphDesc>(2048);
+    MBE_TRY(hipMemcpyAsync(d_gd, &gd, sizeof(gd), hipMemcpyHostToDevice, s));
+
     SearchArgs a{};
-    a.nc = nc;
-    a.no = no;
-    a.ncand = ncand;
-    a.c_is_v = c_is_v ? 1 : 0;
     a.c_off = c_off;
     a.c_adj = c_adj;
     a.o_off = o_off;
     a.o_adj = o_adj;
-    a.order = order;
     a.rank = rank;
-    a.total_fw = 2ull * (unsigned long long)ncand + (unsigned long long)ne;
-    a.ucap = ncand;
-    a.nwords = nwords;
+    a.graphs = d_gd;
+    a.tasks = nullptr;
     a.acc = acc;
     a.flags = flags;
     a.rec = enumerate ? st->rec.as<int32_t>() : nullptr;
@@ -310,33 +298,15 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     unsigned long long hacc[ACC_SLOTS];
     unsigned int hflags = 0;
     float ms = 0.f;
-    for (int attempt = 0; attempt < 8; ++attempt) {
-        a.scap = scap;
-        a.maxdepth = maxdepth;
-        a.lay = make_layout(ncand, nwords, Wmax, waves, scap, maxdepth);
-        MBE_TRY(st->arena.ensure(a.lay.wg_bytes * (size_t)grid));
-        a.arena = st->arena.as<char>();
-        MBE_TRY(hipMemset2DAsync(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, 0, (size_t)nwords * 8, (size_t)grid, s));
-        MBE_TRY(hipMemsetAsync(acc, 0, ACC_SLOTS * 8, s));
-        MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
-        MBE_TRY(hipMemsetAsync(counters, 0, 8 * 4, s));
-        MBE_TRY(hipEventRecord(st->ev0, s));
-        for (int c = 4; c >= 0; --c) {
-            const int64_t clo = std::max(cls_lo[c], lo), chi = std::min(cls_hi[c], hi);
-            if (clo >= chi) continue;
-            const int W = 1 << c;
-            MBE_TRY(launch_search(a, W, opt.diag, enumerate, clo, chi, counters + c, grid, waves,
-                                  search_lds_bytes(W, waves), s));
-        }
-        MBE_TRY(hipEventRecord(st->ev1, s));
-        MBE_TRY(hipMemcpyAsync(hacc, acc, sizeof(hacc), hipMemcpyDeviceToHost, s));
-        MBE_TRY(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, s));
-        MBE_TRY(hipStreamSynchronize(s));
-        MBE_TRY(hipEventElapsedTime(&ms, st->ev0, st->ev1));
-        if (!(hflags & (FLAG_STACK_OVERFLOW | FLAG_DEPTH_OVERFLOW))) break;
-        if (hflags & FLAG_STACK_OVERFLOW) scap = (int32_t)std::min<int64_t>((int64_t)scap * 2, (int64_t)1 << 30);
-        if (hflags & FLAG_DEPTH_OVERFLOW) maxdepth *= 2;
-        if (attempt == 7) return MBE_ERR_OUT_OF_MEMORY;
+    int64_t cls_a[5], cls_b[5];
+    for (int c = 0; c < 5; ++c) {
+        cls_a[c] = std::max(cls_lo[c], lo);
+        cls_b[c] = std::min(cls_hi[c], hi);
+    }
+    {
+        const int rc = run_search(st, a, dims, cls_a, cls_b, opt.diag, enumerate, grid, waves, acc, ACC_SLOTS * 8, hacc,
+                                  &hflags, &ms, s, nullptr, 0);
+        if (rc != MBE_OK) return rc;
     }
 
     out->count = hacc[ACC_COUNT];
@@ -373,9 +343,531 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     return MBE_OK;
 }
 
+// Search run shared by the single-graph and batched calls: sizes the arena, launches one
+// persistent kernel per mask-width class (widest first) and reruns with larger capacities
+// when a kernel reports an overflow.  hacc / hflags receive the run-wide slots and flags.
+int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
+               bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
+               unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
+               unsigned long long *graph_acc, size_t graph_acc_bytes) {
+    unsigned int *flags = a.flags;
+    unsigned int *counters = st->small.as<unsigned int>(512);
+    unsigned int hflags = 0;
+    for (int attempt = 0;; ++attempt) {
+        a.dims = dims;
+        a.lay = search_layout(dims);
+        MBE_TRY(st->arena.ensure(a.lay.wg_bytes * (size_t)grid));
+        a.arena = st->arena.as<char>();
+        MBE_TRY(hipMemset2DAsync(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, 0, (size_t)dims.nwords * 8, (size_t)grid, s));
+        MBE_TRY(hipMemsetAsync(run_acc, 0, run_acc_bytes, s));
+        if (graph_acc && graph_acc != run_acc) MBE_TRY(hipMemsetAsync(graph_acc, 0, graph_acc_bytes, s));
+        MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
+        MBE_TRY(hipMemsetAsync(counters, 0, 8 * 4, s));
+        MBE_TRY(hipEventRecord(st->ev0, s));
+        for (int c = 4; c >= 0; --c) {
+            if (cls_lo[c] >= cls_hi[c]) continue;
+            MBE_TRY(launch_search(a, 1 << c, diag, enumerate, cls_lo[c], cls_hi[c], counters + c, grid, waves, s));
+        }
+        MBE_TRY(hipEventRecord(st->ev1, s));
+        MBE_TRY(hipMemcpyAsync(hacc, run_acc, ACC_SLOTS * 8, hipMemcpyDeviceToHost, s));
+        MBE_TRY(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, s));
+        MBE_TRY(hipStreamSynchronize(s));
+        MBE_TRY(hipEventElapsedTime(ms, st->ev0, st->ev1));
+        if (!(hflags & FLAG_RERUN)) break;
+        if (attempt >= 8) return MBE_ERR_OUT_OF_MEMORY;
+        if (hflags & FLAG_STACK_OVERFLOW) dims.scap = std::min<int64_t>(dims.scap * 2, (int64_t)1 << 31);
+        if (hflags & FLAG_DEPTH_OVERFLOW) dims.maxdepth *= 2;
+        if (hflags & FLAG_UNIVERSE_OVERFLOW) {
+            dims.ucap = (int32_t)std::max<int64_t>(dims.ucap, (int64_t)hacc[ACC_NEED_UCAP]);
+            dims.post_cap = std::max<int64_t>(dims.post_cap, (int64_t)hacc[ACC_NEED_POST]);
+            dims.scap = std::max<int64_t>(dims.scap, 2 * (int64_t)dims.ucap + 16384);
+        }
+    }
+    *hflags_out = hflags;
+    return MBE_OK;
+}
+
+int degree_class(int64_t d) {
+    int c = 0;
+    while (c < 6 && d > (64ll << c)) ++c;
+    return c;
+}
+
+// Host checks of batch input (before any device work): sizes, pointers and, unless the
+// caller vouches for them, the CSR pairs.
+int check_graphs(const mbe_graph *gs, int32_t n, bool validate) {
+    for (int32_t i = 0; i < n; ++i) {
+        const mbe_graph &g = gs[i];
+        if (g.n_u < 0 || g.n_v < 0 || g.n_edges < 0 || g.on_device) return MBE_ERR_INVALID_ARG;
+        if (g.n_edges > 0 && (g.n_u == 0 || g.n_v == 0)) return MBE_ERR_INVALID_GRAPH;
+        if ((g.n_u > 0 && !g.u_off) || (g.n_v > 0 && !g.v_off) || (g.n_edges > 0 && (!g.u_adj || !g.v_adj)))
+            return MBE_ERR_INVALID_ARG;
+        if (validate && g.u_off && g.v_off &&
+            (!host_valid(g.n_u, g.n_v, g.n_edges, g.u_off, g.u_adj, g.v_off, g.v_adj) ||
+             !host_valid(g.n_v, g.n_u, g.n_edges, g.v_off, g.v_adj, g.u_off, g.u_adj)))
+            return MBE_ERR_INVALID_GRAPH;
+    }
+    return MBE_OK;
+}
+
+// The batched pass on a given workspace and stream (the caller holds the workspace and has
+// run check_graphs).
+int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n, const mbe_options *opt_in,
+                 mbe_result *outs);
+
+int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_result *outs) {
+    if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
+    const Opts opt = read_opts(opt_in);
+    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8) return MBE_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
+    const int rc = check_graphs(gs, n, !opt.no_validate);
+    if (rc != MBE_OK) return rc;
+    bool any = false;
+    for (int32_t i = 0; i < n; ++i) any = any || (gs[i].n_edges > 0);
+    if (!any) {
+        for (int32_t i = 0; i < n; ++i) outs[i].side = (uint32_t)(opt.side ? opt.side : (gs[i].n_v < gs[i].n_u ? 2 : 1));
+        return MBE_OK;
+    }
+    int dev = 0;
+    MBE_TRY(hipGetDevice(&dev));
+    DeviceState *st = state_for(dev);
+    if (!st) return MBE_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(st->mu);
+    return run_batch_on(st, opt.stream, gs, n, opt_in, outs);
+}
+
+int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n, const mbe_options *opt_in,
+                 mbe_result *outs) {
+    if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
+    Opts opt = read_opts(opt_in);
+    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8) return MBE_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
+    // host checks and packing (each graph keeps its own candidate side)
+    std::vector<int32_t> side(n), nc(n), no(n), cb(n + 1, 0), ob(n + 1, 0), eb(n + 1, 0);
+    int64_t NC = 0, NO = 0, E = 0;
+    int max_no = 1;
+    for (int32_t i = 0; i < n; ++i) {
+        const mbe_graph &g = gs[i];
+        side[i] = opt.side ? opt.side : (g.n_v < g.n_u ? 2 : 1);
+        outs[i].side = (uint32_t)side[i];
+        nc[i] = side[i] == 2 ? g.n_v : g.n_u;
+        no[i] = side[i] == 2 ? g.n_u : g.n_v;
+        if (g.n_edges == 0) nc[i] = no[i] = 0;  // nothing to search: keep it out of the pack
+        cb[i + 1] = cb[i] + nc[i];
+        ob[i + 1] = ob[i] + no[i];
+        eb[i + 1] = eb[i] + (nc[i] ? g.n_edges : 0);
+        max_no = std::max(max_no, no[i]);
+        if ((int64_t)cb[i + 1] > INT32_MAX / 2 || (int64_t)ob[i + 1] > INT32_MAX / 2) return MBE_ERR_INVALID_ARG;
+    }
+    NC = cb[n];
+    NO = ob[n];
+    E = eb[n];
+    if (E > INT32_MAX) return MBE_ERR_INVALID_ARG;
+    if (NC == 0) return MBE_OK;
+    std::vector<int32_t> c_off(NC + 1), o_off(NO + 1), c_adj(E), o_adj(E), graph_of(NC);
+    int64_t cls_cnt[7] = {0, 0, 0, 0, 0, 0, 0};
+    std::vector<int64_t> ncand_h(n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        if (!nc[i]) continue;
+        const mbe_graph &g = gs[i];
+        const bool cv = side[i] == 2;
+        const int32_t *go = cv ? g.v_off : g.u_off, *ga = cv ? g.v_adj : g.u_adj;
+        const int32_t *ho = cv ? g.u_off : g.v_off, *ha = cv ? g.u_adj : g.v_adj;
+        for (int32_t v = 0; v < nc[i]; ++v) {
+            c_off[cb[i] + v] = eb[i] + go[v];
+            graph_of[cb[i] + v] = i;
+            const int64_t d = go[v + 1] - go[v];
+            if (d > 0) {
+                ++ncand_h[i];
+                ++cls_cnt[degree_class(d)];
+            }
+        }
+        for (int32_t w = 0; w < no[i]; ++w) o_off[ob[i] + w] = eb[i] + ho[w];
+        for (int32_t e = 0; e < g.n_edges; ++e) {
+            c_adj[eb[i] + e] = ga[e] + ob[i];
+            o_adj[eb[i] + e] = ha[e] + cb[i];
+        }
+    }
+    c_off[NC] = (int32_t)E;
+    o_off[NO] = (int32_t)E;
+    if (cls_cnt[5] || cls_cnt[6]) return MBE_ERR_UNSUPPORTED;
+
+    // device copies: graph | prep | per-graph accumulators
+    auto al = [](size_t b) { return align_up(b, 256); };
+    const size_t b_coff = al((NC + 1) * 4), b_ooff = al((NO + 1) * 4), b_adj = al(E * 4), b_nc = al(NC * 4);
+    const size_t b_cb = al((n + 1) * 4);
+    MBE_TRY(st->graph.ensure(b_coff + b_ooff + 2 * b_adj + b_nc + b_cb));
+    int32_t *d_coff = st->graph.as<int32_t>(0);
+    int32_t *d_ooff = st->graph.as<int32_t>(b_coff);
+    int32_t *d_cadj = st->graph.as<int32_t>(b_coff + b_ooff);
+    int32_t *d_oadj = st->graph.as<int32_t>(b_coff + b_ooff + b_adj);
+    int32_t *d_gof = st->graph.as<int32_t>(b_coff + b_ooff + 2 * b_adj);
+    int32_t *d_cb = st->graph.as<int32_t>(b_coff + b_ooff + 2 * b_adj + b_nc);
+    MBE_TRY(hipMemcpyAsync(d_coff, c_off.data(), (NC + 1) * 4, hipMemcpyHostToDevice, s));
+    MBE_TRY(hipMemcpyAsync(d_ooff, o_off.data(), (NO + 1) * 4, hipMemcpyHostToDevice, s));
+    if (E) MBE_TRY(hipMemcpyAsync(d_cadj, c_adj.data(), E * 4, hipMemcpyHostToDevice, s));
+    if (E) MBE_TRY(hipMemcpyAsync(d_oadj, o_adj.data(), E * 4, hipMemcpyHostToDevice, s));
+    MBE_TRY(hipMemcpyAsync(d_gof, graph_of.data(), NC * 4, hipMemcpyHostToDevice, s));
+    MBE_TRY(hipMemcpyAsync(d_cb, cb.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
+
+    int64_t NT = 0;
+    std::vector<int32_t> tb(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) tb[i + 1] = tb[i] + (int32_t)ncand_h[i];
+    NT = tb[n];
+    const size_t b_keys = al(NC * 8), b_i32 = al(NC * 4), b_t = al(std::max<int64_t>(NT, 1) * 8),
+                 b_tk = al(std::max<int64_t>(NT, 1) * 4), b_gs = al((size_t)n * 16), b_gd = al((size_t)n * sizeof(GraphDesc)),
+                 b_ga = al((size_t)n * ACC_SLOTS * 8), b_tb = al((n + 1) * 4);
+    MBE_TRY(st->prep.ensure(2 * b_keys + 2 * b_i32 + 2 * b_t + 2 * b_tk + b_gs + b_gd + b_ga + b_tb));
+    size_t po = 0;
+    auto take = [&](size_t b) { const size_t at = po; po += b; return at; };
+    unsigned long long *keys = st->prep.as<unsigned long long>(take(b_keys));
+    unsigned long long *sorted = st->prep.as<unsigned long long>(take(b_keys));
+    int32_t *order = st->prep.as<int32_t>(take(b_i32));
+    int32_t *rank = st->prep.as<int32_t>(take(b_i32));
+    unsigned long long *task = st->prep.as<unsigned long long>(take(b_t));
+    unsigned long long *task_sorted = st->prep.as<unsigned long long>(take(b_t));
+    unsigned int *tkey = st->prep.as<unsigned int>(take(b_tk));
+    unsigned int *tkey_sorted = st->prep.as<unsigned int>(take(b_tk));
+    unsigned long long *gstats = st->prep.as<unsigned long long>(take(b_gs));
+    GraphDesc *d_gd = st->prep.as<GraphDesc>(take(b_gd));
+    unsigned long long *gacc = st->prep.as<unsigned long long>(take(b_ga));
+    int32_t *d_tb = st->prep.as<int32_t>(take(b_tb));
+    MBE_TRY(st->small.ensure(4096));
+    unsigned long long *acc = st->small.as<unsigned long long>(0);
+    unsigned int *flags = st->small.as<unsigned int>(256);
+    unsigned long long *stats = st->small.as<unsigned long long>(1024);
+    MBE_TRY(hipMemcpyAsync(d_tb, tb.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
+    MBE_TRY(hipMemsetAsync(gstats, 0, (size_t)n * 16, s));
+    MBE_TRY(hipMemsetAsync(stats, 0, 16 * 8, s));
+    MBE_TRY(launch_batch_keys((int32_t)NC, d_coff, d_cadj, d_ooff, d_gof, d_cb, keys, gstats, stats, s));
+    int end_bit = 32;
+    while (end_bit < 64 && ((unsigned long long)max_no >> (end_bit - 32)) != 0ull) ++end_bit;
+    size_t tmp = 0;
+    MBE_TRY(segmented_sort_u64(nullptr, &tmp, keys, sorted, (int32_t)NC, n, d_cb, d_cb + 1, end_bit, s));
+    size_t tmp2 = 0;
+    MBE_TRY(sort_pairs_u32_u64(nullptr, &tmp2, tkey, tkey_sorted, task, task_sorted, (int32_t)NT, 14, s));
+    MBE_TRY(st->sort_tmp.ensure(std::max(tmp, tmp2)));
+    tmp = st->sort_tmp.bytes;
+    MBE_TRY(segmented_sort_u64(st->sort_tmp.p, &tmp, keys, sorted, (int32_t)NC, n, d_cb, d_cb + 1, end_bit, s));
+    std::vector<unsigned long long> hg((size_t)n * 2);
+    unsigned long long hstats[16];
+    MBE_TRY(hipMemcpyAsync(hg.data(), gstats, (size_t)n * 16, hipMemcpyDeviceToHost, s));
+    MBE_TRY(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
+    MBE_TRY(launch_batch_scatter((int32_t)NC, sorted, d_gof, d_cb, gstats, order, rank, tkey, task, d_tb, s));
+    tmp = st->sort_tmp.bytes;
+    MBE_TRY(sort_pairs_u32_u64(st->sort_tmp.p, &tmp, tkey, tkey_sorted, task, task_sorted, (int32_t)NT, 14, s));
+    MBE_TRY(hipStreamSynchronize(s));
+
+    // descriptors and capacities
+    std::vector<GraphDesc> gd(n);
+    int64_t ucap = 1, post = 64, maxc = 1;
+    for (int32_t i = 0; i < n; ++i) {
+        GraphDesc &d = gd[i];
+        std::memset(&d, 0, sizeof(d));
+        d.order = order + cb[i];
+        d.acc = gacc + (size_t)i * ACC_SLOTS;
+        d.ncand = (int32_t)ncand_h[i];
+        d.total_fw = 2ull * (unsigned long long)ncand_h[i] + (unsigned long long)(eb[i + 1] - eb[i]);
+        d.nwords = (int32_t)((ncand_h[i] + 63) / 64);
+        d.c_is_v = side[i] == 2 ? 1 : 0;
+        d.cbase = cb[i];
+        d.obase = ob[i];
+        ucap = std::max<int64_t>(ucap, std::min<int64_t>(ncand_h[i], (int64_t)hg[2 * i + 1]));
+        post = std::max<int64_t>(post, (int64_t)hg[2 * i + 1]);
+        maxc = std::max<int64_t>(maxc, ncand_h[i]);
+    }
+    MBE_TRY(hipMemcpyAsync(d_gd, gd.data(), (size_t)n * sizeof(GraphDesc), hipMemcpyHostToDevice, s));
+    int Wmax = 1;
+    int64_t cls_lo[5], cls_hi[5], run_t = 0;
+    for (int c = 0; c < 5; ++c) {
+        cls_lo[c] = run_t;
+        run_t += cls_cnt[c];
+        cls_hi[c] = run_t;
+        if (cls_cnt[c]) Wmax = 1 << c;
+    }
+    SearchDims dims{};
+    dims.nwords = (int32_t)((maxc + 63) / 64);
+    dims.Wmax = Wmax;
+    dims.waves = opt.waves;
+    dims.ucap = (int32_t)ucap;
+    dims.post_cap = post;
+    dims.scap = 2 * ucap + 16384;
+    dims.maxdepth = 64 * Wmax + 2;
+    const int grid = opt.grid > 0 ? opt.grid : 2 * st->cus;
+
+    SearchArgs a{};
+    a.c_off = d_coff;
+    a.c_adj = d_cadj;
+    a.o_off = d_ooff;
+    a.o_adj = d_oadj;
+    a.rank = rank;
+    a.graphs = d_gd;
+    a.tasks = task_sorted;
+    a.acc = acc;
+    a.flags = flags;
+    unsigned long long hacc[ACC_SLOTS];
+    unsigned int hflags = 0;
+    float ms = 0.f;
+    int rc = run_search(st, a, dims, cls_lo, cls_hi, opt.diag, false, grid, opt.waves, acc, ACC_SLOTS * 8, hacc, &hflags,
+                        &ms, s, gacc, (size_t)n * ACC_SLOTS * 8);
+    if (rc != MBE_OK) return rc;
+    std::vector<unsigned long long> hga((size_t)n * ACC_SLOTS);
+    MBE_TRY(hipMemcpyAsync(hga.data(), gacc, hga.size() * 8, hipMemcpyDeviceToHost, s));
+    MBE_TRY(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < n; ++i) {
+        const unsigned long long *q = &hga[(size_t)i * ACC_SLOTS];
+        outs[i].count = q[ACC_COUNT];
+        outs[i].hash = q[ACC_HASH];
+        outs[i].out_ints = q[ACC_OUT_INTS];
+        outs[i].nodes = q[ACC_NODES];
+        outs[i].nonmaximal = q[ACC_NONMAX];
+        outs[i].bytes_alg = q[ACC_BYTES];
+        outs[i].max_depth = (uint32_t)q[ACC_MAX_DEPTH];
+        outs[i].kernel_ms = ms;
+    }
+    return MBE_OK;
+}
+
+// ------------------------------------------------------------------------------ serving
+//
+// Continuous batching: requests are queued as they arrive; each of the server's slots (a
+// worker thread with its own stream and device workspace, kept between batches) takes the
+// queued requests in arrival order while their estimated device footprint fits the slot's
+// share of the memory budget, runs them as one batched pass, and posts the results.  With
+// two or more slots a batch starts while the previous one is still on the device, so
+// requests that arrive during a run are admitted as soon as a slot and memory free up.
+
+using Clock = std::chrono::steady_clock;
+
+struct ServerRequest {
+    uint64_t ticket = 0;
+    std::vector<int32_t> u_off, u_adj, v_off, v_adj;
+    mbe_graph g{};
+    size_t csr_bytes = 0, arena_bytes = 0;
+    Clock::time_point arrival, finish;
+    mbe_result result{};
+    int rc = 0;
+    bool done = false;
+};
+
+void free_state(DeviceState *st) {
+    DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->rec,
+                      &st->rec_offs, &st->rec_tmp, &st->rec_lens, &st->canon_tmp, &st->out_tmp};
+    for (DevBuf *b : bufs)
+        if (b->p) {
+            (void)hipFree(b->p);
+            b->p = nullptr;
+            b->bytes = 0;
+        }
+    if (st->ev0) (void)hipEventDestroy(st->ev0);
+    if (st->ev1) (void)hipEventDestroy(st->ev1);
+}
+
+}  // namespace
+
+struct mbe_server {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<ServerRequest>> pending;
+    std::unordered_map<uint64_t, std::shared_ptr<ServerRequest>> live;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    size_t slot_budget = 0;
+    int max_batch = 4096;
+    int device = 0;
+    int cus = 256;
+    mbe_options search{};
+    std::vector<std::thread> workers;
+    std::vector<DeviceState *> states;
+    std::vector<hipStream_t> streams;
+    uint64_t batches = 0, served = 0;
+
+    // device bytes a request adds: its CSR and preparation arrays, and the search arena its
+    // largest local universe needs (the arena is shared by a batch, so only its maximum counts)
+    void estimate(ServerRequest &r) const {
+        const mbe_graph &g = r.g;
+        const int64_t nc = std::min(g.n_u, g.n_v), no = std::max(g.n_u, g.n_v);
+        r.csr_bytes = (size_t)4 * ((size_t)g.n_u + g.n_v + 2 + 2 * (size_t)g.n_edges) + (size_t)48 * nc + 4096;
+        int64_t dmax = 0;
+        const int32_t *off = g.n_v < g.n_u ? g.v_off : g.u_off;
+        for (int64_t v = 0; v < nc && off; ++v) dmax = std::max<int64_t>(dmax, off[v + 1] - off[v]);
+        int64_t W = 1;
+        while (64 * W < dmax && W < 16) W *= 2;
+        const int waves = search.wg_waves > 0 ? search.wg_waves : 8;
+        const int grid = search.grid > 0 ? search.grid : 2 * cus;
+        const size_t per_wg = (size_t)nc * (size_t)(24 * W + 40) + (size_t)waves * ((size_t)nc * 20 + 65536) +
+                              (size_t)no / 8 + 65536;
+        r.arena_bytes = per_wg * (size_t)grid;
+    }
+
+    void worker(int slot) {
+        (void)hipSetDevice(device);
+        for (;;) {
+            std::vector<std::shared_ptr<ServerRequest>> batch;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
+                if (pending.empty()) return;  // stopping
+                size_t csr = 0, arena = 0;
+                while (!pending.empty() && (int)batch.size() < max_batch) {
+                    const ServerRequest &r = *pending.front();
+                    const size_t need = csr + r.csr_bytes + std::max(arena, r.arena_bytes);
+                    if (!batch.empty() && need > slot_budget) break;
+                    csr += r.csr_bytes;
+                    arena = std::max(arena, r.arena_bytes);
+                    batch.push_back(pending.front());
+                    pending.pop_front();
+                }
+            }
+            std::vector<mbe_graph> gs(batch.size());
+            std::vector<mbe_result> rs(batch.size());
+            for (size_t i = 0; i < batch.size(); ++i) gs[i] = batch[i]->g;
+            mbe_options o = search;
+            o.stream = streams[slot];
+            o.no_validate = 1;  // checked at submission
+            const int rc = run_batch_on(states[slot], streams[slot], gs.data(), (int32_t)gs.size(), &o, rs.data());
+            const Clock::time_point now = Clock::now();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (size_t i = 0; i < batch.size(); ++i) {
+                    batch[i]->result = rs[i];
+                    batch[i]->rc = rc;
+                    batch[i]->finish = now;
+                    batch[i]->done = true;
+                    // the graph copy is no longer needed
+                    std::vector<int32_t>().swap(batch[i]->u_adj);
+                    std::vector<int32_t>().swap(batch[i]->v_adj);
+                }
+                ++batches;
+                served += batch.size();
+            }
+            cv_done.notify_all();
+        }
+    }
+};
+
+namespace {
+
+int server_create(const mbe_server_options *opt, mbe_server **out) {
+    if (!out) return MBE_ERR_INVALID_ARG;
+    *out = nullptr;
+    int slots = opt && opt->slots > 0 ? opt->slots : 2;
+    if (slots > 8) return MBE_ERR_INVALID_ARG;
+    std::unique_ptr<mbe_server> sv(new mbe_server());
+    if (opt) {
+        sv->search = opt->search;
+        if (opt->max_batch > 0) sv->max_batch = opt->max_batch;
+    }
+    sv->search.root_lo = sv->search.root_hi = 0;
+    if (sv->search.wg_waves < 0 || sv->search.wg_waves > 8 || sv->search.side < 0 || sv->search.side > 2)
+        return MBE_ERR_INVALID_ARG;
+    MBE_TRY(hipGetDevice(&sv->device));
+    if (hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, sv->device) != hipSuccess || sv->cus <= 0)
+        sv->cus = 256;
+    size_t budget = opt ? opt->hbm_budget_bytes : 0;
+    if (budget == 0) {
+        size_t free_b = 0, total_b = 0;
+        MBE_TRY(hipMemGetInfo(&free_b, &total_b));
+        budget = free_b / 2;
+    }
+    sv->slot_budget = budget / (size_t)slots;
+    for (int k = 0; k < slots; ++k) {
+        DeviceState *st = new DeviceState();
+        if (hipEventCreate(&st->ev0) != hipSuccess || hipEventCreate(&st->ev1) != hipSuccess) {
+            delete st;
+            return MBE_ERR_DEVICE;
+        }
+        st->cus = sv->cus;
+        sv->states.push_back(st);
+        hipStream_t strm = nullptr;
+        MBE_TRY(hipStreamCreateWithFlags(&strm, hipStreamNonBlocking));
+        sv->streams.push_back(strm);
+    }
+    mbe_server *raw = sv.get();
+    for (int k = 0; k < slots; ++k) sv->workers.emplace_back([raw, k] { raw->worker(k); });
+    *out = sv.release();
+    return MBE_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int mbe_server_create(const mbe_server_options *opt, mbe_server **out) { return server_create(opt, out); }
+
+int mbe_server_submit(mbe_server *sv, const mbe_graph *g, uint64_t *ticket) {
+    if (!sv || !g || !ticket) return MBE_ERR_INVALID_ARG;
+    if (g->on_device || g->n_u < 0 || g->n_v < 0 || g->n_edges < 0) return MBE_ERR_INVALID_ARG;
+    if ((g->n_u > 0 && !g->u_off) || (g->n_v > 0 && !g->v_off) || (g->n_edges > 0 && (!g->u_adj || !g->v_adj)))
+        return MBE_ERR_INVALID_ARG;
+    {
+        // a malformed graph is refused here, so it can never fail the batch it would join
+        const int rc = check_graphs(g, 1, sv->search.no_validate == 0);
+        if (rc != MBE_OK) return rc;
+    }
+    auto r = std::make_shared<ServerRequest>();
+    r->arrival = Clock::now();
+    r->u_off.assign(g->u_off ? g->u_off : nullptr, g->u_off ? g->u_off + g->n_u + 1 : nullptr);
+    r->v_off.assign(g->v_off ? g->v_off : nullptr, g->v_off ? g->v_off + g->n_v + 1 : nullptr);
+    r->u_adj.assign(g->u_adj ? g->u_adj : nullptr, g->u_adj ? g->u_adj + g->n_edges : nullptr);
+    r->v_adj.assign(g->v_adj ? g->v_adj : nullptr, g->v_adj ? g->v_adj + g->n_edges : nullptr);
+    r->g = *g;
+    r->g.u_off = r->u_off.empty() ? nullptr : r->u_off.data();
+    r->g.v_off = r->v_off.empty() ? nullptr : r->v_off.data();
+    r->g.u_adj = r->u_adj.empty() ? nullptr : r->u_adj.data();
+    r->g.v_adj = r->v_adj.empty() ? nullptr : r->v_adj.data();
+    sv->estimate(*r);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stopping) return MBE_ERR_INVALID_ARG;
+        r->ticket = sv->next_ticket++;
+        sv->live[r->ticket] = r;
+        sv->pending.push_back(r);
+    }
+    sv->cv_work.notify_one();
+    *ticket = r->ticket;
+    return MBE_OK;
+}
+
+int mbe_server_wait(mbe_server *sv, uint64_t ticket, mbe_result *out, double *latency_ms) {
+    if (!sv || !out) return MBE_ERR_INVALID_ARG;
+    std::shared_ptr<ServerRequest> r;
+    {
+        std::unique_lock<std::mutex> lk(sv->mu);
+        auto it = sv->live.find(ticket);
+        if (it == sv->live.end()) return MBE_ERR_INVALID_ARG;
+        r = it->second;
+        sv->cv_done.wait(lk, [&] { return r->done; });
+        sv->live.erase(it);
+    }
+    *out = r->result;
+    if (latency_ms) latency_ms[0] = std::chrono::duration<double, std::milli>(r->finish - r->arrival).count();
+    return r->rc;
+}
+
+int mbe_server_destroy(mbe_server *sv) {
+    if (!sv) return MBE_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stopping = true;
+    }
+    sv->cv_work.notify_all();
+    for (auto &t : sv->workers) t.join();
+    for (size_t k = 0; k < sv->states.size(); ++k) {
+        (void)hipStreamSynchronize(sv->streams[k]);
+        free_state(sv->states[k]);
+        delete sv->states[k];
+        (void)hipStreamDestroy(sv->streams[k]);
+    }
+    delete sv;
+    return MBE_OK;
+}
+
+
+int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_result *outs) {
+    return run_batch(gs, n, opt, outs);
+}
+
 
 int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out) {
     return run(g, opt, out, nullptr, 0, 0, false);

@@ -17,54 +17,88 @@ enum AccSlot : int {
     ACC_NONMAX = 4,
     ACC_BYTES = 5,
     ACC_MAX_DEPTH = 6,
-    ACC_RECORDS = 7,   // records reserved in the record arena
-    ACC_REC_INTS = 8,  // ints reserved in the record arena
+    ACC_RECORDS = 7,    // records reserved in the record arena
+    ACC_REC_INTS = 8,   // ints reserved in the record arena
+    ACC_NEED_UCAP = 9,  // largest universe met (max), for resizing after an overflow
+    ACC_NEED_POST = 10, // largest top-level posting total met (max)
     ACC_SLOTS = 16,
 };
 
 // Status bits raised by kernels.
 enum FlagBits : unsigned int {
-    FLAG_STACK_OVERFLOW = 1u << 0,   // a wave's explicit stack was too small: rerun larger
-    FLAG_DEPTH_OVERFLOW = 1u << 1,   // frame-header array too small: rerun larger
-    FLAG_RECORD_OVERFLOW = 1u << 2,  // record arena too small (count/hash still exact)
-    FLAG_BAD_GRAPH = 1u << 3,        // validation failure
-    FLAG_DEGREE = 1u << 4,           // candidate degree above the supported mask width
+    FLAG_STACK_OVERFLOW = 1u << 0,     // a wave's explicit stack was too small: rerun larger
+    FLAG_DEPTH_OVERFLOW = 1u << 1,     // frame-header array too small: rerun larger
+    FLAG_RECORD_OVERFLOW = 1u << 2,    // record arena too small (count/hash still exact)
+    FLAG_BAD_GRAPH = 1u << 3,          // validation failure
+    FLAG_DEGREE = 1u << 4,             // candidate degree above the supported mask width
+    FLAG_UNIVERSE_OVERFLOW = 1u << 5,  // a local universe or its posting lists did not fit
+};
+constexpr unsigned int FLAG_RERUN = FLAG_STACK_OVERFLOW | FLAG_DEPTH_OVERFLOW | FLAG_UNIVERSE_OVERFLOW;
+
+// Capacities of the search arena.
+struct SearchDims {
+    int32_t ucap;      // local-universe capacity (entries)
+    int32_t nwords;    // words of the rank bitmap
+    int32_t Wmax;      // widest mask class in use (words)
+    int32_t waves;     // waves per workgroup
+    int64_t post_cap;  // posting entries of the top-level candidate list
+    int64_t scap;      // per-wave stack capacity (32-bit words)
+    int32_t maxdepth;  // per-wave frame headers
+    int32_t pad;
 };
 
 // Byte offsets of the per-workgroup and per-wave regions of the search arena.
 struct ArenaLayout {
-    size_t wg_bytes;      // stride between workgroups
-    size_t off_bitmap;    // u64[nwords]     membership bitmap over candidate ranks
-    size_t off_bpre;      // u32[nwords+1]   popcount prefix of the bitmap words
-    size_t off_M;         // u64[ucap*W]     neighbour masks of the local universe
-    size_t off_gid;       // i32[ucap]       global id of each universe entry
-    size_t off_cnt;       // u32[ucap]       top-level counts |N(v) n N(x)|
-    size_t off_hv;        // u64[64*Wmax]    hash term of each local other-side vertex
-    size_t off_deg;       // u32[64*Wmax]    degree of each local other-side vertex
-    size_t off_S1;        // u32[ucap]       the top-level node's child candidate list
-    size_t off_t1v;       // u32[ucap]       sort staging (ids)
-    size_t off_t1c;       // u32[ucap]       sort staging (keys)
-    size_t off_waves;     // start of the per-wave regions
-    size_t wave_bytes;    // stride between waves
-    size_t off_w_stack;   // u32[scap]       explicit DFS stack of candidate lists
-    size_t off_w_tv;      // u32[ucap]       child staging (ids)
-    size_t off_w_tc;      // u32[ucap]       child staging (keys)
-    size_t off_w_hdr;     // frame headers[maxdepth]
+    size_t wg_bytes;    // stride between workgroups
+    size_t off_bitmap;  // u64[nwords]          membership bitmap over candidate ranks
+    size_t off_bpre;    // u32[nwords+1]        popcount prefix of the bitmap words
+    size_t off_M;       // u64[ucap*Wmax]       neighbour masks of the local universe
+    size_t off_gid;     // i32[ucap]            global id of each universe entry
+    size_t off_cnt;     // u32[ucap]            top-level counts |N(v) n N(x)|
+    size_t off_hv;      // u64[64*Wmax]         R-side hash term of each position of N(x)
+    size_t off_deg;     // u32[64*Wmax]         degree of each position of N(x)
+    size_t off_t1v;     // u32[ucap]            sort staging (ids)
+    size_t off_t1c;     // u32[ucap]            sort staging (keys)
+    size_t off_cur1;    // u32[64*Wmax]         posting cursors
+    size_t off_S1;      // u32[s1_words]        the top-level node's child list as a frame
+    size_t s1_words;
+    size_t off_waves;   // start of the per-wave regions
+    size_t wave_bytes;  // stride between waves
+    size_t off_w_stack; // u32[scap]            frames (lists, masks, per-bit tables)
+    size_t off_w_q;     // u32[ucap]            staging of Q' (parent positions)
+    size_t off_w_p;     // u32[ucap]            staging of P' (parent positions)
+    size_t off_w_c;     // u32[ucap]            staging of P' counts
+    size_t off_w_cur;   // u32[64*Wmax]         posting cursors
+    size_t off_w_hdr;   // frame headers[maxdepth]
+};
+
+// One graph of the packed candidate-orientation arrays.  A single call has one; a batch
+// packs its graphs as a disjoint union, each graph in its own orientation.
+struct GraphDesc {
+    const int32_t *order;       // order[r]: packed candidate id of local rank r
+    unsigned long long *acc;    // this graph's ACC_SLOTS accumulators
+    unsigned long long total_fw;// sum over its candidates of (2 + deg v), for the byte tally
+    int32_t ncand;              // candidates of degree > 0
+    int32_t nwords;             // words of its rank bitmap
+    int32_t c_is_v;             // its candidate side is V
+    int32_t cbase, obase;       // first packed id of its candidate / other side
+    int32_t pad;
 };
 
 struct SearchArgs {
-    // graph in candidate orientation
-    int32_t nc, no, ncand, c_is_v;
+    // packed graph(s) in candidate orientation: rows of c_off / c_adj are candidates, ids in
+    // c_adj are other-side ids and vice versa
     const int32_t *c_off, *c_adj, *o_off, *o_adj;
-    const int32_t *order;  // order[r]: candidate of rank r (ascending (deg, id), deg > 0)
-    const int32_t *rank;   // rank[v]: rank of candidate v, -1 if deg v = 0
-    uint64_t total_fw;     // sum over candidates of (2 + deg v), for the byte tally
+    const int32_t *rank;   // rank[v]: local rank of candidate v within its graph, -1 if deg v = 0
+    const GraphDesc *graphs;
+    // work list: tasks[t] = (graph << 32) | local rank; NULL means graph 0, ranks [lo, hi)
+    const unsigned long long *tasks;
     // arena
     char *arena;
+    SearchDims dims;
     ArenaLayout lay;
-    int32_t ucap, scap, maxdepth, nwords;
     // outputs
-    unsigned long long *acc;
+    unsigned long long *acc;    // run-wide slots (overflow sizes, record cursors)
     unsigned int *flags;
     // record arena (mbe_enumerate only)
     int32_t *rec;
@@ -73,26 +107,42 @@ struct SearchArgs {
     unsigned long long rec_offs_cap;
 };
 
-// Launch the search over the candidates of rank [lo, hi), all of whose degrees are at most
-// 64*W for the given mask width class.  counter must be zero.
-hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, int64_t lo,
-                         int64_t hi, unsigned int *counter, int grid, int waves, size_t lds_bytes,
-                         hipStream_t s);
+// Arena layout for the given capacities (host side).
+ArenaLayout search_layout(const SearchDims &d);
 
-size_t frame_header_bytes(int W);
-size_t search_lds_bytes(int W, int waves);
+// Launch the search over tasks [lo, hi) of the work list (or ranks [lo, hi) of graph 0 when
+// it is NULL), all of whose top-level candidates have degree at most 64*W.  counter must be
+// zero.
+hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, int64_t lo,
+                         int64_t hi, unsigned int *counter, int grid, int waves, hipStream_t s);
 
 // Graph preparation and validation (mbe_prep.hip).
 hipError_t launch_validate(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *off,
                            const int32_t *adj, const int32_t *t_off, const int32_t *t_adj,
                            unsigned int *flags, hipStream_t s);
-// keys[v] = (deg v << 32) | v for every candidate; also counts candidates per mask class.
-hipError_t launch_rank_keys(int32_t nc, const int32_t *c_off, unsigned long long *keys,
-                            unsigned long long *stats, hipStream_t s);
+// keys[v] = (deg v << 32) | v for every candidate; also counts candidates per mask class and
+// bounds the local universes (see mbe_prep.hip).
+hipError_t launch_rank_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
+                            unsigned long long *keys, unsigned long long *stats, hipStream_t s);
 hipError_t launch_rank_scatter(int32_t nc, int32_t nzero, const unsigned long long *sorted,
                                int32_t *order, int32_t *rank, hipStream_t s);
 hipError_t radix_sort_u64(void *temp, size_t *temp_bytes, const unsigned long long *in,
                           unsigned long long *out, int32_t n, int end_bit, hipStream_t s);
+
+// Batched preparation (mbe_prep.hip).
+hipError_t launch_batch_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
+                             const int32_t *graph_of, const int32_t *cbase, unsigned long long *keys,
+                             unsigned long long *gstats, unsigned long long *stats, hipStream_t s);
+hipError_t launch_batch_scatter(int32_t nc, const unsigned long long *sorted, const int32_t *graph_of,
+                                const int32_t *cbase, const unsigned long long *gstats, int32_t *order, int32_t *rank,
+                                unsigned int *task_key, unsigned long long *task, const int32_t *tbase,
+                                hipStream_t s);
+hipError_t segmented_sort_u64(void *temp, size_t *temp_bytes, const unsigned long long *in, unsigned long long *out,
+                              int32_t n, int32_t nseg, const int32_t *seg_begin, const int32_t *seg_end, int end_bit,
+                              hipStream_t s);
+hipError_t sort_pairs_u32_u64(void *temp, size_t *temp_bytes, const unsigned int *kin, unsigned int *kout,
+                              const unsigned long long *vin, unsigned long long *vout, int32_t n, int end_bit,
+                              hipStream_t s);
 
 // Record canonicalisation (mbe_records.hip).
 hipError_t canonical_records(const int32_t *rec, unsigned long long *offs, unsigned long long n_rec,

@@ -5,6 +5,7 @@
 // out because they belong to no biclique with two non-empty sides.
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "mbe_internal.h"
 
@@ -50,12 +51,14 @@ __global__ void validate_kernel(int32_t n_rows, int32_t n_cols, int32_t n_edges,
 }
 
 // keys[v] = (deg << 32) | v; stats[0] = number of degree-0 vertices, stats[1 + c] = number of
-// candidates in mask class c (degree <= 64 << c), stats[8] = max degree.
-__global__ void rank_keys_kernel(int32_t nc, const int32_t *c_off, unsigned long long *keys,
-                                 unsigned long long *stats) {
+// candidates in mask class c (degree <= 64 << c), stats[8] = max degree, stats[9] = max over
+// candidates of the 2-hop walk count sum_{w in N(v)} deg w (bounds a local universe).
+__global__ void rank_keys_kernel(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
+                                 unsigned long long *keys, unsigned long long *stats) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nc; v += stride) {
-        const uint32_t d = (uint32_t)(c_off[v + 1] - c_off[v]);
+        const int32_t b = c_off[v], e = c_off[v + 1];
+        const uint32_t d = (uint32_t)(e - b);
         keys[v] = ((unsigned long long)d << 32) | (unsigned long long)(uint32_t)v;
         if (d == 0) {
             atomicAdd(&stats[0], 1ull);
@@ -64,6 +67,12 @@ __global__ void rank_keys_kernel(int32_t nc, const int32_t *c_off, unsigned long
             while (cls < 6 && d > (64u << cls)) ++cls;
             atomicAdd(&stats[1 + cls], 1ull);
             atomicMax(&stats[8], (unsigned long long)d);
+            unsigned long long walks = 0;
+            for (int32_t p = b; p < e; ++p) {
+                const int32_t w = c_adj[p];
+                walks += (unsigned long long)(o_off[w + 1] - o_off[w]);
+            }
+            atomicMax(&stats[9], walks);
         }
     }
 }
@@ -78,6 +87,63 @@ __global__ void rank_scatter_kernel(int32_t nc, int32_t nzero, const unsigned lo
         } else {
             order[i - nzero] = v;
             rank[v] = (int32_t)(i - nzero);
+        }
+    }
+}
+
+// Packed batch: graph g owns candidate ids [cbase[g], cbase[g+1]).  keys[v] = (deg << 32) |
+// local id; gstats[g]: [0] degree-0 candidates, [1] max 2-hop walk count; stats[8] = max
+// degree over the batch.
+__global__ void batch_keys_kernel(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
+                                  const int32_t *graph_of, const int32_t *cbase, unsigned long long *keys,
+                                  unsigned long long *gstats, unsigned long long *stats) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nc; v += stride) {
+        const int32_t g = graph_of[v];
+        const int32_t b = c_off[v], e = c_off[v + 1];
+        const uint32_t d = (uint32_t)(e - b);
+        keys[v] = ((unsigned long long)d << 32) | (unsigned long long)(uint32_t)(v - cbase[g]);
+        if (d == 0) {
+            atomicAdd(&gstats[2 * g], 1ull);
+        } else {
+            atomicMax(&stats[8], (unsigned long long)d);
+            unsigned long long walks = 0;
+            for (int32_t p = b; p < e; ++p) {
+                const int32_t w = c_adj[p];
+                walks += (unsigned long long)(o_off[w + 1] - o_off[w]);
+            }
+            atomicMax(&gstats[2 * g + 1], walks);
+        }
+    }
+}
+
+// After the per-graph sort: order / rank of every candidate, one task per candidate of degree
+// > 0 keyed so that a radix sort groups tasks by mask class, largest degree first, and the
+// graph descriptors.
+__global__ void batch_scatter_kernel(int32_t nc, const unsigned long long *sorted, const int32_t *graph_of,
+                                     const int32_t *cbase, const unsigned long long *gstats, int32_t *order,
+                                     int32_t *rank, unsigned int *task_key, unsigned long long *task,
+                                     const int32_t *tbase) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        const int32_t g = graph_of[i];  // sorted position i lies in graph g's segment
+        const int32_t nzero = (int32_t)gstats[2 * g];
+        const unsigned long long key = sorted[i];
+        const int32_t v = cbase[g] + (int32_t)(key & 0xFFFFFFFFull);
+        const uint32_t d = (uint32_t)(key >> 32);
+        const int32_t li = (int32_t)(i - cbase[g]);
+        if (li < nzero) {
+            rank[v] = -1;
+        } else {
+            const int32_t r = li - nzero;
+            order[cbase[g] + r] = v;
+            rank[v] = r;
+            uint32_t cls = 0;
+            while (cls < 6 && d > (64u << cls)) ++cls;
+            const uint32_t dk = d < 2047u ? d : 2047u;
+            const int32_t t = tbase[g] + r;
+            task_key[t] = (cls << 11) | (2047u - dk);
+            task[t] = ((unsigned long long)(uint32_t)g << 32) | (unsigned long long)(uint32_t)r;
         }
     }
 }
@@ -100,10 +166,11 @@ hipError_t launch_validate(int32_t n_rows, int32_t n_cols, int32_t n_edges, cons
     return hipGetLastError();
 }
 
-hipError_t launch_rank_keys(int32_t nc, const int32_t *c_off, unsigned long long *keys,
-                            unsigned long long *stats, hipStream_t s) {
+hipError_t launch_rank_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
+                            unsigned long long *keys, unsigned long long *stats, hipStream_t s) {
     if (nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(rank_keys_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, c_off, keys, stats);
+    hipLaunchKernelGGL(rank_keys_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, c_off, c_adj, o_off, keys,
+                       stats);
     return hipGetLastError();
 }
 
@@ -113,6 +180,38 @@ hipError_t launch_rank_scatter(int32_t nc, int32_t nzero, const unsigned long lo
     hipLaunchKernelGGL(rank_scatter_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, nzero, sorted,
                        order, rank);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
+                             const int32_t *graph_of, const int32_t *cbase, unsigned long long *keys,
+                             unsigned long long *gstats, unsigned long long *stats, hipStream_t s) {
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_keys_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, c_off, c_adj, o_off, graph_of,
+                       cbase, keys, gstats, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_scatter(int32_t nc, const unsigned long long *sorted, const int32_t *graph_of,
+                                const int32_t *cbase, const unsigned long long *gstats, int32_t *order, int32_t *rank,
+                                unsigned int *task_key, unsigned long long *task, const int32_t *tbase,
+                                hipStream_t s) {
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_scatter_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, sorted, graph_of, cbase,
+                       gstats, order, rank, task_key, task, tbase);
+    return hipGetLastError();
+}
+
+hipError_t segmented_sort_u64(void *temp, size_t *temp_bytes, const unsigned long long *in, unsigned long long *out,
+                              int32_t n, int32_t nseg, const int32_t *seg_begin, const int32_t *seg_end, int end_bit,
+                              hipStream_t s) {
+    return rocprim::segmented_radix_sort_keys(temp, *temp_bytes, in, out, (unsigned int)n, (unsigned int)nseg,
+                                              seg_begin, seg_end, 0, end_bit, s);
+}
+
+hipError_t sort_pairs_u32_u64(void *temp, size_t *temp_bytes, const unsigned int *kin, unsigned int *kout,
+                              const unsigned long long *vin, unsigned long long *vout, int32_t n, int end_bit,
+                              hipStream_t s) {
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, kin, kout, vin, vout, (unsigned int)n, 0, end_bit, s);
 }
 
 hipError_t radix_sort_u64(void *temp, size_t *temp_bytes, const unsigned long long *in,

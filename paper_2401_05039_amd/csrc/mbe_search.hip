@@ -5,35 +5,42 @@
 // shrinking set R (other side O) becomes R' = R n N(x), the maximality check fails when a
 // vertex of Q is adjacent to all of R', the expansion moves every candidate of P adjacent
 // to all of R' into L', and P' / Q' keep the vertices with 0 < |N(v) n R'| < |R'|.  The
-// counts |N(v) n R'| come from the reverse scan of section III-E: walk R' and its
-// neighbours instead of every candidate's list.  Candidates are taken in ascending count
+// counts come from reverse scanning (section III-E): walk the vertices of R' and their
+// neighbours rather than every candidate's list.  Candidates are taken in ascending count
 // (sections II-C and III-E), ties in the order of the parent's list.
 //
-// How it maps to the hardware (this is the build's own design, not the paper's CUDA one):
+// How it maps to the hardware (the build's own design, not the paper's CUDA one):
 //
 //  * Coarse grain (section III-C's first-level subtrees): one workgroup owns one top-level
-//    candidate x at a time, claimed from a global atomic counter, heaviest ranks first.
+//    candidate x at a time, claimed from a global atomic counter, largest degree first.
 //
-//  * Local universe.  Every vertex that can appear below x is a 2-hop neighbour of x and
-//    every R below x is a subset of N(x).  The workgroup runs the reverse scan over N(x)
-//    once and builds, for each 2-hop neighbour v, the mask M[v] = N(v) n N(x) as W 64-bit
-//    words over the positions of N(x) (W = ceil(deg x / 64)).  Universe entries are indexed
-//    in top-level rank order, so the top-level Q (earlier ranks) is a prefix.  After that a
-//    count |N(v) n R'| is popcount(M[v] & R') and never touches the CSR again.
+//  * Local universe.  Every vertex below x is a 2-hop neighbour of x and every R below x is
+//    a subset of N(x).  The workgroup runs the reverse scan over N(x) once and gives each
+//    2-hop neighbour v the mask M[v] = N(v) n N(x) over the positions of N(x) (W 64-bit
+//    words).  Universe entries are numbered in top-level rank order, so the top-level Q is
+//    a prefix.  Below the top level the CSR is never read again.
 //
-//  * Fine grain.  The top-level node's children are independent subtrees (the paper's k = 2
-//    level): the waves of the workgroup claim them from an LDS counter and each runs its
-//    own depth-first search.  A node is one pass of the wave over the parent's candidate
-//    list: 64 lanes read 64 entries, AND them with R', popcount, and ballot/prefix-sum
-//    compact the survivors; P' is stably counting-sorted by its counts.
+//  * Frames.  A frame is the candidate list of one search node: entry k carries its mask
+//    restricted to the frame's R, so a child's R' is simply the candidate's own mask.  When
+//    |R| <= 64 the masks are compressed to |R| bits (one word).  Each frame also holds
+//    inverted per-bit tables -- the paper's reverse scan turned into an index: for every bit
+//    b of R, the first list position with b, the number of entries with b, the sum of their
+//    L-side hash terms and the posting list of positions with b.
 //
-//  * Compact stack (section III-B's goal: no recursion, no allocation).  A wave's frames
-//    are candidate lists laid back to back in one preallocated array; a child's list is
-//    strictly shorter than its parent's and is written right after it.  Frame headers
-//    (list position, R as W words, the running hash of L) sit in a small array.
+//  * Nodes.  A candidate at position i with |R'| = 1 (almost every node on power-law
+//    graphs) is settled by one lookup: it is maximal exactly when the first entry with its
+//    bit is itself, and then L' is every entry with that bit.  The 64 lanes of a wave settle
+//    64 such candidates at once.  Candidates with |R'| >= 2 are handled by the whole wave:
+//    a maximality test on the rarest bit's posting list, and for maximal nodes one scan of
+//    the list that counts, compacts (ballot + prefix sum) and stably counting-sorts P'.
 //
-// Counts and hashes are commutative u64 sums, so results do not depend on which wave or
-// workgroup handled which subtree.
+//  * Second level (the paper's k = 2 subtrees): the waves of the workgroup claim 64-wide
+//    chunks of the top-level node's child list from an LDS counter; each wave then runs its
+//    own depth-first search on an explicit stack of frames (section III-B's goal: no
+//    recursion and no allocation; frames are laid back to back in one preallocated array).
+//
+// Counts and hashes are commutative u64 sums, so results do not depend on which lane, wave
+// or workgroup settled which node.
 
 #include "mbe_internal.h"
 
@@ -42,6 +49,8 @@ namespace mbe {
 namespace {
 
 constexpr uint64_t kHashK = 0x9E3779B97F4A7C15ull;
+constexpr uint32_t kShared = 0xFFFFFFFFu;  // frame offset meaning "the workgroup's top-level list"
+constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -52,11 +61,11 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z ^= z >> 31;
     return z;
 }
-__device__ __forceinline__ uint64_t hash_u(int32_t a) {
-    return mix64(kHashK * (2ull * (uint64_t)(uint32_t)a + 1ull));
-}
-__device__ __forceinline__ uint64_t hash_v(int32_t b) {
-    return mix64(kHashK * (2ull * (uint64_t)(uint32_t)b + 2ull));
+__device__ __forceinline__ uint64_t hash_u(int32_t a) { return mix64(kHashK * (2ull * (uint64_t)(uint32_t)a + 1ull)); }
+__device__ __forceinline__ uint64_t hash_v(int32_t b) { return mix64(kHashK * (2ull * (uint64_t)(uint32_t)b + 2ull)); }
+__device__ __forceinline__ uint64_t pair_hash(int c_is_v, uint64_t sL, uint64_t sR) {
+    // h(A, B) = mix(sum hu(A) + mix(sum hv(B) + K)); A is the U side.
+    return c_is_v ? mix64(sR + mix64(sL + kHashK)) : mix64(sL + mix64(sR + kHashK));
 }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
@@ -67,39 +76,119 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = __shfl_xor(v, o);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = __shfl_xor(v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
 __device__ __forceinline__ int wave_incl_scan(int v) {
     const int ln = lane_id();
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o);
+        const int t = __shfl_up(v, o);
         if (ln >= o) v += t;
     }
     return v;
 }
 
-template <int W>
-struct Frame {
-    const uint32_t *S;  // candidate list: [0, nq) Q part, [nq, n) P part in processing order
-    int32_t n, nq, pos, level;
-    int32_t end;        // candidates [pos, end) of the list are still to be taken here
-    int32_t top;        // first free stack entry above this frame's list
-    int32_t nL;         // |L| of the nodes below this frame
-    uint64_t sL;        // sum of the L-side hash terms of L
-    uint64_t fw;        // sum over S of (2 + deg v), byte tally only
-    uint64_t R[W];      // R as a mask over the positions of N(x_root)
+__device__ __forceinline__ uint32_t align2(uint32_t x) { return (x + 1u) & ~1u; }
+
+// ------------------------------------------------------------------------------ frames
+
+// Registers of the frame a wave is working on; saved whole in the header array on descent.
+struct FrameState {
+    uint32_t off;    // 32-bit-word offset of the frame's data in the wave stack, or kShared
+    uint32_t top;    // first free stack word above this frame
+    int32_t n;       // list length
+    int32_t nq;      // positions [0, nq) are the node's Q; candidates are [nq, n)
+    int32_t level;   // search depth of the candidates taken from this list (top level = 1)
+    int32_t nL;      // |L| of the nodes below
+    int32_t wf;      // mask words per entry
+    int32_t narrow;  // 1: bits are compressed positions of R, mapped by orig[] to N(x) positions
+    int32_t chunk;   // base position of the current 64-candidate chunk
+    int32_t pad;
+    uint64_t heavy;  // lanes of the current chunk still to be handled one by one
+    uint64_t sL;     // sum of the L-side hash terms of L
+    uint64_t fw;     // sum over the list of (2 + deg v), byte tally only
 };
 
-template <int W>
+// Word layout of a frame's data starting at a 2-aligned offset o:
+//   ids[n] | masks[n][wf] (u64) | first[64wf] | cnt[64wf] | H[64wf] (u64) | ptr[64wf+1] |
+//   orig[64] | post[...]
+struct FrameView {
+    const uint32_t *ids;
+    const uint64_t *masks;
+    uint32_t *first;
+    uint32_t *cnt;
+    uint64_t *H;
+    uint32_t *ptr;
+    uint32_t *orig;
+    uint32_t *post;
+};
+
+__device__ __forceinline__ uint32_t frame_words_fixed(int n, int wf) {
+    const uint32_t bits = 64u * (uint32_t)wf;
+    uint32_t o = align2((uint32_t)n);
+    o += 2u * (uint32_t)n * (uint32_t)wf;
+    o += 2u * bits;  // first, cnt
+    o = align2(o);
+    o += 2u * bits;        // H
+    o += bits + 1u + 64u;  // ptr, orig
+    return o;
+}
+
+__device__ __forceinline__ FrameView frame_view(uint32_t *base, int n, int wf) {
+    const uint32_t bits = 64u * (uint32_t)wf;
+    FrameView v;
+    v.ids = base;
+    uint32_t o = align2((uint32_t)n);
+    v.masks = reinterpret_cast<const uint64_t *>(base + o);
+    o += 2u * (uint32_t)n * (uint32_t)wf;
+    v.first = base + o;
+    o += bits;
+    v.cnt = base + o;
+    o += bits;
+    o = align2(o);
+    v.H = reinterpret_cast<uint64_t *>(base + o);
+    o += 2u * bits;
+    v.ptr = base + o;
+    o += bits + 1u;
+    v.orig = base + o;
+    o += 64u;
+    v.post = base + o;
+    return v;
+}
+
 struct Ctx {
-    const uint64_t *M;    // universe masks
-    const int32_t *gid;   // universe global ids
-    const uint64_t *hvl;  // R-side hash term per local other-side vertex
-    const uint32_t *degl; // degree per local other-side vertex
-    const int32_t *row;   // N(x_root) global ids
+    const int32_t *gid;    // universe global ids
+    const uint64_t *M;     // universe masks (records only)
+    const uint64_t *hvl;   // R-side hash term per position of N(x_root)
+    const uint32_t *degl;  // degree per position of N(x_root)
+    const int32_t *row;    // N(x_root)
     const int32_t *c_off;
-    int32_t x_root, s0, c_is_v;
-    uint32_t *tv, *tc;    // per-wave staging for P'
-    uint32_t *hist;       // per-wave LDS histogram (64*W bins)
+    uint32_t *s1;                     // the workgroup's top-level list frame
+    uint32_t *stk;                    // this wave's stack
+    uint32_t *stq, *stp, *stc, *cur;  // this wave's staging
+    uint32_t *hist;                   // this wave's LDS histogram
+    int64_t scap;
+    int32_t x_root, s0, c_is_v, Wroot;
+    int32_t cbase, obase;  // first packed id of the current graph's candidate / other side
     // records
     int32_t *rec;
     unsigned long long rec_cap, rec_offs_cap;
@@ -108,36 +197,41 @@ struct Ctx {
     unsigned int *flags;
 };
 
-struct WaveAcc {
+struct WaveAcc {  // per-lane partial tallies, summed over the wave at the end
     uint64_t count, hash, out_ints, nodes, nonmax, bytes;
     uint32_t max_depth;
 };
 
-__device__ __forceinline__ uint64_t hash_L(int c_is_v, int32_t v) { return c_is_v ? hash_v(v) : hash_u(v); }
-__device__ __forceinline__ uint64_t pair_hash(int c_is_v, uint64_t sL, uint64_t sR) {
-    // h(A, B) = mix(sum hu(A) + mix(sum hv(B) + K)); A is the U side.
-    return c_is_v ? mix64(sR + mix64(sL + kHashK)) : mix64(sL + mix64(sR + kHashK));
+// Hash terms use the graph's own ids (packed id minus the graph's base).
+__device__ __forceinline__ uint64_t hl(const Ctx &c, int32_t v) {
+    return c.c_is_v ? hash_v(v - c.cbase) : hash_u(v - c.cbase);
+}
+__device__ __forceinline__ uint64_t hr(const Ctx &c, int32_t w) {
+    return c.c_is_v ? hash_u(w - c.obase) : hash_v(w - c.obase);
 }
 
-template <int W>
-__device__ __forceinline__ int masked_count(const uint64_t *m, const uint64_t (&R)[W]) {
-    int c = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) c += __popcll(m[w] & R[w]);
-    return c;
+__device__ __forceinline__ uint32_t *frame_base(const Ctx &c, uint32_t off) { return off == kShared ? c.s1 : c.stk + off; }
+
+__device__ __forceinline__ uint32_t root_pos(const FrameState &F, const FrameView &v, uint32_t b) {
+    return F.narrow ? v.orig[b] : b;
+}
+__device__ __forceinline__ uint64_t deg_of(const Ctx &c, uint32_t li) {
+    const int32_t g = c.gid[li];
+    return (uint64_t)(c.c_off[g + 1] - c.c_off[g]);
 }
 
-// Stable counting sort by key of n staged (id, key) pairs into out[0, n); keys in [1, nbins).
-// One wave; hist is this wave's LDS histogram.
-__device__ void wave_sort_by_key(const uint32_t *tv, const uint32_t *tc, int n, int nbins,
-                                 uint32_t *hist, uint32_t *out) {
+// Stable counting sort of n staged (parent position, key) pairs by key (keys in [1, nbins));
+// sorted slot s receives parent position p through put(s, p).  One wave.
+template <typename Put>
+__device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, int n, int nbins, uint32_t *hist,
+                                 Put put) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     for (int b = ln; b < nbins; b += 64) hist[b] = 0;
     __builtin_amdgcn_wave_barrier();
     for (int base = 0; base < n; base += 64) {
         const int j = base + ln;
-        if (j < n) atomicAdd(&hist[tc[j]], 1u);
+        if (j < n) atomicAdd(&hist[key_of[j]], 1u);
     }
     __builtin_amdgcn_wave_barrier();
     int carry = 0;
@@ -153,8 +247,8 @@ __device__ void wave_sort_by_key(const uint32_t *tv, const uint32_t *tc, int n, 
     for (int base = 0; base < n; base += 64) {
         const int j = base + ln;
         const bool act = j < n;
-        const uint32_t key = act ? tc[j] : 0u;
-        const uint32_t v = act ? tv[j] : 0u;
+        const uint32_t key = act ? key_of[j] : 0u;
+        const uint32_t p = act ? src[j] : 0u;
         uint64_t same = __ballot(act);
         for (int bit = 0; bit < nbits; ++bit) {
             const bool on = (key >> bit) & 1u;
@@ -165,19 +259,75 @@ __device__ void wave_sort_by_key(const uint32_t *tv, const uint32_t *tc, int n, 
         if (act) start = hist[key];
         __builtin_amdgcn_wave_barrier();
         if (act) {
-            out[start + __popcll(same & below)] = v;
-            // the highest lane of each equal-key group advances the bin
+            put(start + (uint32_t)__popcll(same & below), p);
             if ((same >> ln) == 1ull) hist[key] = start + (uint32_t)__popcll(same);
         }
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Write one record [|A|, |B|, A..., B...] for the maximal biclique (L', R') of the current
-// node: L' = {x_root} u {universe v : M[v] contains R'} (every vertex adjacent to all of
-// R'), R' = the positions set in R.  Sides are sorted later by the canonicaliser.
-template <int W>
-__device__ void write_record(const Ctx<W> &c, const uint64_t (&R)[W], int nL, int r) {
+// Build the per-bit tables of a frame whose ids and masks are in place.  cursor: 64*WF
+// scratch words.  One wave.
+template <int WF>
+__device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *cursor) {
+    constexpr int bits = 64 * WF;
+    const int ln = lane_id();
+    for (int b = ln; b < bits; b += 64) {
+        v.first[b] = kNone;
+        v.cnt[b] = 0u;
+        v.H[b] = 0ull;
+    }
+    __threadfence_block();
+    for (int base = 0; base < n; base += 64) {
+        const int k = base + ln;
+        if (k < n) {
+            const uint64_t h = hl(c, c.gid[v.ids[k]]);
+#pragma unroll
+            for (int w = 0; w < WF; ++w) {
+                uint64_t m = v.masks[(size_t)k * WF + w];
+                while (m) {
+                    const int b = 64 * w + __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1ull;
+                    atomicMin(&v.first[b], (uint32_t)k);
+                    atomicAdd(&v.cnt[b], 1u);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&v.H[b]), (unsigned long long)h);
+                }
+            }
+        }
+    }
+    __threadfence_block();
+    int carry = 0;
+    for (int base = 0; base < bits; base += 64) {
+        const int b = base + ln;
+        const int h = (int)v.cnt[b];
+        const int incl = wave_incl_scan(h);
+        v.ptr[b] = (uint32_t)(carry + incl - h);
+        cursor[b] = (uint32_t)(carry + incl - h);
+        carry += __shfl(incl, 63);
+    }
+    if (ln == 0) v.ptr[bits] = (uint32_t)carry;
+    __threadfence_block();
+    for (int base = 0; base < n; base += 64) {
+        const int k = base + ln;
+        if (k < n) {
+#pragma unroll
+            for (int w = 0; w < WF; ++w) {
+                uint64_t m = v.masks[(size_t)k * WF + w];
+                while (m) {
+                    const int b = 64 * w + __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1ull;
+                    v.post[atomicAdd(&cursor[b], 1u)] = (uint32_t)k;
+                }
+            }
+        }
+    }
+    __threadfence_block();
+}
+
+// Write the record of the maximal biclique (L', R') of a node.  R' is given as positions of
+// N(x_root) (Rr, Wroot words).  L' = {x_root} u {universe v : M[v] contains R'}: every vertex
+// adjacent to all of R'.  Sides are sorted later by the canonicaliser.
+__device__ void write_record(const Ctx &c, const uint64_t *Rr, int nL, int r) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     const unsigned long long len = 2ull + (unsigned long long)nL + (unsigned long long)r;
@@ -193,160 +343,292 @@ __device__ void write_record(const Ctx<W> &c, const uint64_t (&R)[W], int nL, in
         return;
     }
     int32_t *o = c.rec + off;
-    const int la = c.c_is_v ? r : nL;  // |A|
     int32_t *pl = o + 2 + (c.c_is_v ? r : 0);   // where L' goes
     int32_t *pr = o + 2 + (c.c_is_v ? 0 : nL);  // where R' goes
     if (ln == 0) {
-        o[0] = la;
+        o[0] = c.c_is_v ? r : nL;
         o[1] = c.c_is_v ? nL : r;
         c.rec_offs[idx] = off;
-        pl[0] = c.x_root;
+        pl[0] = c.x_root - c.cbase;
     }
     int k = 1;
     for (int base = 0; base < c.s0; base += 64) {
         const int li = base + ln;
         bool in = li < c.s0;
         if (in) {
-            const uint64_t *m = c.M + (size_t)li * W;
-#pragma unroll
-            for (int w = 0; w < W; ++w) in = in && ((m[w] & R[w]) == R[w]);
+            const uint64_t *m = c.M + (size_t)li * c.Wroot;
+            for (int w = 0; w < c.Wroot; ++w) in = in && ((m[w] & Rr[w]) == Rr[w]);
         }
         const uint64_t b = __ballot(in);
         const int at = k + __popcll(b & below);
-        if (in && at < nL) pl[at] = c.gid[li];  // never past the reserved record
+        if (in && at < nL) pl[at] = c.gid[li] - c.cbase;  // never past the reserved record
         k += __popcll(b);
     }
     int q = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-        const bool in = (R[w] >> ln) & 1ull;
+    for (int w = 0; w < c.Wroot; ++w) {
+        const bool in = (Rr[w] >> ln) & 1ull;
         const uint64_t b = __ballot(in);
         const int at = q + __popcll(b & below);
-        if (in && at < r) pr[at] = c.row[w * 64 + ln];
+        if (in && at < r) pr[at] = c.row[w * 64 + ln] - c.obase;
         q += __popcll(b);
     }
 }
 
-// One node: candidate S[i] of frame F.  Returns true when a child frame was written to C
-// (C.S must point at free stack space of at least F.n - 1 entries).
-template <int W, bool DIAG, bool ENUM>
-__device__ bool process_node(const Ctx<W> &c, const Frame<W> &F, int i, Frame<W> &C, WaveAcc &acc) {
+// Candidates [base, base+64) of frame F: lanes with |R'| = 1 are settled here; the rest are
+// returned as a lane mask.
+template <int WF, bool DIAG, bool ENUM>
+__device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameView &v, int base, WaveAcc &acc) {
     const int ln = lane_id();
-    const uint64_t below = lanes_below();
-    const uint32_t x = F.S[i];
-    const uint64_t *mx = c.M + (size_t)x * W;
-    uint64_t R[W];
+    const int i = base + ln;
+    const bool act = i < F.n;
+    uint64_t m[WF];
     int r = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        R[w] = F.R[w] & mx[w];  // R' = R n N(x)
-        r += __popcll(R[w]);
+    for (int w = 0; w < WF; ++w) {
+        m[w] = act ? v.masks[(size_t)i * WF + w] : 0ull;
+        r += __popcll(m[w]);
     }
-    uint32_t *cs = const_cast<uint32_t *>(C.S);
+    if (ENUM) return __ballot(act);
+    const bool light = act && r == 1;
+    if (light) {
+        int b = 0;
+#pragma unroll
+        for (int w = 0; w < WF; ++w)
+            if (m[w]) b = 64 * w + __ffsll((unsigned long long)m[w]) - 1;
+        const bool maximal = v.first[b] == (uint32_t)i;  // no earlier entry holds bit b
+        const uint32_t rp = root_pos(F, v, (uint32_t)b);
+        if (maximal) {
+            // L' = L u {every entry with bit b}: all of them sit at positions >= i
+            const uint64_t sL = F.sL + v.H[b];
+            acc.count += 1;
+            acc.hash += pair_hash(c.c_is_v, sL, c.hvl[rp]);
+            acc.out_ints += 2ull + (uint64_t)F.nL + (uint64_t)v.cnt[b] + 1ull;
+        }
+        if (DIAG) {
+            acc.nodes += 1;
+            if (!maximal) acc.nonmax += 1;
+            if ((uint32_t)F.level > acc.max_depth) acc.max_depth = (uint32_t)F.level;
+            const uint64_t dx = deg_of(c, v.ids[i]);
+            const uint64_t rs = 2ull + (uint64_t)c.degl[rp];
+            const uint64_t fw = F.fw - (2ull + dx);
+            acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + 1ull);
+        }
+    }
+    return __ballot(act && r >= 2);
+}
 
-    // maximality check against Q = S[0, i): a vertex adjacent to all of R' ends the node
-    int qn = 0;
+// The candidate at position i of frame F, |R'| = r >= 1, handled by the whole wave.
+// Returns true when a child frame was written (its state in C).
+template <int WF, int W, bool DIAG, bool ENUM>
+__device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v, int i, FrameState &C,
+                           WaveAcc &acc) {
+    const int ln = lane_id();
+    const uint64_t below = lanes_below();
+    uint64_t m[WF];
+    int r = 0;
+#pragma unroll
+    for (int w = 0; w < WF; ++w) {
+        m[w] = v.masks[(size_t)i * WF + w];  // R' (uniform)
+        r += __popcll(m[w]);
+    }
+
+    // maximality: an earlier entry holding every bit of R' ends the node.  If some bit of R'
+    // first appears at i itself, nothing earlier can hold R'.
+    bool first_here = false;
+    uint32_t best = 0xFFFFFFFFu;  // (count << 12 | bit) of the rarest bit
+#pragma unroll
+    for (int w = 0; w < WF; ++w) {
+        if ((m[w] >> ln) & 1ull) {
+            const int b = 64 * w + ln;
+            if (v.first[b] == (uint32_t)i) first_here = true;
+            const uint32_t cb = v.cnt[b] < 0xFFFFFu ? v.cnt[b] : 0xFFFFFu;  // saturate: b stays exact
+            const uint32_t key = (cb << 12) | (uint32_t)b;
+            best = key < best ? key : best;
+        }
+    }
     bool nonmax = false;
-    uint64_t fwq = 0;
-    for (int base = 0; base < i; base += 64) {
-        const int j = base + ln;
-        const bool act = j < i;
-        uint32_t v = 0;
-        int cnt = 0;
-        if (act) {
-            v = F.S[j];
-            cnt = masked_count<W>(c.M + (size_t)v * W, R);
+    if (!__ballot(first_here)) {
+        best = wave_min_u32(best);
+        const uint32_t b = best & 0xFFFu;
+        const uint32_t p0 = v.ptr[b], p1 = v.ptr[b + 1];
+        for (uint32_t q = p0; q < p1; q += 64) {
+            const uint32_t qq = q + (uint32_t)ln;
+            bool viol = false;
+            if (qq < p1) {
+                const uint32_t p = v.post[qq];
+                if (p < (uint32_t)i) {
+                    viol = true;
+#pragma unroll
+                    for (int w = 0; w < WF; ++w) viol = viol && ((v.masks[(size_t)p * WF + w] & m[w]) == m[w]);
+                }
+            }
+            if (__ballot(viol)) {
+                nonmax = true;
+                break;
+            }
         }
-        if (__ballot(act && cnt == r)) {
-            nonmax = true;
-            break;
-        }
-        const bool keep = act && cnt > 0;
-        const uint64_t kb = __ballot(keep);
-        if (keep) {
-            cs[qn + __popcll(kb & below)] = v;
-            if (DIAG) fwq += 2ull + (uint64_t)(c.c_off[c.gid[v] + 1] - c.c_off[c.gid[v]]);
-        }
-        qn += __popcll(kb);
     }
 
-    uint64_t degx = 0, rs = 0;
+    uint64_t dx = 0, rs = 0;
     if (DIAG) {
-        acc.nodes += 1;
-        if ((uint32_t)F.level > acc.max_depth) acc.max_depth = (uint32_t)F.level;
-        degx = (uint64_t)(c.c_off[c.gid[x] + 1] - c.c_off[c.gid[x]]);
+        dx = deg_of(c, v.ids[i]);
         uint64_t t = 0;
 #pragma unroll
-        for (int w = 0; w < W; ++w)
-            if ((R[w] >> ln) & 1ull) t += 2ull + (uint64_t)c.degl[w * 64 + ln];
+        for (int w = 0; w < WF; ++w)
+            if ((m[w] >> ln) & 1ull) t += 2ull + (uint64_t)c.degl[root_pos(F, v, (uint32_t)(64 * w + ln))];
         rs = wave_sum_u64(t);
+        if (ln == 0) {
+            acc.nodes += 1;
+            if ((uint32_t)F.level > acc.max_depth) acc.max_depth = (uint32_t)F.level;
+        }
     }
     if (nonmax) {
-        if (DIAG) {
+        if (DIAG && ln == 0) {
             acc.nonmax += 1;
-            const uint64_t fw = F.fw - (2ull + degx);
-            acc.bytes += 4ull * ((2ull + degx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r);
+            const uint64_t fw = F.fw - (2ull + dx);
+            acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r);
         }
         return false;
     }
 
-    // expansion over P = S(i, n): adjacent to all of R' joins L', partially adjacent joins P'
-    int pn = 0, ne = 0;
-    uint64_t exps = 0, fwp = 0;
-    for (int base = i + 1; base < F.n; base += 64) {
-        const int j = base + ln;
-        const bool act = j < F.n;
-        uint32_t v = 0;
+    // maximal: one pass over the list counts every entry against R'
+    int qn = 0, pn = 0, ne = 0;
+    uint64_t exps = 0, fwc = 0;
+    uint32_t csum = 0;
+    for (int base = 0; base < F.n; base += 64) {
+        const int k = base + ln;
+        const bool act = k < F.n && k != i;
         int cnt = 0;
         if (act) {
-            v = F.S[j];
-            cnt = masked_count<W>(c.M + (size_t)v * W, R);
+#pragma unroll
+            for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
         }
-        const bool full = act && cnt == r;
-        if (full) exps += hash_L(c.c_is_v, c.gid[v]);
+        const bool inq = act && k < i && cnt > 0;  // cnt < r: the node passed the check
+        const bool full = act && k > i && cnt == r;
+        const bool inp = act && k > i && cnt > 0 && cnt < r;
+        if (full) exps += hl(c, c.gid[v.ids[k]]);
         ne += __popcll(__ballot(full));
-        const bool pk = act && cnt > 0 && cnt < r;
-        const uint64_t pb = __ballot(pk);
-        if (pk) {
+        const uint64_t qb = __ballot(inq), pb = __ballot(inp);
+        if (inq) c.stq[qn + __popcll(qb & below)] = (uint32_t)k;
+        if (inp) {
             const int p = pn + __popcll(pb & below);
-            c.tv[p] = v;
-            c.tc[p] = (uint32_t)cnt;
-            if (DIAG) fwp += 2ull + (uint64_t)(c.c_off[c.gid[v] + 1] - c.c_off[c.gid[v]]);
+            c.stp[p] = (uint32_t)k;
+            c.stc[p] = (uint32_t)cnt;
         }
+        if (inq || inp) {
+            csum += (uint32_t)cnt;
+            if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
+        }
+        qn += __popcll(qb);
         pn += __popcll(pb);
     }
 
     // report (L', R')
-    const uint64_t sL = F.sL + hash_L(c.c_is_v, c.gid[x]) + wave_sum_u64(exps);
+    const uint64_t sL = F.sL + hl(c, c.gid[v.ids[i]]) + wave_sum_u64(exps);
     uint64_t sr = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w)
-        if ((R[w] >> ln) & 1ull) sr += c.hvl[w * 64 + ln];
+    for (int w = 0; w < WF; ++w)
+        if ((m[w] >> ln) & 1ull) sr += c.hvl[root_pos(F, v, (uint32_t)(64 * w + ln))];
     sr = wave_sum_u64(sr);
     const int nL = F.nL + 1 + ne;
-    acc.count += 1;
-    acc.hash += pair_hash(c.c_is_v, sL, sr);
-    acc.out_ints += 2ull + (uint64_t)nL + (uint64_t)r;
-    if (ENUM) write_record<W>(c, R, nL, r);
-    if (DIAG) {
-        const uint64_t fw = F.fw - (2ull + degx);
-        acc.bytes += 4ull * ((2ull + degx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r +
-                             (uint64_t)pn + (uint64_t)qn);
+    if (ln == 0) {
+        acc.count += 1;
+        acc.hash += pair_hash(c.c_is_v, sL, sr);
+        acc.out_ints += 2ull + (uint64_t)nL + (uint64_t)r;
+    }
+    if (ENUM) {
+        uint64_t Rr[16];
+        for (int w = 0; w < 16; ++w) Rr[w] = 0ull;
+#pragma unroll
+        for (int w = 0; w < WF; ++w) {
+            uint64_t mm = m[w];
+            while (mm) {
+                const int b = 64 * w + __ffsll((unsigned long long)mm) - 1;
+                mm &= mm - 1ull;
+                const uint32_t rp = root_pos(F, v, (uint32_t)b);
+                Rr[rp >> 6] |= 1ull << (rp & 63);
+            }
+        }
+        write_record(c, Rr, nL, r);
+    }
+    if (DIAG && ln == 0) {
+        const uint64_t fw = F.fw - (2ull + dx);
+        acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r + (uint64_t)pn +
+                             (uint64_t)qn);
     }
     if (pn == 0) return false;
 
-    wave_sort_by_key(c.tv, c.tc, pn, r, c.hist, cs + qn);
+    // child frame: Q' then P' stably sorted by count; masks restricted to R' and, when
+    // |R'| <= 64, compressed to |R'| bits
+    const int n2 = qn + pn;
+    const bool narrow = (W == 1) || r <= 64;
+    const int wf2 = narrow ? 1 : W;
+    const uint32_t post2 = (uint32_t)wave_sum_i32((int)csum);
+    const uint32_t off2 = F.top;
+    const uint32_t top2 = align2(off2 + frame_words_fixed(n2, wf2) + post2);
+    if ((int64_t)top2 > c.scap) {
+        if (ln == 0) atomicOr(c.flags, (unsigned int)FLAG_STACK_OVERFLOW);
+        return false;
+    }
+    uint32_t *cb = c.stk + off2;
+    uint32_t *ids2 = cb;
+    uint64_t *masks2 = reinterpret_cast<uint64_t *>(cb + align2((uint32_t)n2));
+    FrameView v2 = frame_view(cb, n2, wf2);
+    if (narrow) {
+        // orig2[t] = N(x_root) position of the t-th bit of R'
+        int t0 = 0;
+#pragma unroll
+        for (int w = 0; w < WF; ++w) {
+            const bool on = (m[w] >> ln) & 1ull;
+            const uint64_t bb = __ballot(on);
+            if (on) v2.orig[t0 + __popcll(bb & below)] = root_pos(F, v, (uint32_t)(64 * w + ln));
+            t0 += __popcll(bb);
+        }
+    }
+    auto put = [&](uint32_t slot, uint32_t k) {
+        ids2[slot] = v.ids[k];
+        if (narrow) {
+            uint64_t out = 0;
+            int t = 0;
+#pragma unroll
+            for (int w = 0; w < WF; ++w) {
+                uint64_t mm = m[w];
+                const uint64_t xx = v.masks[(size_t)k * WF + w];
+                while (mm) {  // the same trip count on every lane: m is uniform
+                    const int p = __ffsll((unsigned long long)mm) - 1;
+                    mm &= mm - 1ull;
+                    out |= ((xx >> p) & 1ull) << t;
+                    ++t;
+                }
+            }
+            masks2[slot] = out;
+        } else {
+#pragma unroll
+            for (int w = 0; w < WF; ++w) masks2[(size_t)slot * W + w] = v.masks[(size_t)k * WF + w] & m[w];
+        }
+    };
+    for (int base = 0; base < qn; base += 64) {
+        const int j = base + ln;
+        if (j < qn) put((uint32_t)j, c.stq[j]);
+    }
+    wave_sort_by_key(c.stp, c.stc, pn, r, c.hist, [&](uint32_t slot, uint32_t k) { put((uint32_t)qn + slot, k); });
     __threadfence_block();
-    C.n = qn + pn;
+    if (narrow) build_tables<1>(c, v2, n2, c.cur);
+    else build_tables<W>(c, v2, n2, c.cur);
+
+    C.off = off2;
+    C.top = top2;
+    C.n = n2;
     C.nq = qn;
-    C.pos = qn;
-    C.end = qn + pn;
     C.level = F.level + 1;
     C.nL = nL;
+    C.wf = wf2;
+    C.narrow = narrow ? 1 : 0;
+    C.chunk = qn - 64;
+    C.pad = 0;
+    C.heavy = 0ull;
     C.sL = sL;
-    C.fw = DIAG ? wave_sum_u64(fwq + fwp) : 0ull;
-#pragma unroll
-    for (int w = 0; w < W; ++w) C.R[w] = R[w];
+    C.fw = DIAG ? wave_sum_u64(fwc) : 0ull;
     return true;
 }
 
@@ -360,13 +642,46 @@ struct WGShared {
     unsigned long long fw1;
     unsigned long long hvsum;
     unsigned long long rs1;
+    unsigned long long post1;
     int nexp;
-    int pad;
-    int scan[16];  // per-wave partial sums for the block scan
+    int graph;  // graph whose tallies the workgroup is holding
+    int scan[16];
+    unsigned long long red[8];  // per-graph tally reduction
 };
 
-// Block-wide exclusive prefix of popcounts over nwords bitmap words into bpre; returns total
-// through sh->s0.  All threads must call it.
+// Add the workgroup's tallies to a graph's accumulators and clear them.  All threads call.
+template <bool DIAG>
+__device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) {
+    const int ln = lane_id();
+    uint64_t v[7];
+    v[0] = wave_sum_u64(acc.count);
+    v[1] = wave_sum_u64(acc.hash);
+    v[2] = wave_sum_u64(acc.out_ints);
+    v[3] = DIAG ? wave_sum_u64(acc.nodes) : 0ull;
+    v[4] = DIAG ? wave_sum_u64(acc.nonmax) : 0ull;
+    v[5] = DIAG ? wave_sum_u64(acc.bytes) : 0ull;
+    v[6] = DIAG ? (uint64_t)wave_max_u32(acc.max_depth) : 0ull;
+    if (ln == 0) {
+        for (int q = 0; q < 6; ++q)
+            if (v[q]) atomicAdd(&sh->red[q], (unsigned long long)v[q]);
+        if (v[6]) atomicMax(&sh->red[6], (unsigned long long)v[6]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int slot[6] = {ACC_COUNT, ACC_HASH, ACC_OUT_INTS, ACC_NODES, ACC_NONMAX, ACC_BYTES};
+        for (int q = 0; q < 6; ++q) {
+            if (sh->red[q]) atomicAdd(&gacc[slot[q]], sh->red[q]);
+            sh->red[q] = 0ull;
+        }
+        if (sh->red[6]) atomicMax(&gacc[ACC_MAX_DEPTH], sh->red[6]);
+        sh->red[6] = 0ull;
+    }
+    __syncthreads();
+    acc = WaveAcc{0, 0, 0, 0, 0, 0, 0};
+}
+
+// Block-wide exclusive prefix of popcounts over nwords bitmap words into bpre; total in
+// sh->s0.  All threads call it.
 __device__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, int nwords, WGShared *sh) {
     const int tid = threadIdx.x, nt = blockDim.x, wid = tid >> 6, nw = nt >> 6;
     const int per = (nwords + nt - 1) / nt;
@@ -397,12 +712,11 @@ __device__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, in
 }
 
 template <int W, bool DIAG, bool ENUM>
-__global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, int64_t hi,
-                                                      unsigned int *counter) {
+__global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
     extern __shared__ unsigned char lds_raw[];
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
     const int tid = threadIdx.x, nt = blockDim.x, wid = tid >> 6, nw = nt >> 6, ln = lane_id();
-    uint32_t *hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * (64 * W);
+    constexpr int BITS = 64 * W;
 
     char *wg = a.arena + (size_t)blockIdx.x * a.lay.wg_bytes;
     uint64_t *bitmap = reinterpret_cast<uint64_t *>(wg + a.lay.off_bitmap);
@@ -412,23 +726,31 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     uint32_t *cnt1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_cnt);
     uint64_t *hvl = reinterpret_cast<uint64_t *>(wg + a.lay.off_hv);
     uint32_t *degl = reinterpret_cast<uint32_t *>(wg + a.lay.off_deg);
-    uint32_t *S1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_S1);
     uint32_t *t1v = reinterpret_cast<uint32_t *>(wg + a.lay.off_t1v);
     uint32_t *t1c = reinterpret_cast<uint32_t *>(wg + a.lay.off_t1c);
+    uint32_t *cur1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_cur1);
+    uint32_t *s1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_S1);
     char *wv = wg + a.lay.off_waves + (size_t)wid * a.lay.wave_bytes;
-    uint32_t *stk = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_stack);
-    Frame<W> *hdr = reinterpret_cast<Frame<W> *>(wv + a.lay.off_w_hdr);
+    FrameState *hdr = reinterpret_cast<FrameState *>(wv + a.lay.off_w_hdr);
 
-    Ctx<W> c;
-    c.M = M;
+    Ctx c;
     c.gid = gid;
+    c.M = M;
     c.hvl = hvl;
     c.degl = degl;
     c.c_off = a.c_off;
-    c.c_is_v = a.c_is_v;
-    c.tv = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_tv);
-    c.tc = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_tc);
-    c.hist = hist;
+    c.s1 = s1;
+    c.stk = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_stack);
+    c.stq = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_q);
+    c.stp = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_p);
+    c.stc = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_c);
+    c.cur = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_cur);
+    c.hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * BITS;
+    c.scap = a.dims.scap;
+    c.c_is_v = 0;
+    c.cbase = 0;
+    c.obase = 0;
+    c.Wroot = W;
     c.rec = a.rec;
     c.rec_cap = a.rec_cap;
     c.rec_offs = a.rec_offs;
@@ -438,19 +760,42 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
 
     WaveAcc acc = {0, 0, 0, 0, 0, 0, 0};
     bool aborted = false;
+    const int ucap = a.dims.ucap;
+    if (tid < 8) sh->red[tid] = 0ull;
+    if (tid == 0) sh->graph = -1;
+    __syncthreads();
 
     for (;;) {
         if (tid == 0) {
-            // stop claiming once any wave has run out of stack: the host reruns with more
+            // stop claiming once a capacity ran out: the host reruns with more room
             const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sh->task = (f & (FLAG_STACK_OVERFLOW | FLAG_DEPTH_OVERFLOW)) ? (1ull << 62)
-                                                                          : (unsigned long long)atomicAdd(counter, 1u);
+            sh->task = (f & FLAG_RERUN) ? (1ull << 62) : (unsigned long long)atomicAdd(counter, 1u);
         }
         __syncthreads();
         const int64_t t = (int64_t)sh->task;
         if (lo + t >= hi) break;
-        const int64_t k = hi - 1 - t;  // ranks are claimed from the top (largest degree) down
-        const int32_t x = a.order[k];
+        int g = 0;
+        int64_t k;
+        if (a.tasks) {
+            const unsigned long long tk = a.tasks[lo + t];
+            g = (int)(tk >> 32);
+            k = (int64_t)(tk & 0xFFFFFFFFull);
+        } else {
+            k = hi - 1 - t;  // ranks are claimed from the top (largest degree) down
+        }
+        if (g != sh->graph) {
+            // tallies belong to the graph they were found in
+            if (sh->graph >= 0) flush_acc<DIAG>(acc, a.graphs[sh->graph].acc, sh);
+            __syncthreads();
+            if (tid == 0) sh->graph = g;
+            __syncthreads();
+        }
+        const GraphDesc gd = a.graphs[g];
+        c.c_is_v = gd.c_is_v;
+        c.cbase = gd.cbase;
+        c.obase = gd.obase;
+        const int nwords = gd.nwords;
+        const int32_t x = gd.order[k];
         const int32_t rb = a.c_off[x];
         const int32_t d = a.c_off[x + 1] - rb;
         const int32_t *row = a.c_adj + rb;
@@ -470,14 +815,19 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             }
         }
         uint64_t hv_local = 0, rs_local = 0;
-        for (int j = tid; j < d; j += nt) {
-            const int32_t w = row[j];
-            const uint64_t h = a.c_is_v ? hash_u(w) : hash_v(w);
-            hvl[j] = h;
-            hv_local += h;
-            const uint32_t dw = (uint32_t)(a.o_off[w + 1] - a.o_off[w]);
-            degl[j] = dw;
-            rs_local += 2ull + dw;
+        for (int j = tid; j < BITS; j += nt) {
+            if (j < d) {
+                const int32_t w = row[j];
+                const uint64_t h = hr(c, w);
+                hvl[j] = h;
+                hv_local += h;
+                const uint32_t dw = (uint32_t)(a.o_off[w + 1] - a.o_off[w]);
+                degl[j] = dw;
+                rs_local += 2ull + dw;
+            } else {
+                hvl[j] = 0ull;
+                degl[j] = 0u;
+            }
         }
         if (tid == 0) {
             sh->nonmax = 0;
@@ -486,6 +836,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             sh->fw1 = 0;
             sh->hvsum = 0;
             sh->rs1 = 0;
+            sh->post1 = 0;
             sh->nexp = 0;
             sh->claim = 0;
         }
@@ -499,19 +850,29 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         }
 
         // -- universe numbering: prefix of bitmap popcounts (rank order)
-        block_popcount_prefix(bitmap, bpre, a.nwords, sh);
+        block_popcount_prefix(bitmap, bpre, nwords, sh);
         __threadfence_block();
         __syncthreads();
         const int s0 = sh->s0;
+        if (s0 > ucap) {
+            // the universe does not fit: clear the bitmap, note the size, skip (rerun later)
+            for (int wd = tid; wd < nwords; wd += nt) bitmap[wd] = 0ull;
+            if (tid == 0) {
+                atomicOr(a.flags, (unsigned int)FLAG_UNIVERSE_OVERFLOW);
+                atomicMax(&a.acc[ACC_NEED_UCAP], (unsigned long long)s0);
+            }
+            __syncthreads();
+            continue;
+        }
         const int nq0 = (int)bpre[k >> 6] + __popcll(bitmap[k >> 6] & ((1ull << (k & 63)) - 1ull));
         c.s0 = s0;
-        for (int wd = tid; wd < a.nwords; wd += nt) {
+        for (int wd = tid; wd < nwords; wd += nt) {
             uint64_t bits = bitmap[wd];
             uint32_t pos = bpre[wd];
             while (bits) {
                 const int b = __ffsll((unsigned long long)bits) - 1;
                 bits &= bits - 1ull;
-                gid[pos++] = a.order[wd * 64 + b];
+                gid[pos++] = gd.order[wd * 64 + b];
             }
         }
         for (size_t q = tid; q < (size_t)s0 * W; q += nt) M[q] = 0ull;
@@ -526,7 +887,8 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 const int32_t v = a.o_adj[p];
                 if (v != x) {
                     const int32_t rk = a.rank[v];
-                    const uint32_t li = bpre[rk >> 6] + (uint32_t)__popcll(bitmap[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
+                    const uint32_t li =
+                        bpre[rk >> 6] + (uint32_t)__popcll(bitmap[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
                     atomicOr(reinterpret_cast<unsigned long long *>(&M[(size_t)li * W + (j >> 6)]), 1ull << (j & 63));
                 }
             }
@@ -535,11 +897,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         __syncthreads();
 
         // -- the top-level node for x: counts, maximality against earlier ranks, expansion
-        for (int wd = tid; wd < a.nwords; wd += nt) bitmap[wd] = 0ull;
+        for (int wd = tid; wd < nwords; wd += nt) bitmap[wd] = 0ull;
         {
             bool nm = false;
             int pc = 0, nexp = 0;
-            uint64_t ex = 0, fw = 0;
+            uint64_t ex = 0, fw = 0, post = 0;
             for (int li = tid; li < s0; li += nt) {
                 int cc = 0;
 #pragma unroll
@@ -548,70 +910,87 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 const int32_t g = gid[li];
                 const uint64_t dg = DIAG ? 2ull + (uint64_t)(a.c_off[g + 1] - a.c_off[g]) : 0ull;
                 if (li < nq0) {
-                    if (cc == d) nm = true;
-                    else fw += dg;
+                    if (cc == d) {
+                        nm = true;
+                    } else {
+                        fw += dg;
+                        post += (uint64_t)cc;
+                    }
                 } else if (cc == d) {
-                    ex += hash_L(a.c_is_v, g);
+                    ex += hl(c, g);
                     ++nexp;
                 } else {
                     ++pc;
                     fw += dg;
+                    post += (uint64_t)cc;
                 }
             }
             if (__ballot(nm) && ln == 0) atomicOr(&sh->nonmax, 1);
             ex = wave_sum_u64(ex);
             fw = wave_sum_u64(fw);
-            for (int o = 32; o > 0; o >>= 1) {
-                pc += __shfl_xor(pc, o);
-                nexp += __shfl_xor(nexp, o);
-            }
+            post = wave_sum_u64(post);
+            pc = wave_sum_i32(pc);
+            nexp = wave_sum_i32(nexp);
             if (ln == 0) {
                 atomicAdd(&sh->pcount, pc);
                 atomicAdd(&sh->nexp, nexp);
                 atomicAdd(reinterpret_cast<unsigned long long *>(&sh->exps), (unsigned long long)ex);
                 atomicAdd(reinterpret_cast<unsigned long long *>(&sh->fw1), (unsigned long long)fw);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&sh->post1), (unsigned long long)post);
             }
         }
         __threadfence_block();
         __syncthreads();
         const bool root_nonmax = sh->nonmax != 0;
         const int P1 = sh->pcount;
-        if (tid == 0 && !aborted) {
+        if (tid == 0) {
             const uint64_t dx = (uint64_t)d;
             if (DIAG) {
                 acc.nodes += 1;
                 if (acc.max_depth < 1) acc.max_depth = 1;
-                const uint64_t fwtop = a.total_fw - (2ull + dx);
+                const uint64_t fwtop = gd.total_fw - (2ull + dx);
                 const uint64_t rs = sh->rs1;
-                uint64_t b = (2ull + dx) + (rs < fwtop ? rs : fwtop) + (uint64_t)(a.ncand - 1) + dx;
+                uint64_t b = (2ull + dx) + (rs < fwtop ? rs : fwtop) + (uint64_t)(gd.ncand - 1) + dx;
                 if (root_nonmax) acc.nonmax += 1;
                 else b += (uint64_t)P1 + (uint64_t)nq0;
                 acc.bytes += 4ull * b;
             }
             if (!root_nonmax) {
-                const uint64_t sL = hash_L(a.c_is_v, x) + sh->exps;
+                const uint64_t sL = hl(c, x) + sh->exps;
                 const int nL = 1 + sh->nexp;
                 acc.count += 1;
-                acc.hash += pair_hash(a.c_is_v, sL, sh->hvsum);
+                acc.hash += pair_hash(c.c_is_v, sL, sh->hvsum);
                 acc.out_ints += 2ull + (uint64_t)nL + (uint64_t)d;
             }
         }
         if (ENUM && !root_nonmax && wid == 0) {
-            uint64_t R1[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
+            uint64_t R1[16];
+            for (int w = 0; w < 16; ++w) {
                 const int bits = d - 64 * w;
                 R1[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : ((1ull << bits) - 1ull));
             }
-            write_record<W>(c, R1, 1 + sh->nexp, d);
+            write_record(c, R1, 1 + sh->nexp, d);
         }
         if (root_nonmax || P1 == 0) {
             __syncthreads();
             continue;
         }
+        const int n1 = nq0 + P1;
+        const uint64_t post1 = sh->post1;
+        if ((int64_t)post1 > a.dims.post_cap) {
+            if (tid == 0) {
+                atomicOr(a.flags, (unsigned int)FLAG_UNIVERSE_OVERFLOW);
+                atomicMax(&a.acc[ACC_NEED_POST], (unsigned long long)post1);
+            }
+            __syncthreads();
+            continue;
+        }
 
-        // -- the top-level child list S1 = Q1 (earlier ranks) ++ P1 sorted by count
-        for (int li = tid; li < nq0; li += nt) S1[li] = (uint32_t)li;
+        // -- the top-level child list as a frame: ids Q1 (earlier ranks) ++ P1 sorted by
+        //    count, masks over the positions of N(x), per-bit tables
+        FrameView v1 = frame_view(s1, n1, W);
+        uint32_t *ids1 = s1;
+        for (int li = tid; li < nq0; li += nt) ids1[li] = (uint32_t)li;
         if (wid == 0) {
             int pn = 0;
             for (int base = nq0; base < s0; base += 64) {
@@ -628,88 +1007,134 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 pn += __popcll(pb);
             }
             __threadfence_block();
-            wave_sort_by_key(t1v, t1c, pn, d, hist, S1 + nq0);
+            wave_sort_by_key(t1v, t1c, pn, d, c.hist, [&](uint32_t slot, uint32_t li) { ids1[nq0 + slot] = li; });
+        }
+        for (int b = tid; b < BITS; b += nt) {
+            v1.first[b] = kNone;
+            v1.cnt[b] = 0u;
+            v1.H[b] = 0ull;
+        }
+        __threadfence_block();
+        __syncthreads();
+        uint64_t *masks1 = const_cast<uint64_t *>(v1.masks);
+        for (int j = tid; j < n1; j += nt) {
+            const uint32_t li = ids1[j];
+            const uint64_t h = hl(c, gid[li]);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                uint64_t mm = M[(size_t)li * W + w];
+                masks1[(size_t)j * W + w] = mm;
+                while (mm) {
+                    const int b = 64 * w + __ffsll((unsigned long long)mm) - 1;
+                    mm &= mm - 1ull;
+                    atomicMin(&v1.first[b], (uint32_t)j);
+                    atomicAdd(&v1.cnt[b], 1u);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&v1.H[b]), (unsigned long long)h);
+                }
+            }
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (wid == 0) {
+            int carry = 0;
+            for (int base = 0; base < BITS; base += 64) {
+                const int b = base + ln;
+                const int h = (int)v1.cnt[b];
+                const int incl = wave_incl_scan(h);
+                v1.ptr[b] = (uint32_t)(carry + incl - h);
+                cur1[b] = (uint32_t)(carry + incl - h);
+                carry += __shfl(incl, 63);
+            }
+            if (ln == 0) v1.ptr[BITS] = (uint32_t)carry;
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (int j = tid; j < n1; j += nt) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                uint64_t mm = masks1[(size_t)j * W + w];
+                while (mm) {
+                    const int b = 64 * w + __ffsll((unsigned long long)mm) - 1;
+                    mm &= mm - 1ull;
+                    v1.post[atomicAdd(&cur1[b], 1u)] = (uint32_t)j;
+                }
+            }
         }
         __threadfence_block();
         __syncthreads();
 
-        // -- second level: waves claim the top-level children, each a depth-first search
-        Frame<W> F1;
-        F1.S = S1;
-        F1.n = nq0 + P1;
-        F1.nq = nq0;
-        F1.pos = nq0;
-        F1.level = 2;
-        F1.nL = 1 + sh->nexp;
-        F1.sL = hash_L(a.c_is_v, x) + sh->exps;
-        F1.fw = sh->fw1;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            const int bits = d - 64 * w;
-            F1.R[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : ((1ull << bits) - 1ull));
-        }
-        F1.end = F1.n;
-        F1.top = 0;
+        // -- second level and below: waves claim 64-candidate chunks of the top-level list
+        //    and search depth-first from them
+        FrameState cur;
+        cur.off = kShared;
+        cur.top = 0;
+        cur.n = n1;
+        cur.nq = nq0;
+        cur.level = 2;
+        cur.nL = 1 + sh->nexp;
+        cur.wf = W;
+        cur.narrow = 0;
+        cur.chunk = 0;
+        cur.pad = 0;
+        cur.heavy = 0ull;
+        cur.sL = hl(c, x) + sh->exps;
+        cur.fw = sh->fw1;
+        int depth = 0;
         while (!aborted) {
-            int i = 0;
-            if (ln == 0) i = atomicAdd(&sh->claim, 1);
-            i = __shfl(i, 0) + nq0;
-            if (i >= F1.n) break;
-            // the claimed child is a one-candidate range of the shared top-level list
-            Frame<W> cur = F1;
-            cur.pos = i;
-            cur.end = i + 1;
-            int depth = 0;
-            for (;;) {
-                if (cur.pos >= cur.end) {
+            const FrameView v = frame_view(frame_base(c, cur.off), cur.n, cur.wf);
+            if (cur.heavy == 0ull) {
+                int base;
+                if (depth == 0) {
+                    int got = 0;
+                    if (ln == 0) got = atomicAdd(&sh->claim, 64);
+                    base = __shfl(got, 0) + nq0;
+                } else {
+                    base = cur.chunk + 64;
+                }
+                if (base >= cur.n) {
                     if (depth == 0) break;
                     --depth;
                     cur = hdr[depth];
                     continue;
                 }
-                const int ii = cur.pos++;
-                if ((size_t)cur.top + (size_t)cur.n > (size_t)a.scap) {
-                    if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_STACK_OVERFLOW);
+                cur.chunk = base;
+                cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM>(c, cur, v, base, acc)
+                                          : light_chunk<W, DIAG, ENUM>(c, cur, v, base, acc);
+                continue;
+            }
+            const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
+            cur.heavy &= cur.heavy - 1ull;
+            FrameState ch;
+            const bool pushed = (cur.wf == 1) ? heavy_node<1, W, DIAG, ENUM>(c, cur, v, cur.chunk + lane, ch, acc)
+                                              : heavy_node<W, W, DIAG, ENUM>(c, cur, v, cur.chunk + lane, ch, acc);
+            if (pushed) {
+                if (depth >= a.dims.maxdepth) {
+                    if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
                     aborted = true;
                     break;
                 }
-                Frame<W> ch;
-                ch.S = stk + cur.top;
-                if (process_node<W, DIAG, ENUM>(c, cur, ii, ch, acc)) {
-                    if (depth >= a.maxdepth) {
-                        if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
-                        aborted = true;
-                        break;
-                    }
-                    ch.top = cur.top + ch.n;
-                    hdr[depth] = cur;  // every lane stores the same header
-                    __threadfence_block();
-                    ++depth;
-                    cur = ch;
-                }
+                hdr[depth] = cur;  // every lane stores the same header
+                __threadfence_block();
+                ++depth;
+                cur = ch;
+            } else if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_STACK_OVERFLOW) {
+                aborted = true;
             }
         }
         __syncthreads();
     }
 
-    // flush this wave's tallies (values are wave-uniform except thread 0's top-level ones)
-    if (ln == 0) {
-        if (acc.count) atomicAdd(&a.acc[ACC_COUNT], (unsigned long long)acc.count);
-        if (acc.hash) atomicAdd(&a.acc[ACC_HASH], (unsigned long long)acc.hash);
-        if (acc.out_ints) atomicAdd(&a.acc[ACC_OUT_INTS], (unsigned long long)acc.out_ints);
-        if (DIAG) {
-            atomicAdd(&a.acc[ACC_NODES], (unsigned long long)acc.nodes);
-            atomicAdd(&a.acc[ACC_NONMAX], (unsigned long long)acc.nonmax);
-            atomicAdd(&a.acc[ACC_BYTES], (unsigned long long)acc.bytes);
-            atomicMax(&a.acc[ACC_MAX_DEPTH], (unsigned long long)acc.max_depth);
-        }
-    }
+    // tallies of the last graph
+    if (sh->graph >= 0) flush_acc<DIAG>(acc, a.graphs[sh->graph].acc, sh);
 }
 
+size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + (size_t)waves * 64 * W * sizeof(uint32_t); }
+
 template <int W>
-hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, int64_t hi,
-                    unsigned int *counter, int grid, int waves, size_t lds, hipStream_t s) {
+hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, int64_t hi, unsigned int *counter,
+                    int grid, int waves, hipStream_t s) {
     dim3 g(grid), b(64 * waves);
+    const size_t lds = lds_bytes(W, waves);
     if (diag && enumerate)
         hipLaunchKernelGGL((search_kernel<W, true, true>), g, b, lds, s, a, lo, hi, counter);
     else if (diag)
@@ -721,30 +1146,58 @@ hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, 
     return hipGetLastError();
 }
 
+size_t align_up(size_t x, size_t al) { return (x + al - 1) / al * al; }
+
 }  // namespace
 
-size_t frame_header_bytes(int W) {
-    switch (W) {
-        case 1: return sizeof(Frame<1>);
-        case 2: return sizeof(Frame<2>);
-        case 4: return sizeof(Frame<4>);
-        case 8: return sizeof(Frame<8>);
-        default: return sizeof(Frame<16>);
-    }
-}
-
-size_t search_lds_bytes(int W, int waves) {
-    return sizeof(WGShared) + (size_t)waves * 64 * W * sizeof(uint32_t);
+ArenaLayout search_layout(const SearchDims &d) {
+    ArenaLayout L{};
+    const size_t ucap = (size_t)d.ucap, W = (size_t)d.Wmax, bits = 64 * W;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    L.off_bitmap = take((size_t)d.nwords * 8);
+    L.off_bpre = take(((size_t)d.nwords + 1) * 4);
+    L.off_M = take(ucap * W * 8);
+    L.off_gid = take(ucap * 4);
+    L.off_cnt = take(ucap * 4);
+    L.off_hv = take(bits * 8);
+    L.off_deg = take(bits * 4);
+    L.off_t1v = take(ucap * 4);
+    L.off_t1c = take(ucap * 4);
+    L.off_cur1 = take(bits * 4);
+    // ids | masks | first | cnt | H | ptr | orig | post (see frame_view)
+    L.s1_words = align_up(ucap, 2) + 2 * ucap * W + 2 * bits + 2 * bits + bits + 1 + 64 + (size_t)d.post_cap + 2;
+    L.off_S1 = take(L.s1_words * 4);
+    L.off_waves = o;
+    size_t w = 0;
+    auto wtake = [&](size_t bytes) {
+        const size_t at = w;
+        w = align_up(w + bytes, 256);
+        return at;
+    };
+    L.off_w_stack = wtake((size_t)d.scap * 4);
+    L.off_w_q = wtake(ucap * 4);
+    L.off_w_p = wtake(ucap * 4);
+    L.off_w_c = wtake(ucap * 4);
+    L.off_w_cur = wtake(bits * 4);
+    L.off_w_hdr = wtake((size_t)d.maxdepth * sizeof(FrameState));
+    L.wave_bytes = w;
+    L.wg_bytes = align_up(o + (size_t)d.waves * w, 4096);
+    return L;
 }
 
 hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, int64_t lo, int64_t hi,
-                         unsigned int *counter, int grid, int waves, size_t lds, hipStream_t s) {
+                         unsigned int *counter, int grid, int waves, hipStream_t s) {
     switch (W) {
-        case 1: return launch_w<1>(a, diag, enumerate, lo, hi, counter, grid, waves, lds, s);
-        case 2: return launch_w<2>(a, diag, enumerate, lo, hi, counter, grid, waves, lds, s);
-        case 4: return launch_w<4>(a, diag, enumerate, lo, hi, counter, grid, waves, lds, s);
-        case 8: return launch_w<8>(a, diag, enumerate, lo, hi, counter, grid, waves, lds, s);
-        case 16: return launch_w<16>(a, diag, enumerate, lo, hi, counter, grid, waves, lds, s);
+        case 1: return launch_w<1>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
+        case 2: return launch_w<2>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
+        case 4: return launch_w<4>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
+        case 8: return launch_w<8>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
+        case 16: return launch_w<16>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -85,3 +85,25 @@ def test_empty_graphs_need_no_device():
     for g in (gg.edgeless(4, 5), gg.edgeless(0, 3), gg.edgeless(3, 0)):
         r = m.mbe_count(g)
         assert r["count"] == 0 and r["hash"] == 0
+
+
+def test_batch_rejects_bad_input_before_device_work():
+    import paper_2401_05039_amd as m
+    good = gg.complete(2, 3)
+    bad = _mk(2, 3, [0, 3, 6], [0, 2, 1, 0, 1, 2], good.v_off, good.v_adj)
+    with pytest.raises(m.MbeError) as e:
+        m.mbe_count_batch([good, bad, good])
+    assert e.value.code == -2
+    with pytest.raises(m.MbeError) as e:
+        m.mbe_count_batch([good], m.Options(wg_waves=99))
+    assert e.value.code == -1
+    assert m.mbe_count_batch([]) == []
+    r = m.mbe_count_batch([gg.edgeless(3, 3), gg.edgeless(0, 2)])
+    assert all(x["count"] == 0 and x["hash"] == 0 for x in r)
+
+
+def test_server_rejects_bad_options():
+    import paper_2401_05039_amd as m
+    with pytest.raises(m.MbeError) as e:
+        m.Server(slots=99)
+    assert e.value.code == -1

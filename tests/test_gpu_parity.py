@@ -200,3 +200,68 @@ def test_workload3_samples(mbe):
         r = mbe.mbe_count(g, mbe.Options(diagnostics=True, root_lo=s["rank_lo"], root_hi=s["rank_hi"]))
         for k in ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "max_depth"):
             assert r[k] == s[k], (s["rank_lo"], k)
+
+
+# ----------------------------------------------------------------------------- batched form
+
+def _small_batch():
+    gs = [gg.random_small(int(5 + (7 * i) % 40), int(4 + (11 * i) % 45), 0.05 + 0.6 * ((i * 37) % 100) / 100, 4000 + i)
+          for i in range(60)]
+    gs += [gg.crown(6), gg.complete(3, 9), gg.edgeless(4, 4), gg.perfect_matching(30), gg.chain(20)]
+    gs += [gg.config1(), gg.transpose(gg.random_small(30, 70, 0.1, 91))]
+    return gs
+
+
+def test_batch_equals_oracle_per_graph(mbe, orc):
+    gs = _small_batch()
+    _say("batch", len(gs))
+    res = mbe.mbe_count_batch(gs, mbe.Options(diagnostics=True))
+    for i, (g, r) in enumerate(zip(gs, res)):
+        want = orc.mbea(g)
+        for k in ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "max_depth", "side"):
+            assert r[k] == want[k], (i, g.name, k, r[k], want[k])
+
+
+def test_batch_equals_single_calls(mbe):
+    gs = [gg.config4_graph(i) for i in range(0, 64, 4)]
+    gs = [g for g in gs if g.n_edges < 8000]
+    _say("batch vs single", len(gs))
+    res = mbe.mbe_count_batch(gs)
+    for g, r in zip(gs, res):
+        one = mbe.mbe_count(g)
+        assert (r["count"], r["hash"]) == (one["count"], one["hash"]), g.name
+
+
+def test_batch_launch_shapes_agree(mbe):
+    gs = _small_batch()
+    _say("batch shapes")
+    base = mbe.mbe_count_batch(gs)
+    for waves, grid in ((1, 1), (4, 7), (8, 0)):
+        res = mbe.mbe_count_batch(gs, mbe.Options(wg_waves=waves, grid=grid))
+        assert [(r["count"], r["hash"]) for r in res] == [(r["count"], r["hash"]) for r in base]
+
+
+# ----------------------------------------------------------------------------- serving form
+
+def test_server_results_equal_alone(mbe):
+    import threading
+    gs = [gg.config4_graph(i) for i in range(0, 200, 5)]
+    gs = [g for g in gs if g.n_edges < 20000] + [gg.config1(), gg.crown(9)]
+    _say("server", len(gs))
+    alone = [mbe.mbe_count(g) for g in gs]
+    with mbe.Server(slots=2) as sv:
+        tickets = [None] * len(gs)
+
+        def feed(lo):
+            for i in range(lo, len(gs), 3):
+                tickets[i] = sv.submit(gs[i])
+
+        th = [threading.Thread(target=feed, args=(k,)) for k in range(3)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        for i, tk in enumerate(tickets):
+            r, lat = sv.wait(tk)
+            assert (r["count"], r["hash"]) == (alone[i]["count"], alone[i]["hash"]), gs[i].name
+            assert lat >= 0.0
