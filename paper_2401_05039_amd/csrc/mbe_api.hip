@@ -53,7 +53,7 @@ struct DevBuf {
 
 struct DeviceState {
     std::mutex mu;
-    DevBuf graph, prep, sort_tmp, arena, small;
+    DevBuf graph, prep, sort_tmp, arena, small, steal;
     DevBuf rec, rec_offs, rec_tmp, rec_lens, canon_tmp, out_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int cus = 0;
@@ -363,9 +363,13 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         if (graph_acc && graph_acc != run_acc) MBE_TRY(hipMemsetAsync(graph_acc, 0, graph_acc_bytes, s));
         MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
         MBE_TRY(hipMemsetAsync(counters, 0, 8 * 4, s));
+        MBE_TRY(st->steal.ensure(sizeof(StealSlot) * (size_t)grid));
+        a.steal = st->steal.as<StealSlot>();
+        a.steal_on = 1;
         MBE_TRY(hipEventRecord(st->ev0, s));
         for (int c = 4; c >= 0; --c) {
             if (cls_lo[c] >= cls_hi[c]) continue;
+            MBE_TRY(hipMemsetAsync(a.steal, 0, sizeof(StealSlot) * (size_t)grid, s));
             MBE_TRY(launch_search(a, 1 << c, diag, enumerate, cls_lo[c], cls_hi[c], counters + c, grid, waves, s));
         }
         MBE_TRY(hipEventRecord(st->ev1, s));
@@ -651,7 +655,7 @@ struct ServerRequest {
 };
 
 void free_state(DeviceState *st) {
-    DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->rec,
+    DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->steal, &st->rec,
                       &st->rec_offs, &st->rec_tmp, &st->rec_lens, &st->canon_tmp, &st->out_tmp};
     for (DevBuf *b : bufs)
         if (b->p) {

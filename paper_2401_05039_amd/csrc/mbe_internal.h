@@ -85,6 +85,15 @@ struct GraphDesc {
     int32_t pad;
 };
 
+// Work-stealing slot of one workgroup: while it searches a top-level candidate whose child
+// list has more than one 64-candidate chunk left, word = (epoch << 32) | chunks claimed so
+// far (in candidates) and the other fields name the task; word = 0 otherwise.
+struct StealSlot {
+    unsigned long long word;
+    int32_t g, k, limit, pad;
+    unsigned long long pad2;
+};
+
 struct SearchArgs {
     // packed graph(s) in candidate orientation: rows of c_off / c_adj are candidates, ids in
     // c_adj are other-side ids and vice versa
@@ -97,6 +106,8 @@ struct SearchArgs {
     char *arena;
     SearchDims dims;
     ArenaLayout lay;
+    StealSlot *steal;           // one per workgroup, zeroed before each launch
+    int32_t steal_on;           // 0: no stealing (each top-level candidate stays in one workgroup)
     // outputs
     unsigned long long *acc;    // run-wide slots (overflow sizes, record cursors)
     unsigned int *flags;

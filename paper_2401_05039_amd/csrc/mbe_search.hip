@@ -645,6 +645,11 @@ struct WGShared {
     unsigned long long post1;
     int nexp;
     int graph;  // graph whose tallies the workgroup is holding
+    int mode;   // 0 done, 1 own task, 2 stolen task
+    int victim; // workgroup whose child list a stolen task shares
+    unsigned int epoch;
+    int gclaim; // chunks are claimed through the global steal slot
+    int sg, sk; // graph and rank of a stolen task
     int scan[16];
     unsigned long long red[8];  // per-graph tally reduction
 };
@@ -678,6 +683,20 @@ __device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) 
     }
     __syncthreads();
     acc = WaveAcc{0, 0, 0, 0, 0, 0, 0};
+}
+
+// Claim the next 64-candidate chunk of a published top-level list: returns the chunk's
+// offset, or -1 once the list is used up or its owner has moved on (epoch changed).
+__device__ int claim_chunk(unsigned long long *word, unsigned int epoch, int limit) {
+    unsigned long long old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if ((unsigned int)(old >> 32) != epoch) return -1;
+        const unsigned int got = (unsigned int)old;
+        if ((int)got >= limit) return -1;
+        const unsigned long long prev = atomicCAS(word, old, old + 64ull);
+        if (prev == old) return (int)got;
+        old = prev;
+    }
 }
 
 // Block-wide exclusive prefix of popcounts over nwords bitmap words into bpre; total in
@@ -767,21 +786,54 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
 
     for (;;) {
         if (tid == 0) {
-            // stop claiming once a capacity ran out: the host reruns with more room
+            // a fresh top-level candidate, else a share of another workgroup's child list;
+            // stop once a capacity ran out (the host reruns with more room)
             const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sh->task = (f & FLAG_RERUN) ? (1ull << 62) : (unsigned long long)atomicAdd(counter, 1u);
+            sh->mode = 0;
+            if (!(f & FLAG_RERUN)) {
+                const unsigned int t = atomicAdd(counter, 1u);
+                if (lo + (int64_t)t < hi) {
+                    sh->mode = 1;
+                    sh->task = t;
+                    sh->epoch = t + 1u;
+                } else if (a.steal_on) {
+                    for (int j = 1; j < (int)gridDim.x && sh->mode == 0; ++j) {
+                        const int vwg = (int)((blockIdx.x + j) % gridDim.x);
+                        StealSlot *sl = &a.steal[vwg];
+                        const unsigned long long w1 = __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned int e = (unsigned int)(w1 >> 32);
+                        if (e == 0u) continue;
+                        const int sg = __hip_atomic_load(&sl->g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int sk = __hip_atomic_load(&sl->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int lim = __hip_atomic_load(&sl->limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __threadfence();
+                        const unsigned long long w2 = __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                        if ((unsigned int)(w2 >> 32) != e) continue;       // owner moved on meanwhile
+                        if ((int)(unsigned int)w2 + 128 > lim) continue;   // under two chunks left
+                        sh->mode = 2;
+                        sh->victim = vwg;
+                        sh->epoch = e;
+                        sh->sg = sg;
+                        sh->sk = sk;
+                    }
+                }
+            }
         }
         __syncthreads();
-        const int64_t t = (int64_t)sh->task;
-        if (lo + t >= hi) break;
+        const int mode = sh->mode;
+        if (mode == 0) break;
+        const bool thief = mode == 2;
         int g = 0;
         int64_t k;
-        if (a.tasks) {
-            const unsigned long long tk = a.tasks[lo + t];
+        if (thief) {
+            g = sh->sg;
+            k = sh->sk;
+        } else if (a.tasks) {
+            const unsigned long long tk = a.tasks[lo + (int64_t)sh->task];
             g = (int)(tk >> 32);
             k = (int64_t)(tk & 0xFFFFFFFFull);
         } else {
-            k = hi - 1 - t;  // ranks are claimed from the top (largest degree) down
+            k = hi - 1 - (int64_t)sh->task;  // ranks are claimed from the top (largest degree) down
         }
         if (g != sh->graph) {
             // tallies belong to the graph they were found in
@@ -839,6 +891,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             sh->post1 = 0;
             sh->nexp = 0;
             sh->claim = 0;
+            sh->gclaim = 0;
         }
         __threadfence_block();
         __syncthreads();
@@ -943,7 +996,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         __syncthreads();
         const bool root_nonmax = sh->nonmax != 0;
         const int P1 = sh->pcount;
-        if (tid == 0) {
+        if (tid == 0 && !thief) {  // a stolen task's top-level node belongs to its owner
             const uint64_t dx = (uint64_t)d;
             if (DIAG) {
                 acc.nodes += 1;
@@ -963,7 +1016,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 acc.out_ints += 2ull + (uint64_t)nL + (uint64_t)d;
             }
         }
-        if (ENUM && !root_nonmax && wid == 0) {
+        if (ENUM && !root_nonmax && !thief && wid == 0) {
             uint64_t R1[16];
             for (int w = 0; w < 16; ++w) {
                 const int bits = d - 64 * w;
@@ -1063,6 +1116,26 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         __threadfence_block();
         __syncthreads();
 
+        // -- share the child list: with more than one chunk, claims go through the global
+        //    steal slot so that idle workgroups can take chunks (they rebuild the same list)
+        StealSlot *slot = thief ? &a.steal[sh->victim] : &a.steal[blockIdx.x];
+        if (tid == 0) {
+            if (thief) {
+                sh->gclaim = 1;
+            } else if (a.steal_on && P1 > 64) {
+                slot->g = g;
+                slot->k = (int)k;
+                slot->limit = P1;
+                __threadfence();
+                __hip_atomic_store(&slot->word, (unsigned long long)sh->epoch << 32, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                sh->gclaim = 1;
+            }
+        }
+        __syncthreads();
+        const bool gclaim = sh->gclaim != 0;
+        const unsigned int epoch = sh->epoch;
+
         // -- second level and below: waves claim 64-candidate chunks of the top-level list
         //    and search depth-first from them
         FrameState cur;
@@ -1086,8 +1159,9 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 int base;
                 if (depth == 0) {
                     int got = 0;
-                    if (ln == 0) got = atomicAdd(&sh->claim, 64);
-                    base = __shfl(got, 0) + nq0;
+                    if (ln == 0) got = gclaim ? claim_chunk(&slot->word, epoch, P1) : atomicAdd(&sh->claim, 64);
+                    got = __shfl(got, 0);
+                    base = got < 0 ? cur.n : got + nq0;
                 } else {
                     base = cur.chunk + 64;
                 }
@@ -1122,6 +1196,9 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             }
         }
         __syncthreads();
+        // every chunk is claimed: withdraw the list (thieves still finish the chunks they hold)
+        if (tid == 0 && gclaim && !thief)
+            __hip_atomic_store(&slot->word, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // tallies of the last graph

@@ -107,13 +107,22 @@ def test_transpose_gives_same_set(mbe, orc):
     assert sorted((y, x) for x, y in la) == lb
 
 
-@pytest.mark.parametrize("deg", [60, 130, 250, 500, 1000])
+@pytest.mark.parametrize("deg", [60, 130, 250, 500, 900])
 def test_mask_width_classes(mbe, orc, deg):
     # 40 candidates of degree about deg put the top-level candidates in every mask-width
     # class; the other side is 20x larger so that common neighbourhoods stay small
     nu, nv = 40, 20 * deg
     g = gg.random_small(nu, nv, deg / nv, 900 + deg)
     _check(mbe, orc, g, f"width{deg}")
+
+
+def test_degree_above_mask_width_is_refused(mbe):
+    g = gg.complete(2, 1025)
+    _say("degree 1025")
+    with pytest.raises(mbe.MbeError) as e:
+        mbe.mbe_count(g)
+    assert e.value.code == -6
+    assert mbe.mbe_count(gg.complete(2, 1024))["count"] == 1
 
 
 @pytest.mark.parametrize("seed", range(3))
