@@ -76,6 +76,11 @@ typedef struct mbe_graph {
  *            written by the reverse-scanning method of section III-E, see the design notes).
  * side       candidate side used: 1 = U, 2 = V
  * kernel_ms  device time of the search kernel(s) of this call, from HIP events
+ * phase_cycles  with diagnostics: shader-clock cycles summed over waves, per phase of the
+ *            search (the breakdown of the paper's evaluation, section IV): [0] top-level
+ *            candidate set-up, [1] settling single-vertex nodes, [2] maximality tests of the
+ *            other nodes, [3] scans of maximal nodes, [4] building child lists, [5] waiting,
+ *            stealing and claiming
  */
 typedef struct mbe_result {
     uint64_t count;
@@ -87,6 +92,7 @@ typedef struct mbe_result {
     uint32_t max_depth;
     uint32_t side;
     double kernel_ms;
+    uint64_t phase_cycles[6];
 } mbe_result;
 
 /* ------------------------------------------------------------------------- options */

@@ -45,7 +45,8 @@ class _Result(ctypes.Structure):
     _fields_ = [("count", ctypes.c_uint64), ("hash", ctypes.c_uint64), ("out_ints", ctypes.c_uint64),
                 ("nodes", ctypes.c_uint64), ("nonmaximal", ctypes.c_uint64),
                 ("bytes_alg", ctypes.c_uint64), ("max_depth", ctypes.c_uint32),
-                ("side", ctypes.c_uint32), ("kernel_ms", ctypes.c_double)]
+                ("side", ctypes.c_uint32), ("kernel_ms", ctypes.c_double),
+                ("phase_cycles", ctypes.c_uint64 * 6)]
 
 
 class _Options(ctypes.Structure):
@@ -164,8 +165,13 @@ def _marshal_opts(opt: Optional[Options], on_device: bool) -> _Options:
                     0, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0))
 
 
+PHASES = ("root", "light", "check", "expand", "child", "wait")
+
+
 def _result_dict(r: _Result) -> Dict[str, Any]:
-    return {k: getattr(r, k) for k, _ in _Result._fields_}
+    d = {k: getattr(r, k) for k, _ in _Result._fields_ if k != "phase_cycles"}
+    d["phase_cycles"] = dict(zip(PHASES, list(r.phase_cycles)))
+    return d
 
 
 def mbe_count(g, opt: Optional[Options] = None) -> Dict[str, Any]:

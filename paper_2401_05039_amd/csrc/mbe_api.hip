@@ -317,6 +317,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     out->bytes_alg = hacc[ACC_BYTES];
     out->max_depth = (uint32_t)hacc[ACC_MAX_DEPTH];
     out->kernel_ms = ms;
+    for (int q = 0; q < PH_COUNT; ++q) out->phase_cycles[q] = hacc[ACC_PHASE + q];
 
     if (!enumerate) return MBE_OK;
     if ((hflags & FLAG_RECORD_OVERFLOW) || out->out_ints > ucap_ints) return MBE_ERR_BUFFER_TOO_SMALL;
@@ -628,6 +629,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         outs[i].bytes_alg = q[ACC_BYTES];
         outs[i].max_depth = (uint32_t)q[ACC_MAX_DEPTH];
         outs[i].kernel_ms = ms;
+        for (int ph = 0; ph < PH_COUNT; ++ph) outs[i].phase_cycles[ph] = q[ACC_PHASE + ph];
     }
     return MBE_OK;
 }

@@ -21,7 +21,19 @@ enum AccSlot : int {
     ACC_REC_INTS = 8,   // ints reserved in the record arena
     ACC_NEED_UCAP = 9,  // largest universe met (max), for resizing after an overflow
     ACC_NEED_POST = 10, // largest top-level posting total met (max)
-    ACC_SLOTS = 16,
+    ACC_PHASE = 11,     // 6 slots: shader-clock cycles per search phase (diagnostics only)
+    ACC_SLOTS = 24,
+};
+
+// Search phases timed in diagnostics mode (cycles summed over waves).
+enum Phase : int {
+    PH_ROOT = 0,    // top-level candidate: reverse scans, universe, child list and its tables
+    PH_LIGHT = 1,   // 64-candidate chunks: settling the |R'| = 1 candidates
+    PH_CHECK = 2,   // |R'| >= 2 candidates: maximality test
+    PH_EXPAND = 3,  // maximal candidates: scan of the list, expansion, report
+    PH_CHILD = 4,   // building child lists and their tables
+    PH_WAIT = 5,    // waiting for the workgroup, stealing, claiming
+    PH_COUNT = 6,
 };
 
 // Status bits raised by kernels.

@@ -200,6 +200,7 @@ struct Ctx {
 struct WaveAcc {  // per-lane partial tallies, summed over the wave at the end
     uint64_t count, hash, out_ints, nodes, nonmax, bytes;
     uint32_t max_depth;
+    uint64_t ph[PH_COUNT];  // cycles per phase (wave-uniform; diagnostics only)
 };
 
 // Hash terms use the graph's own ids (packed id minus the graph's base).
@@ -447,6 +448,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         }
     }
     bool nonmax = false;
+    uint64_t tp = DIAG ? clock64() : 0ull;
     if (!__ballot(first_here)) {
         best = wave_min_u32(best);
         const uint32_t b = best & 0xFFFu;
@@ -471,6 +473,9 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
 
     uint64_t dx = 0, rs = 0;
     if (DIAG) {
+        const uint64_t now = clock64();
+        acc.ph[PH_CHECK] += now - tp;
+        tp = now;
         dx = deg_of(c, v.ids[i]);
         uint64_t t = 0;
 #pragma unroll
@@ -556,6 +561,11 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r + (uint64_t)pn +
                              (uint64_t)qn);
     }
+    if (DIAG) {
+        const uint64_t now = clock64();
+        acc.ph[PH_EXPAND] += now - tp;
+        tp = now;
+    }
     if (pn == 0) return false;
 
     // child frame: Q' then P' stably sorted by count; masks restricted to R' and, when
@@ -629,6 +639,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     C.heavy = 0ull;
     C.sL = sL;
     C.fw = DIAG ? wave_sum_u64(fwc) : 0ull;
+    if (DIAG) acc.ph[PH_CHILD] += clock64() - tp;
     return true;
 }
 
@@ -651,7 +662,7 @@ struct WGShared {
     int gclaim; // chunks are claimed through the global steal slot
     int sg, sk; // graph and rank of a stolen task
     int scan[16];
-    unsigned long long red[8];  // per-graph tally reduction
+    unsigned long long red[16];  // per-graph tally reduction
 };
 
 // Add the workgroup's tallies to a graph's accumulators and clear them.  All threads call.
@@ -670,6 +681,9 @@ __device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) 
         for (int q = 0; q < 6; ++q)
             if (v[q]) atomicAdd(&sh->red[q], (unsigned long long)v[q]);
         if (v[6]) atomicMax(&sh->red[6], (unsigned long long)v[6]);
+        if (DIAG)
+            for (int q = 0; q < PH_COUNT; ++q)
+                if (acc.ph[q]) atomicAdd(&sh->red[8 + q], (unsigned long long)acc.ph[q]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -680,9 +694,13 @@ __device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) 
         }
         if (sh->red[6]) atomicMax(&gacc[ACC_MAX_DEPTH], sh->red[6]);
         sh->red[6] = 0ull;
+        for (int q = 0; q < PH_COUNT; ++q) {
+            if (sh->red[8 + q]) atomicAdd(&gacc[ACC_PHASE + q], sh->red[8 + q]);
+            sh->red[8 + q] = 0ull;
+        }
     }
     __syncthreads();
-    acc = WaveAcc{0, 0, 0, 0, 0, 0, 0};
+    acc = WaveAcc{};
 }
 
 // Claim the next 64-candidate chunk of a published top-level list: returns the chunk's
@@ -777,10 +795,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     c.acc = a.acc;
     c.flags = a.flags;
 
-    WaveAcc acc = {0, 0, 0, 0, 0, 0, 0};
+    WaveAcc acc{};
     bool aborted = false;
     const int ucap = a.dims.ucap;
-    if (tid < 8) sh->red[tid] = 0ull;
+    if (tid < 16) sh->red[tid] = 0ull;
+    uint64_t t_mark = DIAG ? clock64() : 0ull;  // start of the phase being timed
     if (tid == 0) sh->graph = -1;
     __syncthreads();
 
@@ -820,6 +839,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             }
         }
         __syncthreads();
+        if (DIAG) {
+            const uint64_t now = clock64();
+            acc.ph[PH_WAIT] += now - t_mark;
+            t_mark = now;
+        }
         const int mode = sh->mode;
         if (mode == 0) break;
         const bool thief = mode == 2;
@@ -915,6 +939,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 atomicMax(&a.acc[ACC_NEED_UCAP], (unsigned long long)s0);
             }
             __syncthreads();
+            if (DIAG) {
+                const uint64_t now = clock64();
+                acc.ph[PH_ROOT] += now - t_mark;
+                t_mark = now;
+            }
             continue;
         }
         const int nq0 = (int)bpre[k >> 6] + __popcll(bitmap[k >> 6] & ((1ull << (k & 63)) - 1ull));
@@ -1026,6 +1055,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         }
         if (root_nonmax || P1 == 0) {
             __syncthreads();
+            if (DIAG) {
+                const uint64_t now = clock64();
+                acc.ph[PH_ROOT] += now - t_mark;
+                t_mark = now;
+            }
             continue;
         }
         const int n1 = nq0 + P1;
@@ -1036,6 +1070,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 atomicMax(&a.acc[ACC_NEED_POST], (unsigned long long)post1);
             }
             __syncthreads();
+            if (DIAG) {
+                const uint64_t now = clock64();
+                acc.ph[PH_ROOT] += now - t_mark;
+                t_mark = now;
+            }
             continue;
         }
 
@@ -1135,6 +1174,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         __syncthreads();
         const bool gclaim = sh->gclaim != 0;
         const unsigned int epoch = sh->epoch;
+        if (DIAG) {
+            const uint64_t now = clock64();
+            acc.ph[PH_ROOT] += now - t_mark;
+            t_mark = now;
+        }
 
         // -- second level and below: waves claim 64-candidate chunks of the top-level list
         //    and search depth-first from them
@@ -1172,8 +1216,10 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                     continue;
                 }
                 cur.chunk = base;
+                const uint64_t tl = DIAG ? clock64() : 0ull;
                 cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM>(c, cur, v, base, acc)
                                           : light_chunk<W, DIAG, ENUM>(c, cur, v, base, acc);
+                if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
                 continue;
             }
             const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
@@ -1195,6 +1241,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 aborted = true;
             }
         }
+        if (DIAG) t_mark = clock64();  // from here to the next task: waiting
         __syncthreads();
         // every chunk is claimed: withdraw the list (thieves still finish the chunks they hold)
         if (tid == 0 && gclaim && !thief)
