@@ -215,7 +215,11 @@ def main():
     base = dict(wg_waves=args.waves, grid=args.grid, root_lo=lo, root_hi=hi)
 
     # one untimed run with diagnostics gives the algorithmic bytes of the (deterministic) tree
+    # and the time split over search phases
     diag = mbe.mbe_count(dg, mbe.Options(diagnostics=True, **base))
+    ph = diag["phase_cycles"]
+    ph_tot = max(1, sum(ph.values()))
+    phase_share = {k: round(v / ph_tot, 4) for k, v in ph.items()}
     log("diagnostics", {k: diag[k] for k in ("count", "hash", "nodes", "nonmaximal", "bytes_alg", "max_depth",
                                              "kernel_ms")})
     opt = mbe.Options(**base)
@@ -252,6 +256,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "search_kernel (all mask-width launches of one step)",
                      "kernel_ms": kavg, "bytes_alg": diag["bytes_alg"]},
+        "phase_share": phase_share,
     }
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

@@ -81,6 +81,8 @@ struct ArenaLayout {
     size_t off_w_p;     // u32[ucap]            staging of P' (parent positions)
     size_t off_w_c;     // u32[ucap]            staging of P' counts
     size_t off_w_cur;   // u32[64*Wmax]         posting cursors
+    size_t off_w_u;     // u32[ucap]            a maximal node's entries, in list order
+    size_t off_w_bm;    // u64[(ucap+63)/64]    position bitmap of those entries (kept zero)
     size_t off_w_hdr;   // frame headers[maxdepth]
 };
 

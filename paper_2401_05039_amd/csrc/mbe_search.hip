@@ -185,6 +185,10 @@ struct Ctx {
     uint32_t *s1;                     // the workgroup's top-level list frame
     uint32_t *stk;                    // this wave's stack
     uint32_t *stq, *stp, *stc, *cur;  // this wave's staging
+    uint32_t *stu;                    // a maximal node's entries in list order
+    uint64_t *ubm;                    // their position bitmap (all zero between nodes)
+    uint32_t *tl_first, *tl_cnt, *tl_cur;  // this wave's LDS tables for narrow children
+    uint64_t *tl_H;
     uint32_t *hist;                   // this wave's LDS histogram
     int64_t scap;
     int32_t x_root, s0, c_is_v, Wroot;
@@ -319,6 +323,52 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
                     m &= m - 1ull;
                     v.post[atomicAdd(&cursor[b], 1u)] = (uint32_t)k;
                 }
+            }
+        }
+    }
+    __threadfence_block();
+}
+
+// Tables of a narrow frame (one mask word per entry), accumulated in the wave's LDS scratch
+// and then written out.  One wave.
+__device__ void build_tables_narrow(const Ctx &c, const FrameView &v, int n) {
+    const int ln = lane_id();
+    c.tl_first[ln] = kNone;
+    c.tl_cnt[ln] = 0u;
+    c.tl_H[ln] = 0ull;
+    __builtin_amdgcn_wave_barrier();
+    for (int base = 0; base < n; base += 64) {
+        const int k = base + ln;
+        if (k < n) {
+            const uint64_t h = hl(c, c.gid[v.ids[k]]);
+            uint64_t m = v.masks[k];
+            while (m) {
+                const int b = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                atomicMin(&c.tl_first[b], (uint32_t)k);
+                atomicAdd(&c.tl_cnt[b], 1u);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&c.tl_H[b]), (unsigned long long)h);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int h = (int)c.tl_cnt[ln];
+    const int incl = wave_incl_scan(h);
+    v.first[ln] = c.tl_first[ln];
+    v.cnt[ln] = (uint32_t)h;
+    v.H[ln] = c.tl_H[ln];
+    v.ptr[ln] = (uint32_t)(incl - h);
+    c.tl_cur[ln] = (uint32_t)(incl - h);
+    if (ln == 63) v.ptr[64] = (uint32_t)incl;
+    __builtin_amdgcn_wave_barrier();
+    for (int base = 0; base < n; base += 64) {
+        const int k = base + ln;
+        if (k < n) {
+            uint64_t m = v.masks[k];
+            while (m) {
+                const int b = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                v.post[atomicAdd(&c.tl_cur[b], 1u)] = (uint32_t)k;
             }
         }
     }
@@ -496,21 +546,67 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         return false;
     }
 
-    // maximal: one pass over the list counts every entry against R'
+    // maximal: the entries sharing a bit with R' are the union of R''s posting lists.  Each
+    // is taken once (from the list of its lowest bit in R'), marked in a position bitmap,
+    // and the bitmap is read back in list order, which keeps the stable tie order of P'.
     int qn = 0, pn = 0, ne = 0;
     uint64_t exps = 0, fwc = 0;
     uint32_t csum = 0;
-    for (int base = 0; base < F.n; base += 64) {
-        const int k = base + ln;
-        const bool act = k < F.n && k != i;
-        int cnt = 0;
+#pragma unroll
+    for (int w = 0; w < WF; ++w) {
+        uint64_t mb = m[w];
+        while (mb) {  // uniform loop over the bits of R'
+            const int bit = __ffsll((unsigned long long)mb) - 1;
+            mb &= mb - 1ull;
+            const int b = 64 * w + bit;
+            const uint32_t p0 = v.ptr[b], p1 = v.ptr[b + 1];
+            for (uint32_t q = p0 + (uint32_t)ln; q < p1; q += 64) {
+                const uint32_t p = v.post[q];
+                if ((int)p == i) continue;
+                // lowest bit of mask[p] & R'
+                int low = -1;
+#pragma unroll
+                for (int ww = 0; ww < WF; ++ww) {
+                    const uint64_t x = v.masks[(size_t)p * WF + ww] & m[ww];
+                    if (low < 0 && x) low = 64 * ww + __ffsll((unsigned long long)x) - 1;
+                }
+                if (low == b) atomicOr(reinterpret_cast<unsigned long long *>(&c.ubm[p >> 6]), 1ull << (p & 63));
+            }
+        }
+    }
+    __threadfence_block();
+    int nu = 0;
+    const int nwords_n = (F.n + 63) >> 6;
+    for (int base = 0; base < nwords_n; base += 64) {
+        const int wd = base + ln;
+        uint64_t bits = 0;
+        if (wd < nwords_n) {
+            bits = c.ubm[wd];
+            if (bits) c.ubm[wd] = 0ull;
+        }
+        const int pc = __popcll(bits);
+        const int incl = wave_incl_scan(pc);
+        int at = nu + incl - pc;
+        while (bits) {
+            const int b = __ffsll((unsigned long long)bits) - 1;
+            bits &= bits - 1ull;
+            c.stu[at++] = (uint32_t)(wd * 64 + b);
+        }
+        nu += __shfl(incl, 63);
+    }
+    __threadfence_block();
+    for (int base = 0; base < nu; base += 64) {
+        const int j = base + ln;
+        const bool act = j < nu;
+        int k = 0, cnt = 0;
         if (act) {
+            k = (int)c.stu[j];
 #pragma unroll
             for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
         }
-        const bool inq = act && k < i && cnt > 0;  // cnt < r: the node passed the check
+        const bool inq = act && k < i;  // 0 < cnt < r: the node passed the check
         const bool full = act && k > i && cnt == r;
-        const bool inp = act && k > i && cnt > 0 && cnt < r;
+        const bool inp = act && k > i && cnt < r;
         if (full) exps += hl(c, c.gid[v.ids[k]]);
         ne += __popcll(__ballot(full));
         const uint64_t qb = __ballot(inq), pb = __ballot(inp);
@@ -623,7 +719,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     }
     wave_sort_by_key(c.stp, c.stc, pn, r, c.hist, [&](uint32_t slot, uint32_t k) { put((uint32_t)qn + slot, k); });
     __threadfence_block();
-    if (narrow) build_tables<1>(c, v2, n2, c.cur);
+    if (narrow) build_tables_narrow(c, v2, n2);
     else build_tables<W>(c, v2, n2, c.cur);
 
     C.off = off2;
@@ -782,7 +878,17 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     c.stp = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_p);
     c.stc = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_c);
     c.cur = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_cur);
+    c.stu = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_u);
+    c.ubm = reinterpret_cast<uint64_t *>(wv + a.lay.off_w_bm);
     c.hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * BITS;
+    {
+        // narrow-child table scratch: first[64] cnt[64] cur[64] (u32) then H[64] (u64) per wave
+        unsigned char *tb = lds_raw + sizeof(WGShared) + (size_t)nw * BITS * 4 + (size_t)wid * 1280;
+        c.tl_first = reinterpret_cast<uint32_t *>(tb);
+        c.tl_cnt = c.tl_first + 64;
+        c.tl_cur = c.tl_first + 128;
+        c.tl_H = reinterpret_cast<uint64_t *>(tb + 768);
+    }
     c.scap = a.dims.scap;
     c.c_is_v = 0;
     c.cbase = 0;
@@ -1252,7 +1358,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     if (sh->graph >= 0) flush_acc<DIAG>(acc, a.graphs[sh->graph].acc, sh);
 }
 
-size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + (size_t)waves * 64 * W * sizeof(uint32_t); }
+size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + (size_t)waves * (64 * W * sizeof(uint32_t) + 1280); }
 
 template <int W>
 hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, int64_t hi, unsigned int *counter,
@@ -1308,6 +1414,8 @@ ArenaLayout search_layout(const SearchDims &d) {
     L.off_w_p = wtake(ucap * 4);
     L.off_w_c = wtake(ucap * 4);
     L.off_w_cur = wtake(bits * 4);
+    L.off_w_u = wtake(ucap * 4);
+    L.off_w_bm = wtake((ucap + 63) / 64 * 8);
     L.off_w_hdr = wtake((size_t)d.maxdepth * sizeof(FrameState));
     L.wave_bytes = w;
     L.wg_bytes = align_up(o + (size_t)d.waves * w, 4096);
