@@ -28,8 +28,11 @@ using namespace mbe;
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool fresh = false;  // set when ensure() allocated new memory (contents undefined)
     hipError_t ensure(size_t n) {
+        fresh = false;
         if (n <= bytes && p) return hipSuccess;
+        fresh = true;
         if (p) {
             hipError_t e = hipFree(p);
             if (e != hipSuccess) return e;
@@ -53,11 +56,25 @@ struct DevBuf {
 
 struct DeviceState {
     std::mutex mu;
-    DevBuf graph, prep, sort_tmp, arena, small, steal;
+    DevBuf graph, prep, sort_tmp, arena, small, steal, slots;
     DevBuf rec, rec_offs, rec_tmp, rec_lens, canon_tmp, out_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int cus = 0;
+    // one stream per mask class, so the class launches overlap (created on first use)
+    hipStream_t cls_stream[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
+
+hipError_t ensure_class_streams(DeviceState *st) {
+    if (st->fork) return hipSuccess;
+    for (int c = 0; c < 5; ++c) {
+        hipError_t e = hipStreamCreateWithFlags(&st->cls_stream[c], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipEventCreateWithFlags(&st->join[c], hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    return hipEventCreateWithFlags(&st->fork, hipEventDisableTiming);
+}
 
 std::mutex g_states_mu;
 DeviceState *g_states[64] = {nullptr};
@@ -248,7 +265,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     const int64_t hi = opt.root_hi < 0 ? ncand : std::min<int64_t>(opt.root_hi, ncand);
 
     const int waves = opt.waves;
-    const int grid = opt.grid > 0 ? opt.grid : 2 * st->cus;
+    const int grid = opt.grid > 0 ? opt.grid : 0;  // 0: occupancy-sized per class
     SearchDims dims{};
     dims.nwords = (ncand + 63) / 64;
     dims.Wmax = Wmax;
@@ -354,24 +371,61 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
     unsigned int *flags = a.flags;
     unsigned int *counters = st->small.as<unsigned int>(512);
     unsigned int hflags = 0;
+    MBE_TRY(ensure_class_streams(st));
+    // persistent grids: as many workgroups per class as fit on the device at once (unless the
+    // caller fixed the grid); the arena has one slot per workgroup that can be resident
+    int cls_grid[5] = {0, 0, 0, 0, 0}, cls_res[5] = {0, 0, 0, 0, 0};
+    int64_t cap = 1, sum_grid = 0;
+    for (int c = 0; c < 5; ++c) {
+        if (cls_lo[c] >= cls_hi[c]) continue;
+        cls_res[c] = st->cus * search_occupancy(1 << c, diag, enumerate, waves);
+        cls_grid[c] = grid > 0 ? grid : cls_res[c];
+        cap = std::max<int64_t>(cap, cls_res[c]);
+        sum_grid += cls_grid[c];
+    }
+    bool sequential = false;
     for (int attempt = 0;; ++attempt) {
+        // concurrent launches: no more workgroups can hold slots than fit on the device or
+        // than the launches have; one class at a time: the largest of its grid and residency
+        int nslots = (int)std::max<int64_t>(1, std::min(cap, sum_grid));
+        if (sequential) {
+            nslots = 1;
+            for (int c = 0; c < 5; ++c) nslots = std::max(nslots, std::min(cls_grid[c], cls_res[c]));
+        }
         a.dims = dims;
         a.lay = search_layout(dims);
-        MBE_TRY(st->arena.ensure(a.lay.wg_bytes * (size_t)grid));
+        a.nslots = nslots;
+        MBE_TRY(st->arena.ensure(a.lay.wg_bytes * (size_t)nslots));
         a.arena = st->arena.as<char>();
-        MBE_TRY(hipMemset2DAsync(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, 0, (size_t)dims.nwords * 8, (size_t)grid, s));
+        // kernels keep their scratch bitmaps zero between uses; new memory starts zero too
+        if (st->arena.fresh) MBE_TRY(hipMemsetAsync(st->arena.p, 0, st->arena.bytes, s));
+        MBE_TRY(st->slots.ensure(sizeof(unsigned int) * (size_t)nslots));
+        a.slot_busy = st->slots.as<unsigned int>();
+        MBE_TRY(st->steal.ensure(sizeof(StealSlot) * (size_t)nslots * 5));
+        a.steal_on = 1;
+        MBE_TRY(hipMemset2DAsync(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, 0, (size_t)dims.nwords * 8, (size_t)nslots, s));
+        MBE_TRY(hipMemsetAsync(a.slot_busy, 0, sizeof(unsigned int) * (size_t)nslots, s));
+        MBE_TRY(hipMemsetAsync(st->steal.p, 0, sizeof(StealSlot) * (size_t)nslots * 5, s));
         MBE_TRY(hipMemsetAsync(run_acc, 0, run_acc_bytes, s));
         if (graph_acc && graph_acc != run_acc) MBE_TRY(hipMemsetAsync(graph_acc, 0, graph_acc_bytes, s));
         MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
         MBE_TRY(hipMemsetAsync(counters, 0, 8 * 4, s));
-        MBE_TRY(st->steal.ensure(sizeof(StealSlot) * (size_t)grid));
-        a.steal = st->steal.as<StealSlot>();
-        a.steal_on = 1;
         MBE_TRY(hipEventRecord(st->ev0, s));
+        if (!sequential) MBE_TRY(hipEventRecord(st->fork, s));
         for (int c = 4; c >= 0; --c) {
             if (cls_lo[c] >= cls_hi[c]) continue;
-            MBE_TRY(hipMemsetAsync(a.steal, 0, sizeof(StealSlot) * (size_t)grid, s));
-            MBE_TRY(launch_search(a, 1 << c, diag, enumerate, cls_lo[c], cls_hi[c], counters + c, grid, waves, s));
+            SearchArgs ac = a;
+            ac.steal = st->steal.as<StealSlot>() + (size_t)c * nslots;
+            hipStream_t cs = s;
+            if (!sequential) {
+                cs = st->cls_stream[c];
+                MBE_TRY(hipStreamWaitEvent(cs, st->fork, 0));
+            }
+            MBE_TRY(launch_search(ac, 1 << c, diag, enumerate, cls_lo[c], cls_hi[c], counters + c, cls_grid[c], waves, cs));
+            if (!sequential) {
+                MBE_TRY(hipEventRecord(st->join[c], cs));
+                MBE_TRY(hipStreamWaitEvent(s, st->join[c], 0));
+            }
         }
         MBE_TRY(hipEventRecord(st->ev1, s));
         MBE_TRY(hipMemcpyAsync(hacc, run_acc, ACC_SLOTS * 8, hipMemcpyDeviceToHost, s));
@@ -380,6 +434,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         MBE_TRY(hipEventElapsedTime(ms, st->ev0, st->ev1));
         if (!(hflags & FLAG_RERUN)) break;
         if (attempt >= 8) return MBE_ERR_OUT_OF_MEMORY;
+        if (hflags & FLAG_NO_SLOT) sequential = true;
         if (hflags & FLAG_STACK_OVERFLOW) dims.scap = std::min<int64_t>(dims.scap * 2, (int64_t)1 << 31);
         if (hflags & FLAG_DEPTH_OVERFLOW) dims.maxdepth *= 2;
         if (hflags & FLAG_UNIVERSE_OVERFLOW) {
@@ -598,7 +653,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     dims.post_cap = post;
     dims.scap = 2 * ucap + 16384;
     dims.maxdepth = 64 * Wmax + 2;
-    const int grid = opt.grid > 0 ? opt.grid : 2 * st->cus;
+    const int grid = opt.grid > 0 ? opt.grid : 0;  // 0: occupancy-sized per class
 
     SearchArgs a{};
     a.c_off = d_coff;
@@ -657,7 +712,7 @@ struct ServerRequest {
 };
 
 void free_state(DeviceState *st) {
-    DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->steal, &st->rec,
+    DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->steal, &st->slots, &st->rec,
                       &st->rec_offs, &st->rec_tmp, &st->rec_lens, &st->canon_tmp, &st->out_tmp};
     for (DevBuf *b : bufs)
         if (b->p) {
@@ -667,6 +722,13 @@ void free_state(DeviceState *st) {
         }
     if (st->ev0) (void)hipEventDestroy(st->ev0);
     if (st->ev1) (void)hipEventDestroy(st->ev1);
+    if (st->fork) {
+        (void)hipEventDestroy(st->fork);
+        for (int c = 0; c < 5; ++c) {
+            (void)hipEventDestroy(st->join[c]);
+            (void)hipStreamDestroy(st->cls_stream[c]);
+        }
+    }
 }
 
 }  // namespace

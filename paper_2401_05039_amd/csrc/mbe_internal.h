@@ -44,8 +44,9 @@ enum FlagBits : unsigned int {
     FLAG_BAD_GRAPH = 1u << 3,          // validation failure
     FLAG_DEGREE = 1u << 4,             // candidate degree above the supported mask width
     FLAG_UNIVERSE_OVERFLOW = 1u << 5,  // a local universe or its posting lists did not fit
+    FLAG_NO_SLOT = 1u << 6,            // a workgroup found no free arena slot: rerun one class at a time
 };
-constexpr unsigned int FLAG_RERUN = FLAG_STACK_OVERFLOW | FLAG_DEPTH_OVERFLOW | FLAG_UNIVERSE_OVERFLOW;
+constexpr unsigned int FLAG_RERUN = FLAG_STACK_OVERFLOW | FLAG_DEPTH_OVERFLOW | FLAG_UNIVERSE_OVERFLOW | FLAG_NO_SLOT;
 
 // Capacities of the search arena.
 struct SearchDims {
@@ -120,8 +121,10 @@ struct SearchArgs {
     char *arena;
     SearchDims dims;
     ArenaLayout lay;
-    StealSlot *steal;           // one per workgroup, zeroed before each launch
+    StealSlot *steal;           // one per arena slot for this launch's mask class, zeroed first
     int32_t steal_on;           // 0: no stealing (each top-level candidate stays in one workgroup)
+    int32_t nslots;             // arena slots shared by the concurrent launches
+    unsigned int *slot_busy;    // nslots flags: a slot is held by a running workgroup
     // outputs
     unsigned long long *acc;    // run-wide slots (overflow sizes, record cursors)
     unsigned int *flags;
@@ -134,6 +137,9 @@ struct SearchArgs {
 
 // Arena layout for the given capacities (host side).
 ArenaLayout search_layout(const SearchDims &d);
+
+// Workgroups of one search launch that fit on a compute unit at once.
+int search_occupancy(int W, bool diag, bool enumerate, int waves);
 
 // Launch the search over tasks [lo, hi) of the work list (or ranks [lo, hi) of graph 0 when
 // it is NULL), all of whose top-level candidates have degree at most 64*W.  counter must be

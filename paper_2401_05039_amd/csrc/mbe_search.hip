@@ -757,6 +757,7 @@ struct WGShared {
     unsigned int epoch;
     int gclaim; // chunks are claimed through the global steal slot
     int sg, sk; // graph and rank of a stolen task
+    int slot;   // arena slot held by this workgroup
     int scan[16];
     unsigned long long red[16];  // per-graph tally reduction
 };
@@ -851,7 +852,22 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     const int tid = threadIdx.x, nt = blockDim.x, wid = tid >> 6, nw = nt >> 6, ln = lane_id();
     constexpr int BITS = 64 * W;
 
-    char *wg = a.arena + (size_t)blockIdx.x * a.lay.wg_bytes;
+    // take a free arena slot (the launches of all mask classes share the slots; there are as
+    // many as workgroups that can be resident at once, so one is always free)
+    if (threadIdx.x == 0) {
+        int got = -1;
+        for (int round = 0; round < 64 && got < 0; ++round)
+            for (int j = 0; j < a.nslots && got < 0; ++j) {
+                const int sidx = (int)((blockIdx.x + (unsigned)j) % (unsigned)a.nslots);
+                if (atomicCAS(&a.slot_busy[sidx], 0u, 1u) == 0u) got = sidx;
+            }
+        reinterpret_cast<WGShared *>(lds_raw)->slot = got;
+        if (got < 0) atomicOr(a.flags, (unsigned int)FLAG_NO_SLOT);
+    }
+    __syncthreads();
+    const int my_slot = reinterpret_cast<WGShared *>(lds_raw)->slot;
+    if (my_slot < 0) return;
+    char *wg = a.arena + (size_t)my_slot * a.lay.wg_bytes;
     uint64_t *bitmap = reinterpret_cast<uint64_t *>(wg + a.lay.off_bitmap);
     uint32_t *bpre = reinterpret_cast<uint32_t *>(wg + a.lay.off_bpre);
     uint64_t *M = reinterpret_cast<uint64_t *>(wg + a.lay.off_M);
@@ -922,8 +938,8 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                     sh->task = t;
                     sh->epoch = t + 1u;
                 } else if (a.steal_on) {
-                    for (int j = 1; j < (int)gridDim.x && sh->mode == 0; ++j) {
-                        const int vwg = (int)((blockIdx.x + j) % gridDim.x);
+                    for (int j = 1; j < a.nslots && sh->mode == 0; ++j) {
+                        const int vwg = (my_slot + j) % a.nslots;
                         StealSlot *sl = &a.steal[vwg];
                         const unsigned long long w1 = __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                         const unsigned int e = (unsigned int)(w1 >> 32);
@@ -1263,7 +1279,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
 
         // -- share the child list: with more than one chunk, claims go through the global
         //    steal slot so that idle workgroups can take chunks (they rebuild the same list)
-        StealSlot *slot = thief ? &a.steal[sh->victim] : &a.steal[blockIdx.x];
+        StealSlot *slot = thief ? &a.steal[sh->victim] : &a.steal[my_slot];
         if (tid == 0) {
             if (thief) {
                 sh->gclaim = 1;
@@ -1356,6 +1372,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
 
     // tallies of the last graph
     if (sh->graph >= 0) flush_acc<DIAG>(acc, a.graphs[sh->graph].acc, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicExch(&a.slot_busy[my_slot], 0u);
+    }
 }
 
 size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + (size_t)waves * (64 * W * sizeof(uint32_t) + 1280); }
@@ -1378,7 +1399,34 @@ hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, 
 
 size_t align_up(size_t x, size_t al) { return (x + al - 1) / al * al; }
 
+template <int W, bool DIAG, bool ENUM>
+int occ(int waves) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search_kernel<W, DIAG, ENUM>, 64 * waves, lds_bytes(W, waves)) !=
+        hipSuccess)
+        return 2;
+    return nb > 0 ? nb : 1;
+}
+
+template <int W>
+int occ_w(bool diag, bool enumerate, int waves) {
+    if (diag && enumerate) return occ<W, true, true>(waves);
+    if (diag) return occ<W, true, false>(waves);
+    if (enumerate) return occ<W, false, true>(waves);
+    return occ<W, false, false>(waves);
+}
+
 }  // namespace
+
+int search_occupancy(int W, bool diag, bool enumerate, int waves) {
+    switch (W) {
+        case 1: return occ_w<1>(diag, enumerate, waves);
+        case 2: return occ_w<2>(diag, enumerate, waves);
+        case 4: return occ_w<4>(diag, enumerate, waves);
+        case 8: return occ_w<8>(diag, enumerate, waves);
+        default: return occ_w<16>(diag, enumerate, waves);
+    }
+}
 
 ArenaLayout search_layout(const SearchDims &d) {
     ArenaLayout L{};
