@@ -109,6 +109,20 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 
 __device__ __forceinline__ uint32_t align2(uint32_t x) { return (x + 1u) & ~1u; }
 
+// Global atomics are performed in L2, so a plain load issued after them may still be served
+// from a stale line in this compute unit's vector L1, or overtake them.  After a phase that
+// builds data with global atomics (and its barrier, if other waves read it), every reading
+// wave waits for its memory operations and invalidates the L1.  The data involved is private
+// to one workgroup, hence on one compute unit and one L2: the L2 stays valid.
+// Wait until this wave's memory operations are done, so that plain stores made by some
+// lanes are in place before other lanes load them.
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ void see_atomics() {
+    __builtin_amdgcn_s_waitcnt(0);
+    asm volatile("buffer_inv sc0" ::: "memory");
+}
+
 // ------------------------------------------------------------------------------ frames
 
 // Registers of the frame a wave is working on; saved whole in the header array on descent.
@@ -282,7 +296,7 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
         v.cnt[b] = 0u;
         v.H[b] = 0ull;
     }
-    __threadfence_block();
+    wait_mem();
     for (int base = 0; base < n; base += 64) {
         const int k = base + ln;
         if (k < n) {
@@ -300,7 +314,7 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
             }
         }
     }
-    __threadfence_block();
+    see_atomics();
     int carry = 0;
     for (int base = 0; base < bits; base += 64) {
         const int b = base + ln;
@@ -311,7 +325,7 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
         carry += __shfl(incl, 63);
     }
     if (ln == 0) v.ptr[bits] = (uint32_t)carry;
-    __threadfence_block();
+    wait_mem();
     for (int base = 0; base < n; base += 64) {
         const int k = base + ln;
         if (k < n) {
@@ -326,7 +340,7 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
             }
         }
     }
-    __threadfence_block();
+    wait_mem();
 }
 
 // Tables of a narrow frame (one mask word per entry), accumulated in the wave's LDS scratch
@@ -372,7 +386,7 @@ __device__ void build_tables_narrow(const Ctx &c, const FrameView &v, int n) {
             }
         }
     }
-    __threadfence_block();
+    wait_mem();
 }
 
 // Write the record of the maximal biclique (L', R') of a node.  R' is given as positions of
@@ -574,16 +588,14 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
             }
         }
     }
-    __threadfence_block();
+    see_atomics();
     int nu = 0;
     const int nwords_n = (F.n + 63) >> 6;
     for (int base = 0; base < nwords_n; base += 64) {
         const int wd = base + ln;
         uint64_t bits = 0;
-        if (wd < nwords_n) {
-            bits = c.ubm[wd];
-            if (bits) c.ubm[wd] = 0ull;
-        }
+        // read and clear each word in L2, where the marks were made
+        if (wd < nwords_n) bits = atomicExch(reinterpret_cast<unsigned long long *>(&c.ubm[wd]), 0ull);
         const int pc = __popcll(bits);
         const int incl = wave_incl_scan(pc);
         int at = nu + incl - pc;
@@ -594,7 +606,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         }
         nu += __shfl(incl, 63);
     }
-    __threadfence_block();
+    wait_mem();
     for (int base = 0; base < nu; base += 64) {
         const int j = base + ln;
         const bool act = j < nu;
@@ -623,6 +635,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         qn += __popcll(qb);
         pn += __popcll(pb);
     }
+    wait_mem();  // the staged Q' / P' entries are read by other lanes below
 
     // report (L', R')
     const uint64_t sL = F.sL + hl(c, c.gid[v.ids[i]]) + wave_sum_u64(exps);
@@ -718,7 +731,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         if (j < qn) put((uint32_t)j, c.stq[j]);
     }
     wave_sort_by_key(c.stp, c.stc, pn, r, c.hist, [&](uint32_t slot, uint32_t k) { put((uint32_t)qn + slot, k); });
-    __threadfence_block();
+    wait_mem();
     if (narrow) build_tables_narrow(c, v2, n2);
     else build_tables<W>(c, v2, n2, c.cur);
 
@@ -896,6 +909,10 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     c.cur = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_cur);
     c.stu = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_u);
     c.ubm = reinterpret_cast<uint64_t *>(wv + a.lay.off_w_bm);
+    // the position bitmap must start out clear: the slot's memory may hold an earlier call's
+    // data under another layout
+    for (int wd = ln; wd < (a.dims.ucap + 63) / 64; wd += 64) c.ubm[wd] = 0ull;
+    wait_mem();
     c.hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * BITS;
     {
         // narrow-child table scratch: first[64] cnt[64] cur[64] (u32) then H[64] (u64) per wave
@@ -1039,8 +1056,8 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             sh->claim = 0;
             sh->gclaim = 0;
         }
-        __threadfence_block();
         __syncthreads();
+        see_atomics();  // the rank bitmap was built with atomics
         hv_local = wave_sum_u64(hv_local);
         rs_local = wave_sum_u64(rs_local);
         if (ln == 0) {
@@ -1050,7 +1067,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
 
         // -- universe numbering: prefix of bitmap popcounts (rank order)
         block_popcount_prefix(bitmap, bpre, nwords, sh);
-        __threadfence_block();
+        wait_mem();
         __syncthreads();
         const int s0 = sh->s0;
         if (s0 > ucap) {
@@ -1080,7 +1097,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             }
         }
         for (size_t q = tid; q < (size_t)s0 * W; q += nt) M[q] = 0ull;
-        __threadfence_block();
+        wait_mem();
         __syncthreads();
 
         // -- reverse scan 2: M[v] gets bit j for every w_j in N(x) adjacent to v
@@ -1097,8 +1114,8 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 }
             }
         }
-        __threadfence_block();
         __syncthreads();
+        see_atomics();  // M was built with atomics
 
         // -- the top-level node for x: counts, maximality against earlier ranks, expansion
         for (int wd = tid; wd < nwords; wd += nt) bitmap[wd] = 0ull;
@@ -1143,7 +1160,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 atomicAdd(reinterpret_cast<unsigned long long *>(&sh->post1), (unsigned long long)post);
             }
         }
-        __threadfence_block();
+        wait_mem();
         __syncthreads();
         const bool root_nonmax = sh->nonmax != 0;
         const int P1 = sh->pcount;
@@ -1220,7 +1237,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 }
                 pn += __popcll(pb);
             }
-            __threadfence_block();
+            wait_mem();
             wave_sort_by_key(t1v, t1c, pn, d, c.hist, [&](uint32_t slot, uint32_t li) { ids1[nq0 + slot] = li; });
         }
         for (int b = tid; b < BITS; b += nt) {
@@ -1228,7 +1245,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             v1.cnt[b] = 0u;
             v1.H[b] = 0ull;
         }
-        __threadfence_block();
+        wait_mem();
         __syncthreads();
         uint64_t *masks1 = const_cast<uint64_t *>(v1.masks);
         for (int j = tid; j < n1; j += nt) {
@@ -1247,8 +1264,8 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 }
             }
         }
-        __threadfence_block();
         __syncthreads();
+        see_atomics();  // the top-level tables were built with atomics
         if (wid == 0) {
             int carry = 0;
             for (int base = 0; base < BITS; base += 64) {
@@ -1261,7 +1278,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             }
             if (ln == 0) v1.ptr[BITS] = (uint32_t)carry;
         }
-        __threadfence_block();
+        wait_mem();
         __syncthreads();
         for (int j = tid; j < n1; j += nt) {
 #pragma unroll
@@ -1274,7 +1291,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 }
             }
         }
-        __threadfence_block();
+        wait_mem();
         __syncthreads();
 
         // -- share the child list: with more than one chunk, claims go through the global
@@ -1356,7 +1373,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                     break;
                 }
                 hdr[depth] = cur;  // every lane stores the same header
-                __threadfence_block();
+                wait_mem();
                 ++depth;
                 cur = ch;
             } else if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_STACK_OVERFLOW) {
