@@ -74,6 +74,9 @@ struct ArenaLayout {
     size_t off_t1c;     // u32[ucap]            sort staging (keys)
     size_t off_cur1;    // u32[64*Wmax]         posting cursors
     size_t off_S1;      // u32[s1_words]        the top-level node's child list as a frame
+    size_t off_hb;      // u64[ucap/64+1]       top-level candidates with |R'| >= 2, per chunk
+    size_t off_hpre;    // u32[ucap/64+2]       popcount prefix of those words
+    size_t off_hpos;    // u32[ucap]            their positions, in list order
     size_t s1_words;
     size_t off_waves;   // start of the per-wave regions
     size_t wave_bytes;  // stride between waves

@@ -69,17 +69,27 @@ __device__ __forceinline__ uint64_t pair_hash(int c_is_v, uint64_t sL, uint64_t 
 }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Wave-uniform values moved to scalar registers (the value of the first active lane; only
+// for values every lane holds alike).
+__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t uni(uint64_t x) {
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | (uint64_t)uni((uint32_t)x);
+}
+// lane 63's value (a wave-wide scan total) in a scalar register
+__device__ __forceinline__ int last_lane(int x) { return __builtin_amdgcn_readlane(x, 63); }
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return uni(v);
 }
 __device__ __forceinline__ int wave_sum_i32(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return uni(v);
 }
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
@@ -87,7 +97,7 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
         const uint32_t t = __shfl_xor(v, o);
         v = t < v ? t : v;
     }
-    return v;
+    return uni(v);
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
@@ -95,7 +105,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
         const uint32_t t = __shfl_xor(v, o);
         v = t > v ? t : v;
     }
-    return v;
+    return uni(v);
 }
 __device__ __forceinline__ int wave_incl_scan(int v) {
     const int ln = lane_id();
@@ -141,6 +151,24 @@ struct FrameState {
     uint64_t sL;     // sum of the L-side hash terms of L
     uint64_t fw;     // sum over the list of (2 + deg v), byte tally only
 };
+
+__device__ __forceinline__ FrameState uni_frame(const FrameState &f) {
+    FrameState u;
+    u.off = uni(f.off);
+    u.top = uni(f.top);
+    u.n = uni(f.n);
+    u.nq = uni(f.nq);
+    u.level = uni(f.level);
+    u.nL = uni(f.nL);
+    u.wf = uni(f.wf);
+    u.narrow = uni(f.narrow);
+    u.chunk = uni(f.chunk);
+    u.pad = 0;
+    u.heavy = uni(f.heavy);
+    u.sL = uni(f.sL);
+    u.fw = uni(f.fw);
+    return u;
+}
 
 // Word layout of a frame's data starting at a 2-aligned offset o:
 //   ids[n] | masks[n][wf] (u64) | first[64wf] | cnt[64wf] | H[64wf] (u64) | ptr[64wf+1] |
@@ -259,7 +287,7 @@ __device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, in
         const int h = b < nbins ? (int)hist[b] : 0;
         const int incl = wave_incl_scan(h);
         if (b < nbins) hist[b] = (uint32_t)(carry + incl - h);
-        carry += __shfl(incl, 63);
+        carry += last_lane(incl);
     }
     __builtin_amdgcn_wave_barrier();
     const int nbits = nbins <= 1 ? 1 : 32 - __clz(nbins - 1);
@@ -322,7 +350,7 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
         const int incl = wave_incl_scan(h);
         v.ptr[b] = (uint32_t)(carry + incl - h);
         cursor[b] = (uint32_t)(carry + incl - h);
-        carry += __shfl(incl, 63);
+        carry += last_lane(incl);
     }
     if (ln == 0) v.ptr[bits] = (uint32_t)carry;
     wait_mem();
@@ -442,7 +470,8 @@ __device__ void write_record(const Ctx &c, const uint64_t *Rr, int nL, int r) {
 // Candidates [base, base+64) of frame F: lanes with |R'| = 1 are settled here; the rest are
 // returned as a lane mask.
 template <int WF, bool DIAG, bool ENUM>
-__device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameView &v, int base, WaveAcc &acc) {
+__device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameView &v, int base, WaveAcc &acc,
+                                bool settle = true) {
     const int ln = lane_id();
     const int i = base + ln;
     const bool act = i < F.n;
@@ -454,7 +483,7 @@ __device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameVi
         r += __popcll(m[w]);
     }
     if (ENUM) return __ballot(act);
-    const bool light = act && r == 1;
+    const bool light = settle && act && r == 1;
     if (light) {
         int b = 0;
 #pragma unroll
@@ -493,7 +522,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     int r = 0;
 #pragma unroll
     for (int w = 0; w < WF; ++w) {
-        m[w] = v.masks[(size_t)i * WF + w];  // R' (uniform)
+        m[w] = uni(v.masks[(size_t)i * WF + w]);  // R' (uniform)
         r += __popcll(m[w]);
     }
 
@@ -604,7 +633,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
             bits &= bits - 1ull;
             c.stu[at++] = (uint32_t)(wd * 64 + b);
         }
-        nu += __shfl(incl, 63);
+        nu += last_lane(incl);
     }
     wait_mem();
     for (int base = 0; base < nu; base += 64) {
@@ -813,15 +842,15 @@ __device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) 
     acc = WaveAcc{};
 }
 
-// Claim the next 64-candidate chunk of a published top-level list: returns the chunk's
-// offset, or -1 once the list is used up or its owner has moved on (epoch changed).
-__device__ int claim_chunk(unsigned long long *word, unsigned int epoch, int limit) {
+// Claim the next step items of a published list: returns the first one's index, or -1 once
+// the list is used up or its owner has moved on (epoch changed).
+__device__ int claim_chunk(unsigned long long *word, unsigned int epoch, int limit, unsigned int step) {
     unsigned long long old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         if ((unsigned int)(old >> 32) != epoch) return -1;
         const unsigned int got = (unsigned int)old;
         if ((int)got >= limit) return -1;
-        const unsigned long long prev = atomicCAS(word, old, old + 64ull);
+        const unsigned long long prev = atomicCAS(word, old, old + (unsigned long long)step);
         if (prev == old) return (int)got;
         old = prev;
     }
@@ -862,7 +891,7 @@ template <int W, bool DIAG, bool ENUM>
 __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
     extern __shared__ unsigned char lds_raw[];
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
-    const int tid = threadIdx.x, nt = blockDim.x, wid = tid >> 6, nw = nt >> 6, ln = lane_id();
+    const int tid = threadIdx.x, nt = blockDim.x, wid = uni(tid >> 6), nw = nt >> 6, ln = lane_id();
     constexpr int BITS = 64 * W;
 
     // take a free arena slot (the launches of all mask classes share the slots; there are as
@@ -892,6 +921,9 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     uint32_t *t1c = reinterpret_cast<uint32_t *>(wg + a.lay.off_t1c);
     uint32_t *cur1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_cur1);
     uint32_t *s1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_S1);
+    uint64_t *hb = reinterpret_cast<uint64_t *>(wg + a.lay.off_hb);
+    uint32_t *hpre = reinterpret_cast<uint32_t *>(wg + a.lay.off_hpre);
+    uint32_t *hpos = reinterpret_cast<uint32_t *>(wg + a.lay.off_hpos);
     char *wv = wg + a.lay.off_waves + (size_t)wid * a.lay.wave_bytes;
     FrameState *hdr = reinterpret_cast<FrameState *>(wv + a.lay.off_w_hdr);
 
@@ -967,7 +999,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                         __threadfence();
                         const unsigned long long w2 = __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                         if ((unsigned int)(w2 >> 32) != e) continue;       // owner moved on meanwhile
-                        if ((int)(unsigned int)w2 + 128 > lim) continue;   // under two chunks left
+                        if ((int)(unsigned int)w2 + 2 > lim) continue;     // under two items left
                         sh->mode = 2;
                         sh->victim = vwg;
                         sh->epoch = e;
@@ -1274,7 +1306,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 const int incl = wave_incl_scan(h);
                 v1.ptr[b] = (uint32_t)(carry + incl - h);
                 cur1[b] = (uint32_t)(carry + incl - h);
-                carry += __shfl(incl, 63);
+                carry += last_lane(incl);
             }
             if (ln == 0) v1.ptr[BITS] = (uint32_t)carry;
         }
@@ -1294,16 +1326,57 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         wait_mem();
         __syncthreads();
 
-        // -- share the child list: with more than one chunk, claims go through the global
-        //    steal slot so that idle workgroups can take chunks (they rebuild the same list)
+        // -- top-level light pass: chunks of P1 are split over the waves; candidates with
+        //    |R'| = 1 are settled here (by the owner only), and those with |R'| >= 2 are
+        //    flagged per chunk.  Their ordered list hpos depends on the list alone, so a
+        //    thief that rebuilt the list finds the same items at the same indices.
+        FrameState top;
+        top.off = kShared;
+        top.top = 0;
+        top.n = n1;
+        top.nq = nq0;
+        top.level = 2;
+        top.nL = 1 + sh->nexp;
+        top.wf = W;
+        top.narrow = 0;
+        top.chunk = 0;
+        top.pad = 0;
+        top.heavy = 0ull;
+        top.sL = hl(c, x) + sh->exps;
+        top.fw = sh->fw1;
+        const int nch = (P1 + 63) >> 6;
+        for (int q = wid; q < nch; q += nw) {
+            const uint64_t tl = DIAG ? clock64() : 0ull;
+            const uint64_t hm = light_chunk<W, DIAG, ENUM>(c, top, v1, nq0 + 64 * q, acc, !thief);
+            if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
+            if (ln == 0) hb[q] = hm;
+        }
+        wait_mem();
+        __syncthreads();
+        block_popcount_prefix(hb, hpre, nch, sh);
+        for (int q = tid; q < nch; q += nt) {
+            uint64_t bits = hb[q];
+            uint32_t at = hpre[q];
+            while (bits) {
+                const int bb = __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1ull;
+                hpos[at++] = (uint32_t)(nq0 + 64 * q + bb);
+            }
+        }
+        wait_mem();
+        __syncthreads();
+        const int H = sh->s0;
+
+        // -- share the items: with more than one per wave, claims go through the global steal
+        //    slot so that idle workgroups can take some (they rebuild the same list)
         StealSlot *slot = thief ? &a.steal[sh->victim] : &a.steal[my_slot];
         if (tid == 0) {
             if (thief) {
                 sh->gclaim = 1;
-            } else if (a.steal_on && P1 > 64) {
+            } else if (a.steal_on && H > nw) {
                 slot->g = g;
                 slot->k = (int)k;
-                slot->limit = P1;
+                slot->limit = H;
                 __threadfence();
                 __hip_atomic_store(&slot->word, (unsigned long long)sh->epoch << 32, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -1319,61 +1392,51 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             t_mark = now;
         }
 
-        // -- second level and below: waves claim 64-candidate chunks of the top-level list
-        //    and search depth-first from them
-        FrameState cur;
-        cur.off = kShared;
-        cur.top = 0;
-        cur.n = n1;
-        cur.nq = nq0;
-        cur.level = 2;
-        cur.nL = 1 + sh->nexp;
-        cur.wf = W;
-        cur.narrow = 0;
-        cur.chunk = 0;
-        cur.pad = 0;
-        cur.heavy = 0ull;
-        cur.sL = hl(c, x) + sh->exps;
-        cur.fw = sh->fw1;
+        // -- second level and below: each wave claims one top-level item at a time, expands
+        //    it and searches depth-first below it
+        FrameState cur = top;
         int depth = 0;
         while (!aborted) {
             const FrameView v = frame_view(frame_base(c, cur.off), cur.n, cur.wf);
-            if (cur.heavy == 0ull) {
-                int base;
-                if (depth == 0) {
-                    int got = 0;
-                    if (ln == 0) got = gclaim ? claim_chunk(&slot->word, epoch, P1) : atomicAdd(&sh->claim, 64);
-                    got = __shfl(got, 0);
-                    base = got < 0 ? cur.n : got + nq0;
-                } else {
-                    base = cur.chunk + 64;
-                }
-                if (base >= cur.n) {
-                    if (depth == 0) break;
-                    --depth;
-                    cur = hdr[depth];
+            int i;
+            if (depth == 0) {
+                int got = 0;
+                if (ln == 0) got = gclaim ? claim_chunk(&slot->word, epoch, H, 1u) : atomicAdd(&sh->claim, 1);
+                got = __builtin_amdgcn_readlane(got, 0);
+                if (got < 0 || got >= H) break;
+                i = (int)uni(hpos[got]);
+            } else {
+                if (cur.heavy == 0ull) {
+                    const int base = cur.chunk + 64;
+                    if (base >= cur.n) {
+                        --depth;
+                        cur = depth > 0 ? uni_frame(hdr[depth]) : top;
+                        continue;
+                    }
+                    cur.chunk = base;
+                    const uint64_t tl = DIAG ? clock64() : 0ull;
+                    cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM>(c, cur, v, base, acc)
+                                              : light_chunk<W, DIAG, ENUM>(c, cur, v, base, acc);
+                    if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
                     continue;
                 }
-                cur.chunk = base;
-                const uint64_t tl = DIAG ? clock64() : 0ull;
-                cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM>(c, cur, v, base, acc)
-                                          : light_chunk<W, DIAG, ENUM>(c, cur, v, base, acc);
-                if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
-                continue;
+                const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
+                cur.heavy &= cur.heavy - 1ull;
+                i = cur.chunk + lane;
             }
-            const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
-            cur.heavy &= cur.heavy - 1ull;
             FrameState ch;
-            const bool pushed = (cur.wf == 1) ? heavy_node<1, W, DIAG, ENUM>(c, cur, v, cur.chunk + lane, ch, acc)
-                                              : heavy_node<W, W, DIAG, ENUM>(c, cur, v, cur.chunk + lane, ch, acc);
+            const bool pushed = (cur.wf == 1) ? heavy_node<1, W, DIAG, ENUM>(c, cur, v, i, ch, acc)
+                                              : heavy_node<W, W, DIAG, ENUM>(c, cur, v, i, ch, acc);
             if (pushed) {
                 if (depth >= a.dims.maxdepth) {
                     if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
                     aborted = true;
                     break;
                 }
-                hdr[depth] = cur;  // every lane stores the same header
-                wait_mem();
+                if (depth > 0) {
+                    hdr[depth] = cur;  // every lane stores the same header
+                    wait_mem();
+                }
                 ++depth;
                 cur = ch;
             } else if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_STACK_OVERFLOW) {
@@ -1467,6 +1530,9 @@ ArenaLayout search_layout(const SearchDims &d) {
     // ids | masks | first | cnt | H | ptr | orig | post (see frame_view)
     L.s1_words = align_up(ucap, 2) + 2 * ucap * W + 2 * bits + 2 * bits + bits + 1 + 64 + (size_t)d.post_cap + 2;
     L.off_S1 = take(L.s1_words * 4);
+    L.off_hb = take((ucap / 64 + 1) * 8);
+    L.off_hpre = take((ucap / 64 + 2) * 4);
+    L.off_hpos = take(ucap * 4);
     L.off_waves = o;
     size_t w = 0;
     auto wtake = [&](size_t bytes) {
