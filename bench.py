@@ -183,6 +183,9 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a reference "
+                         "kernel of known traffic for scaling hardware byte counters)")
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--serve-n", type=int, default=400)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -211,6 +214,15 @@ def main():
     import graphgen as gg
     dg = gg.BiGraph(g.n_u, g.n_v, *[torch.from_numpy(np.asarray(a)).to(dev) for a in
                                     (g.u_off, g.u_adj, g.v_off, g.v_adj)])
+    if args.copy_mib > 0:
+        n = args.copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes")
+        del src, dst
     lo, hi = rng_range if rng_range else (0, 0)
     base = dict(wg_waves=args.waves, grid=args.grid, root_lo=lo, root_hi=hi)
 

@@ -51,6 +51,10 @@ namespace {
 constexpr uint64_t kHashK = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kShared = 0xFFFFFFFFu;  // frame offset meaning "the workgroup's top-level list"
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// A maximal node scans its whole list when the list is at most kScanFactor times the total
+// length of R''s posting lists plus kScanMin entries; otherwise it walks those lists.
+constexpr int kScanFactor = 4;
+constexpr int kScanMin = 512;
 
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -511,6 +515,80 @@ __device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameVi
     return __ballot(act && r >= 2);
 }
 
+// Write the child frame of a maximal node at the top of the wave's stack: Q' (staged in stq,
+// list order) then P' (staged in stp / stc) stably sorted by count, each entry's mask
+// restricted to R' -- compressed to |R'| bits when NARROW -- and the per-bit tables.  Sets
+// the layout fields of C; false when the stack is full.
+template <int WF, int W, bool NARROW>
+__device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int qn,
+                            int pn, int r, uint32_t post2, FrameState &C) {
+    const int ln = lane_id();
+    const int n2 = qn + pn;
+    constexpr int wf2 = NARROW ? 1 : W;
+    const uint32_t off2 = F.top;
+    const uint32_t top2 = align2(off2 + frame_words_fixed(n2, wf2) + post2);
+    if ((int64_t)top2 > c.scap) {
+        if (ln == 0) atomicOr(c.flags, (unsigned int)FLAG_STACK_OVERFLOW);
+        return false;
+    }
+    uint32_t *cb = c.stk + off2;
+    uint32_t *ids2 = cb;
+    uint64_t *masks2 = reinterpret_cast<uint64_t *>(cb + align2((uint32_t)n2));
+    FrameView v2 = frame_view(cb, n2, wf2);
+    if (NARROW) {
+        // orig2[t] = N(x_root) position of the t-th bit of R'
+        const uint64_t below = lanes_below();
+        int t0 = 0;
+#pragma unroll
+        for (int w = 0; w < WF; ++w) {
+            const bool on = (m[w] >> ln) & 1ull;
+            const uint64_t bb = __ballot(on);
+            if (on) v2.orig[t0 + __popcll(bb & below)] = root_pos(F, v, (uint32_t)(64 * w + ln));
+            t0 += __popcll(bb);
+        }
+    }
+    auto put = [&](uint32_t slot, uint32_t k) {
+        ids2[slot] = v.ids[k];
+        if (NARROW) {
+            uint64_t out = 0;
+            int t = 0;
+#pragma unroll
+            for (int w = 0; w < WF; ++w) {
+                uint64_t mm = m[w];
+                const uint64_t xx = v.masks[(size_t)k * WF + w];
+                while (mm) {  // the same trip count on every lane: m is uniform
+                    const int p = __ffsll((unsigned long long)mm) - 1;
+                    mm &= mm - 1ull;
+                    out |= ((xx >> p) & 1ull) << t;
+                    ++t;
+                }
+            }
+            masks2[slot] = out;
+        } else {
+#pragma unroll
+            for (int w = 0; w < WF; ++w) masks2[(size_t)slot * W + w] = v.masks[(size_t)k * WF + w] & m[w];
+        }
+    };
+    for (int base = 0; base < qn; base += 64) {
+        const int j = base + ln;
+        if (j < qn) put((uint32_t)j, c.stq[j]);
+    }
+    wave_sort_by_key(c.stp, c.stc, pn, r, c.hist, [&](uint32_t slot, uint32_t k) { put((uint32_t)qn + slot, k); });
+    wait_mem();
+    if (NARROW) build_tables_narrow(c, v2, n2);
+    else build_tables<W>(c, v2, n2, c.cur);
+    C.off = off2;
+    C.top = top2;
+    C.n = n2;
+    C.nq = qn;
+    C.wf = wf2;
+    C.narrow = NARROW ? 1 : 0;
+    C.chunk = qn - 64;
+    C.pad = 0;
+    C.heavy = 0ull;
+    return true;
+}
+
 // The candidate at position i of frame F, |R'| = r >= 1, handled by the whole wave.
 // Returns true when a child frame was written (its state in C).
 template <int WF, int W, bool DIAG, bool ENUM>
@@ -530,11 +608,13 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     // first appears at i itself, nothing earlier can hold R'.
     bool first_here = false;
     uint32_t best = 0xFFFFFFFFu;  // (count << 12 | bit) of the rarest bit
+    uint32_t inc = 0;             // posting-list entries of this lane's bits
 #pragma unroll
     for (int w = 0; w < WF; ++w) {
         if ((m[w] >> ln) & 1ull) {
             const int b = 64 * w + ln;
             if (v.first[b] == (uint32_t)i) first_here = true;
+            inc += v.cnt[b];
             const uint32_t cb = v.cnt[b] < 0xFFFFFu ? v.cnt[b] : 0xFFFFFu;  // saturate: b stays exact
             const uint32_t key = (cb << 12) | (uint32_t)b;
             best = key < best ? key : best;
@@ -589,65 +669,23 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         return false;
     }
 
-    // maximal: the entries sharing a bit with R' are the union of R''s posting lists.  Each
-    // is taken once (from the list of its lowest bit in R'), marked in a position bitmap,
-    // and the bitmap is read back in list order, which keeps the stable tie order of P'.
+    // maximal: classify every entry sharing a bit with R' (list order is kept, so P' keeps
+    // the stable tie order).  Short lists are scanned whole with coalesced loads; otherwise
+    // the entries are the union of R''s posting lists: each is taken once (from the list of
+    // its lowest bit in R'), marked in a position bitmap, and the bitmap is read back in
+    // list order.
     int qn = 0, pn = 0, ne = 0;
     uint64_t exps = 0, fwc = 0;
     uint32_t csum = 0;
-#pragma unroll
-    for (int w = 0; w < WF; ++w) {
-        uint64_t mb = m[w];
-        while (mb) {  // uniform loop over the bits of R'
-            const int bit = __ffsll((unsigned long long)mb) - 1;
-            mb &= mb - 1ull;
-            const int b = 64 * w + bit;
-            const uint32_t p0 = v.ptr[b], p1 = v.ptr[b + 1];
-            for (uint32_t q = p0 + (uint32_t)ln; q < p1; q += 64) {
-                const uint32_t p = v.post[q];
-                if ((int)p == i) continue;
-                // lowest bit of mask[p] & R'
-                int low = -1;
-#pragma unroll
-                for (int ww = 0; ww < WF; ++ww) {
-                    const uint64_t x = v.masks[(size_t)p * WF + ww] & m[ww];
-                    if (low < 0 && x) low = 64 * ww + __ffsll((unsigned long long)x) - 1;
-                }
-                if (low == b) atomicOr(reinterpret_cast<unsigned long long *>(&c.ubm[p >> 6]), 1ull << (p & 63));
-            }
-        }
-    }
-    see_atomics();
-    int nu = 0;
-    const int nwords_n = (F.n + 63) >> 6;
-    for (int base = 0; base < nwords_n; base += 64) {
-        const int wd = base + ln;
-        uint64_t bits = 0;
-        // read and clear each word in L2, where the marks were made
-        if (wd < nwords_n) bits = atomicExch(reinterpret_cast<unsigned long long *>(&c.ubm[wd]), 0ull);
-        const int pc = __popcll(bits);
-        const int incl = wave_incl_scan(pc);
-        int at = nu + incl - pc;
-        while (bits) {
-            const int b = __ffsll((unsigned long long)bits) - 1;
-            bits &= bits - 1ull;
-            c.stu[at++] = (uint32_t)(wd * 64 + b);
-        }
-        nu += last_lane(incl);
-    }
-    wait_mem();
-    for (int base = 0; base < nu; base += 64) {
-        const int j = base + ln;
-        const bool act = j < nu;
-        int k = 0, cnt = 0;
+    auto classify = [&](int k, bool act) {
+        int cnt = 0;
         if (act) {
-            k = (int)c.stu[j];
 #pragma unroll
             for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
         }
-        const bool inq = act && k < i;  // 0 < cnt < r: the node passed the check
+        const bool inq = act && k < i && cnt > 0;  // cnt < r: the node passed the check
         const bool full = act && k > i && cnt == r;
-        const bool inp = act && k > i && cnt < r;
+        const bool inp = act && k > i && cnt > 0 && cnt < r;
         if (full) exps += hl(c, c.gid[v.ids[k]]);
         ne += __popcll(__ballot(full));
         const uint64_t qb = __ballot(inq), pb = __ballot(inp);
@@ -663,6 +701,60 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         }
         qn += __popcll(qb);
         pn += __popcll(pb);
+    };
+    const int incidences = wave_sum_i32((int)inc);
+    if (F.n <= kScanFactor * incidences + kScanMin) {
+        for (int base = 0; base < F.n; base += 64) {
+            const int k = base + ln;
+            classify(k, k < F.n && k != i);
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < WF; ++w) {
+            uint64_t mb = m[w];
+            while (mb) {  // uniform loop over the bits of R'
+                const int bit = __ffsll((unsigned long long)mb) - 1;
+                mb &= mb - 1ull;
+                const int b = 64 * w + bit;
+                const uint32_t p0 = v.ptr[b], p1 = v.ptr[b + 1];
+                for (uint32_t q = p0 + (uint32_t)ln; q < p1; q += 64) {
+                    const uint32_t p = v.post[q];
+                    if ((int)p == i) continue;
+                    // lowest bit of mask[p] & R'
+                    int low = -1;
+#pragma unroll
+                    for (int ww = 0; ww < WF; ++ww) {
+                        const uint64_t x = v.masks[(size_t)p * WF + ww] & m[ww];
+                        if (low < 0 && x) low = 64 * ww + __ffsll((unsigned long long)x) - 1;
+                    }
+                    if (low == b)
+                        atomicOr(reinterpret_cast<unsigned long long *>(&c.ubm[p >> 6]), 1ull << (p & 63));
+                }
+            }
+        }
+        see_atomics();
+        int nu = 0;
+        const int nwords_n = (F.n + 63) >> 6;
+        for (int base = 0; base < nwords_n; base += 64) {
+            const int wd = base + ln;
+            uint64_t bits = 0;
+            // read and clear each word in L2, where the marks were made
+            if (wd < nwords_n) bits = atomicExch(reinterpret_cast<unsigned long long *>(&c.ubm[wd]), 0ull);
+            const int pc = __popcll(bits);
+            const int incl = wave_incl_scan(pc);
+            int at = nu + incl - pc;
+            while (bits) {
+                const int bb = __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1ull;
+                c.stu[at++] = (uint32_t)(wd * 64 + bb);
+            }
+            nu += last_lane(incl);
+        }
+        wait_mem();
+        for (int base = 0; base < nu; base += 64) {
+            const int j = base + ln;
+            classify(j < nu ? (int)c.stu[j] : 0, j < nu);
+        }
     }
     wait_mem();  // the staged Q' / P' entries are read by other lanes below
 
@@ -708,73 +800,12 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
 
     // child frame: Q' then P' stably sorted by count; masks restricted to R' and, when
     // |R'| <= 64, compressed to |R'| bits
-    const int n2 = qn + pn;
-    const bool narrow = (W == 1) || r <= 64;
-    const int wf2 = narrow ? 1 : W;
     const uint32_t post2 = (uint32_t)wave_sum_i32((int)csum);
-    const uint32_t off2 = F.top;
-    const uint32_t top2 = align2(off2 + frame_words_fixed(n2, wf2) + post2);
-    if ((int64_t)top2 > c.scap) {
-        if (ln == 0) atomicOr(c.flags, (unsigned int)FLAG_STACK_OVERFLOW);
-        return false;
-    }
-    uint32_t *cb = c.stk + off2;
-    uint32_t *ids2 = cb;
-    uint64_t *masks2 = reinterpret_cast<uint64_t *>(cb + align2((uint32_t)n2));
-    FrameView v2 = frame_view(cb, n2, wf2);
-    if (narrow) {
-        // orig2[t] = N(x_root) position of the t-th bit of R'
-        int t0 = 0;
-#pragma unroll
-        for (int w = 0; w < WF; ++w) {
-            const bool on = (m[w] >> ln) & 1ull;
-            const uint64_t bb = __ballot(on);
-            if (on) v2.orig[t0 + __popcll(bb & below)] = root_pos(F, v, (uint32_t)(64 * w + ln));
-            t0 += __popcll(bb);
-        }
-    }
-    auto put = [&](uint32_t slot, uint32_t k) {
-        ids2[slot] = v.ids[k];
-        if (narrow) {
-            uint64_t out = 0;
-            int t = 0;
-#pragma unroll
-            for (int w = 0; w < WF; ++w) {
-                uint64_t mm = m[w];
-                const uint64_t xx = v.masks[(size_t)k * WF + w];
-                while (mm) {  // the same trip count on every lane: m is uniform
-                    const int p = __ffsll((unsigned long long)mm) - 1;
-                    mm &= mm - 1ull;
-                    out |= ((xx >> p) & 1ull) << t;
-                    ++t;
-                }
-            }
-            masks2[slot] = out;
-        } else {
-#pragma unroll
-            for (int w = 0; w < WF; ++w) masks2[(size_t)slot * W + w] = v.masks[(size_t)k * WF + w] & m[w];
-        }
-    };
-    for (int base = 0; base < qn; base += 64) {
-        const int j = base + ln;
-        if (j < qn) put((uint32_t)j, c.stq[j]);
-    }
-    wave_sort_by_key(c.stp, c.stc, pn, r, c.hist, [&](uint32_t slot, uint32_t k) { put((uint32_t)qn + slot, k); });
-    wait_mem();
-    if (narrow) build_tables_narrow(c, v2, n2);
-    else build_tables<W>(c, v2, n2, c.cur);
-
-    C.off = off2;
-    C.top = top2;
-    C.n = n2;
-    C.nq = qn;
+    const bool ok = (W == 1 || r <= 64) ? build_child<WF, W, true>(c, F, v, m, qn, pn, r, post2, C)
+                                        : build_child<WF, W, false>(c, F, v, m, qn, pn, r, post2, C);
+    if (!ok) return false;
     C.level = F.level + 1;
     C.nL = nL;
-    C.wf = wf2;
-    C.narrow = narrow ? 1 : 0;
-    C.chunk = qn - 64;
-    C.pad = 0;
-    C.heavy = 0ull;
     C.sL = sL;
     C.fw = DIAG ? wave_sum_u64(fwc) : 0ull;
     if (DIAG) acc.ph[PH_CHILD] += clock64() - tp;
