@@ -272,7 +272,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     dims.waves = waves;
     dims.ucap = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ncand, (int64_t)hstats[9]));
     dims.post_cap = std::max<int64_t>(64, (int64_t)hstats[9]);
-    dims.scap = 2 * (int64_t)dims.ucap + 16384;
+    dims.scap = 4 * (int64_t)dims.ucap + 16384;
     dims.maxdepth = 64 * Wmax + 2;
 
     // record arena for mbe_enumerate
@@ -440,7 +440,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         if (hflags & FLAG_UNIVERSE_OVERFLOW) {
             dims.ucap = (int32_t)std::max<int64_t>(dims.ucap, (int64_t)hacc[ACC_NEED_UCAP]);
             dims.post_cap = std::max<int64_t>(dims.post_cap, (int64_t)hacc[ACC_NEED_POST]);
-            dims.scap = std::max<int64_t>(dims.scap, 2 * (int64_t)dims.ucap + 16384);
+            dims.scap = std::max<int64_t>(dims.scap, 4 * (int64_t)dims.ucap + 16384);
         }
     }
     *hflags_out = hflags;
@@ -651,7 +651,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     dims.waves = opt.waves;
     dims.ucap = (int32_t)ucap;
     dims.post_cap = post;
-    dims.scap = 2 * ucap + 16384;
+    dims.scap = 4 * ucap + 16384;
     dims.maxdepth = 64 * Wmax + 2;
     const int grid = opt.grid > 0 ? opt.grid : 0;  // 0: occupancy-sized per class
 
@@ -763,7 +763,8 @@ struct mbe_server {
         while (64 * W < dmax && W < 16) W *= 2;
         const int waves = search.wg_waves > 0 ? search.wg_waves : 8;
         const int grid = search.grid > 0 ? search.grid : 2 * cus;
-        const size_t per_wg = (size_t)nc * (size_t)(24 * W + 40) + (size_t)waves * ((size_t)nc * 20 + 65536) +
+        // universe, top-level list and item tables per workgroup; stack and staging per wave
+        const size_t per_wg = (size_t)nc * (size_t)(24 * W + 60) + (size_t)waves * ((size_t)nc * 36 + 65536) +
                               (size_t)no / 8 + 65536;
         r.arena_bytes = per_wg * (size_t)grid;
     }

@@ -175,10 +175,12 @@ __device__ __forceinline__ FrameState uni_frame(const FrameState &f) {
 }
 
 // Word layout of a frame's data starting at a 2-aligned offset o:
-//   ids[n] | masks[n][wf] (u64) | first[64wf] | cnt[64wf] | H[64wf] (u64) | ptr[64wf+1] |
-//   orig[64] | post[...]
+//   ids[n] | hs[n] (u64) | masks[n][wf] (u64) | first[64wf] | cnt[64wf] | H[64wf] (u64) |
+//   ptr[64wf+1] | orig[64] | post[...]
+// ids are universe indices, hs the L-side hash term of each entry.
 struct FrameView {
     const uint32_t *ids;
+    const uint64_t *hs;
     const uint64_t *masks;
     uint32_t *first;
     uint32_t *cnt;
@@ -191,6 +193,7 @@ struct FrameView {
 __device__ __forceinline__ uint32_t frame_words_fixed(int n, int wf) {
     const uint32_t bits = 64u * (uint32_t)wf;
     uint32_t o = align2((uint32_t)n);
+    o += 2u * (uint32_t)n;  // hs
     o += 2u * (uint32_t)n * (uint32_t)wf;
     o += 2u * bits;  // first, cnt
     o = align2(o);
@@ -204,6 +207,8 @@ __device__ __forceinline__ FrameView frame_view(uint32_t *base, int n, int wf) {
     FrameView v;
     v.ids = base;
     uint32_t o = align2((uint32_t)n);
+    v.hs = reinterpret_cast<const uint64_t *>(base + o);
+    o += 2u * (uint32_t)n;
     v.masks = reinterpret_cast<const uint64_t *>(base + o);
     o += 2u * (uint32_t)n * (uint32_t)wf;
     v.first = base + o;
@@ -332,7 +337,7 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
     for (int base = 0; base < n; base += 64) {
         const int k = base + ln;
         if (k < n) {
-            const uint64_t h = hl(c, c.gid[v.ids[k]]);
+            const uint64_t h = v.hs[k];
 #pragma unroll
             for (int w = 0; w < WF; ++w) {
                 uint64_t m = v.masks[(size_t)k * WF + w];
@@ -375,28 +380,27 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
     wait_mem();
 }
 
-// Tables of a narrow frame (one mask word per entry), accumulated in the wave's LDS scratch
-// and then written out.  One wave.
-__device__ void build_tables_narrow(const Ctx &c, const FrameView &v, int n) {
+// Narrow frames (one mask word per entry) accumulate first / cnt / H in the wave's LDS
+// scratch while their entries are written (narrow_table_add); this writes the tables out and
+// fills the posting lists.  One wave.
+__device__ __forceinline__ void narrow_table_clear(const Ctx &c) {
     const int ln = lane_id();
     c.tl_first[ln] = kNone;
     c.tl_cnt[ln] = 0u;
     c.tl_H[ln] = 0ull;
     __builtin_amdgcn_wave_barrier();
-    for (int base = 0; base < n; base += 64) {
-        const int k = base + ln;
-        if (k < n) {
-            const uint64_t h = hl(c, c.gid[v.ids[k]]);
-            uint64_t m = v.masks[k];
-            while (m) {
-                const int b = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1ull;
-                atomicMin(&c.tl_first[b], (uint32_t)k);
-                atomicAdd(&c.tl_cnt[b], 1u);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&c.tl_H[b]), (unsigned long long)h);
-            }
-        }
+}
+__device__ __forceinline__ void narrow_table_add(const Ctx &c, uint32_t slot, uint64_t m, uint64_t h) {
+    while (m) {
+        const int b = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1ull;
+        atomicMin(&c.tl_first[b], slot);
+        atomicAdd(&c.tl_cnt[b], 1u);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&c.tl_H[b]), (unsigned long long)h);
     }
+}
+__device__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n) {
+    const int ln = lane_id();
     __builtin_amdgcn_wave_barrier();
     const int h = (int)c.tl_cnt[ln];
     const int incl = wave_incl_scan(h);
@@ -532,9 +536,11 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
         return false;
     }
     uint32_t *cb = c.stk + off2;
-    uint32_t *ids2 = cb;
-    uint64_t *masks2 = reinterpret_cast<uint64_t *>(cb + align2((uint32_t)n2));
     FrameView v2 = frame_view(cb, n2, wf2);
+    uint32_t *ids2 = cb;
+    uint64_t *hs2 = const_cast<uint64_t *>(v2.hs);
+    uint64_t *masks2 = const_cast<uint64_t *>(v2.masks);
+    if (NARROW) narrow_table_clear(c);
     if (NARROW) {
         // orig2[t] = N(x_root) position of the t-th bit of R'
         const uint64_t below = lanes_below();
@@ -549,6 +555,8 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     }
     auto put = [&](uint32_t slot, uint32_t k) {
         ids2[slot] = v.ids[k];
+        const uint64_t h = v.hs[k];
+        hs2[slot] = h;
         if (NARROW) {
             uint64_t out = 0;
             int t = 0;
@@ -564,6 +572,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
                 }
             }
             masks2[slot] = out;
+            narrow_table_add(c, slot, out, h);
         } else {
 #pragma unroll
             for (int w = 0; w < WF; ++w) masks2[(size_t)slot * W + w] = v.masks[(size_t)k * WF + w] & m[w];
@@ -575,7 +584,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     }
     wave_sort_by_key(c.stp, c.stc, pn, r, c.hist, [&](uint32_t slot, uint32_t k) { put((uint32_t)qn + slot, k); });
     wait_mem();
-    if (NARROW) build_tables_narrow(c, v2, n2);
+    if (NARROW) narrow_table_finish(c, v2, n2);
     else build_tables<W>(c, v2, n2, c.cur);
     C.off = off2;
     C.top = top2;
@@ -686,7 +695,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         const bool inq = act && k < i && cnt > 0;  // cnt < r: the node passed the check
         const bool full = act && k > i && cnt == r;
         const bool inp = act && k > i && cnt > 0 && cnt < r;
-        if (full) exps += hl(c, c.gid[v.ids[k]]);
+        if (full) exps += v.hs[k];
         ne += __popcll(__ballot(full));
         const uint64_t qb = __ballot(inq), pb = __ballot(inp);
         if (inq) c.stq[qn + __popcll(qb & below)] = (uint32_t)k;
@@ -759,7 +768,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     wait_mem();  // the staged Q' / P' entries are read by other lanes below
 
     // report (L', R')
-    const uint64_t sL = F.sL + hl(c, c.gid[v.ids[i]]) + wave_sum_u64(exps);
+    const uint64_t sL = F.sL + v.hs[i] + wave_sum_u64(exps);
     uint64_t sr = 0;
 #pragma unroll
     for (int w = 0; w < WF; ++w)
@@ -1311,9 +1320,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         wait_mem();
         __syncthreads();
         uint64_t *masks1 = const_cast<uint64_t *>(v1.masks);
+        uint64_t *hs1 = const_cast<uint64_t *>(v1.hs);
         for (int j = tid; j < n1; j += nt) {
             const uint32_t li = ids1[j];
             const uint64_t h = hl(c, gid[li]);
+            hs1[j] = h;
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 uint64_t mm = M[(size_t)li * W + w];
@@ -1559,7 +1570,7 @@ ArenaLayout search_layout(const SearchDims &d) {
     L.off_t1c = take(ucap * 4);
     L.off_cur1 = take(bits * 4);
     // ids | masks | first | cnt | H | ptr | orig | post (see frame_view)
-    L.s1_words = align_up(ucap, 2) + 2 * ucap * W + 2 * bits + 2 * bits + bits + 1 + 64 + (size_t)d.post_cap + 2;
+    L.s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 2 * bits + 2 * bits + bits + 1 + 64 + (size_t)d.post_cap + 2;
     L.off_S1 = take(L.s1_words * 4);
     L.off_hb = take((ucap / 64 + 1) * 8);
     L.off_hpre = take((ucap / 64 + 2) * 4);
