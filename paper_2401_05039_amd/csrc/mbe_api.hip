@@ -764,7 +764,7 @@ struct mbe_server {
         const int waves = search.wg_waves > 0 ? search.wg_waves : 8;
         const int grid = search.grid > 0 ? search.grid : 2 * cus;
         // universe, top-level list and item tables per workgroup; stack and staging per wave
-        const size_t per_wg = (size_t)nc * (size_t)(24 * W + 60) + (size_t)waves * ((size_t)nc * 36 + 65536) +
+        const size_t per_wg = (size_t)nc * (size_t)(24 * W + 60) + (size_t)waves * ((size_t)nc * 24 + 65536) +
                               (size_t)no / 8 + 65536;
         r.arena_bytes = per_wg * (size_t)grid;
     }

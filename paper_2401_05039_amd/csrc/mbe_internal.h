@@ -81,9 +81,6 @@ struct ArenaLayout {
     size_t off_waves;   // start of the per-wave regions
     size_t wave_bytes;  // stride between waves
     size_t off_w_stack; // u32[scap]            frames (lists, masks, per-bit tables)
-    size_t off_w_q;     // u32[ucap]            staging of Q' (parent positions)
-    size_t off_w_p;     // u32[ucap]            staging of P' (parent positions)
-    size_t off_w_c;     // u32[ucap]            staging of P' counts
     size_t off_w_cur;   // u32[64*Wmax]         posting cursors
     size_t off_w_u;     // u32[ucap]            a maximal node's entries, in list order
     size_t off_w_bm;    // u64[(ucap+63)/64]    position bitmap of those entries (kept zero)

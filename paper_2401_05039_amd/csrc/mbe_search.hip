@@ -235,7 +235,7 @@ struct Ctx {
     const int32_t *c_off;
     uint32_t *s1;                     // the workgroup's top-level list frame
     uint32_t *stk;                    // this wave's stack
-    uint32_t *stq, *stp, *stc, *cur;  // this wave's staging
+    uint32_t *cur;                    // this wave's posting cursors
     uint32_t *stu;                    // a maximal node's entries in list order
     uint64_t *ubm;                    // their position bitmap (all zero between nodes)
     uint32_t *tl_first, *tl_cnt, *tl_cur;  // this wave's LDS tables for narrow children
@@ -519,14 +519,19 @@ __device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameVi
     return __ballot(act && r >= 2);
 }
 
-// Write the child frame of a maximal node at the top of the wave's stack: Q' (staged in stq,
-// list order) then P' (staged in stp / stc) stably sorted by count, each entry's mask
-// restricted to R' -- compressed to |R'| bits when NARROW -- and the per-bit tables.  Sets
-// the layout fields of C; false when the stack is full.
-template <int WF, int W, bool NARROW>
-__device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int qn,
-                            int pn, int r, uint32_t post2, FrameState &C) {
+// Write the child frame of the maximal node at position i at the top of the wave's stack.
+// Its entries are the node's list entries k != i with 0 < |mask_k n R'| < |R'|: those before
+// i (Q') in list order, then those after i (P') stably sorted by that count.  The entries
+// are visited in list order -- positions 0..nu-1 when scan, else the positions stu[0..nu) --
+// and each is written straight to its slot: c.hist holds, per count, the number of P'
+// entries (filled by the caller's classification pass).  Masks are restricted to R' and,
+// when NARROW, compressed to |R'| bits; the per-bit tables follow.  Sets the layout fields
+// of C; false when the stack is full.
+template <int WF, int W, bool NARROW, bool DIAG>
+__device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], bool scan,
+                            int nu, int i, int r, int qn, int pn, uint32_t post2, FrameState &C) {
     const int ln = lane_id();
+    const uint64_t below = lanes_below();
     const int n2 = qn + pn;
     constexpr int wf2 = NARROW ? 1 : W;
     const uint32_t off2 = F.top;
@@ -540,10 +545,8 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     uint32_t *ids2 = cb;
     uint64_t *hs2 = const_cast<uint64_t *>(v2.hs);
     uint64_t *masks2 = const_cast<uint64_t *>(v2.masks);
-    if (NARROW) narrow_table_clear(c);
     if (NARROW) {
         // orig2[t] = N(x_root) position of the t-th bit of R'
-        const uint64_t below = lanes_below();
         int t0 = 0;
 #pragma unroll
         for (int w = 0; w < WF; ++w) {
@@ -552,37 +555,80 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
             if (on) v2.orig[t0 + __popcll(bb & below)] = root_pos(F, v, (uint32_t)(64 * w + ln));
             t0 += __popcll(bb);
         }
+        narrow_table_clear(c);
     }
-    auto put = [&](uint32_t slot, uint32_t k) {
-        ids2[slot] = v.ids[k];
-        const uint64_t h = v.hs[k];
-        hs2[slot] = h;
-        if (NARROW) {
-            uint64_t out = 0;
-            int t = 0;
-#pragma unroll
-            for (int w = 0; w < WF; ++w) {
-                uint64_t mm = m[w];
-                const uint64_t xx = v.masks[(size_t)k * WF + w];
-                while (mm) {  // the same trip count on every lane: m is uniform
-                    const int p = __ffsll((unsigned long long)mm) - 1;
-                    mm &= mm - 1ull;
-                    out |= ((xx >> p) & 1ull) << t;
-                    ++t;
-                }
-            }
-            masks2[slot] = out;
-            narrow_table_add(c, slot, out, h);
-        } else {
-#pragma unroll
-            for (int w = 0; w < WF; ++w) masks2[(size_t)slot * W + w] = v.masks[(size_t)k * WF + w] & m[w];
-        }
-    };
-    for (int base = 0; base < qn; base += 64) {
+    // first slot of each count among the P' entries
+    int carry = qn;
+    for (int base = 0; base < r; base += 64) {
+        const int b = base + ln;
+        const int h = b < r ? (int)c.hist[b] : 0;
+        const int incl = wave_incl_scan(h);
+        if (b < r) c.hist[b] = (uint32_t)(carry + incl - h);
+        carry += last_lane(incl);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int nbits = r <= 1 ? 1 : 32 - __clz(r - 1);
+    int qpos = 0;
+    for (int base = 0; base < nu; base += 64) {
         const int j = base + ln;
-        if (j < qn) put((uint32_t)j, c.stq[j]);
+        bool act = j < nu;
+        const int k = act ? (scan ? j : (int)c.stu[j]) : 0;
+        act = act && k != i;
+        uint64_t x[WF];
+        int cnt = 0;
+#pragma unroll
+        for (int w = 0; w < WF; ++w) {
+            x[w] = act ? v.masks[(size_t)k * WF + w] & m[w] : 0ull;
+            cnt += __popcll(x[w]);
+        }
+        const bool inq = act && k < i && cnt > 0;
+        const bool inp = act && k > i && cnt > 0 && cnt < r;
+        const uint64_t qb = __ballot(inq);
+        uint32_t slot = (uint32_t)(qpos + __popcll(qb & below));
+        qpos += __popcll(qb);
+        const uint64_t pb = __ballot(inp);
+        if (pb) {
+            // stable placement among equal counts: lanes with the same count, in lane order
+            uint64_t same = pb;
+            for (int bit = 0; bit < nbits; ++bit) {
+                const bool on = (cnt >> bit) & 1;
+                const uint64_t bb = __ballot(inp && on);
+                same &= on ? bb : ~bb;
+            }
+            uint32_t start = 0;
+            if (inp) start = c.hist[cnt];
+            __builtin_amdgcn_wave_barrier();
+            if (inp) {
+                slot = start + (uint32_t)__popcll(same & below);
+                if ((same >> ln) == 1ull) c.hist[cnt] = start + (uint32_t)__popcll(same);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (inq || inp) {
+            if (DIAG) ids2[slot] = v.ids[k];
+            const uint64_t h = v.hs[k];
+            hs2[slot] = h;
+            if (NARROW) {
+                uint64_t out = 0;
+                int t = 0;
+#pragma unroll
+                for (int w = 0; w < WF; ++w) {
+                    uint64_t mm = m[w];
+                    while (mm) {  // the same trip count on every lane: m is uniform
+                        const int p = __ffsll((unsigned long long)mm) - 1;
+                        mm &= mm - 1ull;
+                        out |= ((x[w] >> p) & 1ull) << t;
+                        ++t;
+                    }
+                }
+                masks2[slot] = out;
+                narrow_table_add(c, slot, out, h);
+            } else {
+#pragma unroll
+                for (int w = 0; w < WF; ++w) masks2[(size_t)slot * W + w] = x[w];
+            }
+        }
     }
-    wave_sort_by_key(c.stp, c.stc, pn, r, c.hist, [&](uint32_t slot, uint32_t k) { put((uint32_t)qn + slot, k); });
     wait_mem();
     if (NARROW) narrow_table_finish(c, v2, n2);
     else build_tables<W>(c, v2, n2, c.cur);
@@ -678,46 +724,18 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         return false;
     }
 
-    // maximal: classify every entry sharing a bit with R' (list order is kept, so P' keeps
-    // the stable tie order).  Short lists are scanned whole with coalesced loads; otherwise
-    // the entries are the union of R''s posting lists: each is taken once (from the list of
-    // its lowest bit in R'), marked in a position bitmap, and the bitmap is read back in
-    // list order.
+    // maximal: classify every entry sharing a bit with R', in list order.  Short lists are
+    // scanned whole with coalesced loads; otherwise the entries are the union of R''s
+    // posting lists: each is taken once (from the list of its lowest bit in R'), marked in a
+    // position bitmap, and the bitmap is read back in list order into stu.  The P' counts
+    // are tallied per count value in c.hist for the child's stable sort.
     int qn = 0, pn = 0, ne = 0;
     uint64_t exps = 0, fwc = 0;
     uint32_t csum = 0;
-    auto classify = [&](int k, bool act) {
-        int cnt = 0;
-        if (act) {
-#pragma unroll
-            for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
-        }
-        const bool inq = act && k < i && cnt > 0;  // cnt < r: the node passed the check
-        const bool full = act && k > i && cnt == r;
-        const bool inp = act && k > i && cnt > 0 && cnt < r;
-        if (full) exps += v.hs[k];
-        ne += __popcll(__ballot(full));
-        const uint64_t qb = __ballot(inq), pb = __ballot(inp);
-        if (inq) c.stq[qn + __popcll(qb & below)] = (uint32_t)k;
-        if (inp) {
-            const int p = pn + __popcll(pb & below);
-            c.stp[p] = (uint32_t)k;
-            c.stc[p] = (uint32_t)cnt;
-        }
-        if (inq || inp) {
-            csum += (uint32_t)cnt;
-            if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
-        }
-        qn += __popcll(qb);
-        pn += __popcll(pb);
-    };
     const int incidences = wave_sum_i32((int)inc);
-    if (F.n <= kScanFactor * incidences + kScanMin) {
-        for (int base = 0; base < F.n; base += 64) {
-            const int k = base + ln;
-            classify(k, k < F.n && k != i);
-        }
-    } else {
+    const bool scan = F.n <= kScanFactor * incidences + kScanMin;
+    int nu = F.n;
+    if (!scan) {
 #pragma unroll
         for (int w = 0; w < WF; ++w) {
             uint64_t mb = m[w];
@@ -742,7 +760,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
             }
         }
         see_atomics();
-        int nu = 0;
+        nu = 0;
         const int nwords_n = (F.n + 63) >> 6;
         for (int base = 0; base < nwords_n; base += 64) {
             const int wd = base + ln;
@@ -760,12 +778,32 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
             nu += last_lane(incl);
         }
         wait_mem();
-        for (int base = 0; base < nu; base += 64) {
-            const int j = base + ln;
-            classify(j < nu ? (int)c.stu[j] : 0, j < nu);
+    }
+    for (int b = ln; b < r; b += 64) c.hist[b] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    for (int base = 0; base < nu; base += 64) {
+        const int j = base + ln;
+        bool act = j < nu;
+        const int k = act ? (scan ? j : (int)c.stu[j]) : 0;
+        act = act && k != i;
+        int cnt = 0;
+        if (act) {
+#pragma unroll
+            for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
+        }
+        const bool inq = act && k < i && cnt > 0;  // cnt < r: the node passed the check
+        const bool full = act && k > i && cnt == r;
+        const bool inp = act && k > i && cnt > 0 && cnt < r;
+        if (full) exps += v.hs[k];
+        ne += __popcll(__ballot(full));
+        qn += __popcll(__ballot(inq));
+        pn += __popcll(__ballot(inp));
+        if (inp) atomicAdd(&c.hist[cnt], 1u);
+        if (inq || inp) {
+            csum += (uint32_t)cnt;
+            if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
         }
     }
-    wait_mem();  // the staged Q' / P' entries are read by other lanes below
 
     // report (L', R')
     const uint64_t sL = F.sL + v.hs[i] + wave_sum_u64(exps);
@@ -810,8 +848,13 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     // child frame: Q' then P' stably sorted by count; masks restricted to R' and, when
     // |R'| <= 64, compressed to |R'| bits
     const uint32_t post2 = (uint32_t)wave_sum_i32((int)csum);
-    const bool ok = (W == 1 || r <= 64) ? build_child<WF, W, true>(c, F, v, m, qn, pn, r, post2, C)
-                                        : build_child<WF, W, false>(c, F, v, m, qn, pn, r, post2, C);
+    bool ok;
+    if constexpr (WF == 1) {
+        ok = build_child<1, W, true, DIAG>(c, F, v, m, scan, nu, i, r, qn, pn, post2, C);
+    } else {
+        ok = r <= 64 ? build_child<WF, W, true, DIAG>(c, F, v, m, scan, nu, i, r, qn, pn, post2, C)
+                     : build_child<WF, W, false, DIAG>(c, F, v, m, scan, nu, i, r, qn, pn, post2, C);
+    }
     if (!ok) return false;
     C.level = F.level + 1;
     C.nL = nL;
@@ -975,9 +1018,6 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     c.c_off = a.c_off;
     c.s1 = s1;
     c.stk = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_stack);
-    c.stq = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_q);
-    c.stp = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_p);
-    c.stc = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_c);
     c.cur = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_cur);
     c.stu = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_u);
     c.ubm = reinterpret_cast<uint64_t *>(wv + a.lay.off_w_bm);
@@ -1583,9 +1623,6 @@ ArenaLayout search_layout(const SearchDims &d) {
         return at;
     };
     L.off_w_stack = wtake((size_t)d.scap * 4);
-    L.off_w_q = wtake(ucap * 4);
-    L.off_w_p = wtake(ucap * 4);
-    L.off_w_c = wtake(ucap * 4);
     L.off_w_cur = wtake(bits * 4);
     L.off_w_u = wtake(ucap * 4);
     L.off_w_bm = wtake((ucap + 63) / 64 * 8);
