@@ -271,7 +271,6 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     dims.Wmax = Wmax;
     dims.waves = waves;
     dims.ucap = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ncand, (int64_t)hstats[9]));
-    dims.post_cap = std::max<int64_t>(64, (int64_t)hstats[9]);
     dims.scap = 4 * (int64_t)dims.ucap + 16384;
     dims.maxdepth = 64 * Wmax + 2;
 
@@ -439,7 +438,6 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         if (hflags & FLAG_DEPTH_OVERFLOW) dims.maxdepth *= 2;
         if (hflags & FLAG_UNIVERSE_OVERFLOW) {
             dims.ucap = (int32_t)std::max<int64_t>(dims.ucap, (int64_t)hacc[ACC_NEED_UCAP]);
-            dims.post_cap = std::max<int64_t>(dims.post_cap, (int64_t)hacc[ACC_NEED_POST]);
             dims.scap = std::max<int64_t>(dims.scap, 4 * (int64_t)dims.ucap + 16384);
         }
     }
@@ -620,7 +618,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
 
     // descriptors and capacities
     std::vector<GraphDesc> gd(n);
-    int64_t ucap = 1, post = 64, maxc = 1;
+    int64_t ucap = 1, maxc = 1;
     for (int32_t i = 0; i < n; ++i) {
         GraphDesc &d = gd[i];
         std::memset(&d, 0, sizeof(d));
@@ -633,7 +631,6 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         d.cbase = cb[i];
         d.obase = ob[i];
         ucap = std::max<int64_t>(ucap, std::min<int64_t>(ncand_h[i], (int64_t)hg[2 * i + 1]));
-        post = std::max<int64_t>(post, (int64_t)hg[2 * i + 1]);
         maxc = std::max<int64_t>(maxc, ncand_h[i]);
     }
     MBE_TRY(hipMemcpyAsync(d_gd, gd.data(), (size_t)n * sizeof(GraphDesc), hipMemcpyHostToDevice, s));
@@ -650,7 +647,6 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     dims.Wmax = Wmax;
     dims.waves = opt.waves;
     dims.ucap = (int32_t)ucap;
-    dims.post_cap = post;
     dims.scap = 4 * ucap + 16384;
     dims.maxdepth = 64 * Wmax + 2;
     const int grid = opt.grid > 0 ? opt.grid : 0;  // 0: occupancy-sized per class

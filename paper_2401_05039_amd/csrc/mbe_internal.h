@@ -20,7 +20,7 @@ enum AccSlot : int {
     ACC_RECORDS = 7,    // records reserved in the record arena
     ACC_REC_INTS = 8,   // ints reserved in the record arena
     ACC_NEED_UCAP = 9,  // largest universe met (max), for resizing after an overflow
-    ACC_NEED_POST = 10, // largest top-level posting total met (max)
+    ACC_RESERVED10 = 10,
     ACC_PHASE = 11,     // 6 slots: shader-clock cycles per search phase (diagnostics only)
     ACC_SLOTS = 24,
 };
@@ -54,7 +54,6 @@ struct SearchDims {
     int32_t nwords;    // words of the rank bitmap
     int32_t Wmax;      // widest mask class in use (words)
     int32_t waves;     // waves per workgroup
-    int64_t post_cap;  // posting entries of the top-level candidate list
     int64_t scap;      // per-wave stack capacity (32-bit words)
     int32_t maxdepth;  // per-wave frame headers
     int32_t pad;
@@ -72,7 +71,6 @@ struct ArenaLayout {
     size_t off_deg;     // u32[64*Wmax]         degree of each position of N(x)
     size_t off_t1v;     // u32[ucap]            sort staging (ids)
     size_t off_t1c;     // u32[ucap]            sort staging (keys)
-    size_t off_cur1;    // u32[64*Wmax]         posting cursors
     size_t off_S1;      // u32[s1_words]        the top-level node's child list as a frame
     size_t off_hb;      // u64[ucap/64+1]       top-level candidates with |R'| >= 2, per chunk
     size_t off_hpre;    // u32[ucap/64+2]       popcount prefix of those words
@@ -81,9 +79,7 @@ struct ArenaLayout {
     size_t off_waves;   // start of the per-wave regions
     size_t wave_bytes;  // stride between waves
     size_t off_w_stack; // u32[scap]            frames (lists, masks, per-bit tables)
-    size_t off_w_cur;   // u32[64*Wmax]         posting cursors
     size_t off_w_u;     // u32[ucap]            a maximal node's entries, in list order
-    size_t off_w_bm;    // u64[(ucap+63)/64]    position bitmap of those entries (kept zero)
     size_t off_w_hdr;   // frame headers[maxdepth]
 };
 

@@ -51,10 +51,6 @@ namespace {
 constexpr uint64_t kHashK = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kShared = 0xFFFFFFFFu;  // frame offset meaning "the workgroup's top-level list"
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-// A maximal node scans its whole list when the list is at most kScanFactor times the total
-// length of R''s posting lists plus kScanMin entries; otherwise it walks those lists.
-constexpr int kScanFactor = 4;
-constexpr int kScanMin = 512;
 
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -176,8 +172,11 @@ __device__ __forceinline__ FrameState uni_frame(const FrameState &f) {
 
 // Word layout of a frame's data starting at a 2-aligned offset o:
 //   ids[n] | hs[n] (u64) | masks[n][wf] (u64) | first[64wf] | cnt[64wf] | H[64wf] (u64) |
-//   ptr[64wf+1] | orig[64] | post[...]
-// ids are universe indices, hs the L-side hash term of each entry.
+//   orig[64] | rows[64wf][nw] (u64), nw = ceil(n / 64)
+// ids are universe indices (kept for diagnostics), hs the L-side hash term of each entry.
+// Row b is the position bitmap of mask bit b: bit k % 64 of its word k / 64 is set when entry
+// k holds bit b.  first / cnt / H: per bit, the first position holding it, how many entries
+// hold it, and the sum of their hash terms.
 struct FrameView {
     const uint32_t *ids;
     const uint64_t *hs;
@@ -185,26 +184,27 @@ struct FrameView {
     uint32_t *first;
     uint32_t *cnt;
     uint64_t *H;
-    uint32_t *ptr;
     uint32_t *orig;
-    uint32_t *post;
+    uint64_t *rows;
+    int nw;
 };
 
 __device__ __forceinline__ uint32_t frame_words_fixed(int n, int wf) {
-    const uint32_t bits = 64u * (uint32_t)wf;
+    const uint32_t bits = 64u * (uint32_t)wf, nw = ((uint32_t)n + 63u) >> 6;
     uint32_t o = align2((uint32_t)n);
-    o += 2u * (uint32_t)n;  // hs
-    o += 2u * (uint32_t)n * (uint32_t)wf;
-    o += 2u * bits;  // first, cnt
-    o = align2(o);
-    o += 2u * bits;        // H
-    o += bits + 1u + 64u;  // ptr, orig
+    o += 2u * (uint32_t)n;                 // hs
+    o += 2u * (uint32_t)n * (uint32_t)wf;  // masks
+    o += 2u * bits;                        // first, cnt
+    o += 2u * bits;                        // H
+    o += 64u;                              // orig
+    o += 2u * bits * nw;                   // rows
     return o;
 }
 
 __device__ __forceinline__ FrameView frame_view(uint32_t *base, int n, int wf) {
     const uint32_t bits = 64u * (uint32_t)wf;
     FrameView v;
+    v.nw = (n + 63) >> 6;
     v.ids = base;
     uint32_t o = align2((uint32_t)n);
     v.hs = reinterpret_cast<const uint64_t *>(base + o);
@@ -215,15 +215,35 @@ __device__ __forceinline__ FrameView frame_view(uint32_t *base, int n, int wf) {
     o += bits;
     v.cnt = base + o;
     o += bits;
-    o = align2(o);
     v.H = reinterpret_cast<uint64_t *>(base + o);
     o += 2u * bits;
-    v.ptr = base + o;
-    o += bits + 1u;
     v.orig = base + o;
     o += 64u;
-    v.post = base + o;
+    v.rows = reinterpret_cast<uint64_t *>(base + o);
     return v;
+}
+
+// 64 x 64 bit-matrix transpose across the wave: on entry lane i holds row i (bit j is element
+// (i, j)), on return lane j holds column j (bit i is element (i, j)).  Recursive block swap:
+// at block size s, the upper-right and lower-left s x s blocks trade places.
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t x) {
+    const int ln = lane_id();
+    const uint64_t keep[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                              0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
+        const int sft = 32 >> l;
+        const uint64_t lo = keep[l];  // bits whose index has bit sft clear
+        const uint64_t y = __shfl_xor(x, sft);
+        x = (ln & sft) ? ((x & ~lo) | ((y & ~lo) >> sft)) : ((x & lo) | ((y & lo) << sft));
+    }
+    return x;
+}
+
+// Rows [64q, 64q + 64) at word w of a frame, from mask word q of entries 64w .. 64w + 63
+// (x: this lane's entry's word, 0 past the end).  One wave.
+__device__ __forceinline__ void store_rows(const FrameView &v, int q, int w, uint64_t x) {
+    v.rows[(size_t)(64 * q + lane_id()) * v.nw + w] = wave_transpose64(x);
 }
 
 struct Ctx {
@@ -235,10 +255,8 @@ struct Ctx {
     const int32_t *c_off;
     uint32_t *s1;                     // the workgroup's top-level list frame
     uint32_t *stk;                    // this wave's stack
-    uint32_t *cur;                    // this wave's posting cursors
-    uint32_t *stu;                    // a maximal node's entries in list order
-    uint64_t *ubm;                    // their position bitmap (all zero between nodes)
-    uint32_t *tl_first, *tl_cnt, *tl_cur;  // this wave's LDS tables for narrow children
+    uint32_t *stu;                    // a maximal node's Q' and P' positions in list order
+    uint32_t *tl_first, *tl_cnt;           // this wave's LDS tables for narrow children
     uint64_t *tl_H;
     uint32_t *hist;                   // this wave's LDS histogram
     int64_t scap;
@@ -322,10 +340,9 @@ __device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, in
     }
 }
 
-// Build the per-bit tables of a frame whose ids and masks are in place.  cursor: 64*WF
-// scratch words.  One wave.
+// Per-bit tables and rows of a wide frame whose entries are in place.  One wave.
 template <int WF>
-__device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *cursor) {
+__device__ void build_tables_wide(const FrameView &v, int n) {
     constexpr int bits = 64 * WF;
     const int ln = lane_id();
     for (int b = ln; b < bits; b += 64) {
@@ -336,53 +353,28 @@ __device__ void build_tables(const Ctx &c, const FrameView &v, int n, uint32_t *
     wait_mem();
     for (int base = 0; base < n; base += 64) {
         const int k = base + ln;
-        if (k < n) {
-            const uint64_t h = v.hs[k];
+        const bool act = k < n;
+        const uint64_t h = act ? v.hs[k] : 0ull;
 #pragma unroll
-            for (int w = 0; w < WF; ++w) {
-                uint64_t m = v.masks[(size_t)k * WF + w];
-                while (m) {
-                    const int b = 64 * w + __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1ull;
-                    atomicMin(&v.first[b], (uint32_t)k);
-                    atomicAdd(&v.cnt[b], 1u);
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&v.H[b]), (unsigned long long)h);
-                }
+        for (int w = 0; w < WF; ++w) {
+            const uint64_t x = act ? v.masks[(size_t)k * WF + w] : 0ull;
+            uint64_t m = x;
+            while (m) {
+                const int b = 64 * w + __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                atomicMin(&v.first[b], (uint32_t)k);
+                atomicAdd(&v.cnt[b], 1u);
+                atomicAdd(reinterpret_cast<unsigned long long *>(&v.H[b]), (unsigned long long)h);
             }
+            store_rows(v, w, base >> 6, x);
         }
     }
     see_atomics();
-    int carry = 0;
-    for (int base = 0; base < bits; base += 64) {
-        const int b = base + ln;
-        const int h = (int)v.cnt[b];
-        const int incl = wave_incl_scan(h);
-        v.ptr[b] = (uint32_t)(carry + incl - h);
-        cursor[b] = (uint32_t)(carry + incl - h);
-        carry += last_lane(incl);
-    }
-    if (ln == 0) v.ptr[bits] = (uint32_t)carry;
-    wait_mem();
-    for (int base = 0; base < n; base += 64) {
-        const int k = base + ln;
-        if (k < n) {
-#pragma unroll
-            for (int w = 0; w < WF; ++w) {
-                uint64_t m = v.masks[(size_t)k * WF + w];
-                while (m) {
-                    const int b = 64 * w + __ffsll((unsigned long long)m) - 1;
-                    m &= m - 1ull;
-                    v.post[atomicAdd(&cursor[b], 1u)] = (uint32_t)k;
-                }
-            }
-        }
-    }
-    wait_mem();
 }
 
 // Narrow frames (one mask word per entry) accumulate first / cnt / H in the wave's LDS
-// scratch while their entries are written (narrow_table_add); this writes the tables out and
-// fills the posting lists.  One wave.
+// scratch while their entries are written (narrow_table_add); narrow_table_finish writes the
+// tables out and builds the rows.  One wave.
 __device__ __forceinline__ void narrow_table_clear(const Ctx &c) {
     const int ln = lane_id();
     c.tl_first[ln] = kNone;
@@ -402,25 +394,12 @@ __device__ __forceinline__ void narrow_table_add(const Ctx &c, uint32_t slot, ui
 __device__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n) {
     const int ln = lane_id();
     __builtin_amdgcn_wave_barrier();
-    const int h = (int)c.tl_cnt[ln];
-    const int incl = wave_incl_scan(h);
     v.first[ln] = c.tl_first[ln];
-    v.cnt[ln] = (uint32_t)h;
+    v.cnt[ln] = c.tl_cnt[ln];
     v.H[ln] = c.tl_H[ln];
-    v.ptr[ln] = (uint32_t)(incl - h);
-    c.tl_cur[ln] = (uint32_t)(incl - h);
-    if (ln == 63) v.ptr[64] = (uint32_t)incl;
-    __builtin_amdgcn_wave_barrier();
     for (int base = 0; base < n; base += 64) {
         const int k = base + ln;
-        if (k < n) {
-            uint64_t m = v.masks[k];
-            while (m) {
-                const int b = __ffsll((unsigned long long)m) - 1;
-                m &= m - 1ull;
-                v.post[atomicAdd(&c.tl_cur[b], 1u)] = (uint32_t)k;
-            }
-        }
+        store_rows(v, 0, base >> 6, k < n ? v.masks[k] : 0ull);
     }
     wait_mem();
 }
@@ -520,22 +499,21 @@ __device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameVi
 }
 
 // Write the child frame of the maximal node at position i at the top of the wave's stack.
-// Its entries are the node's list entries k != i with 0 < |mask_k n R'| < |R'|: those before
-// i (Q') in list order, then those after i (P') stably sorted by that count.  The entries
-// are visited in list order -- positions 0..nu-1 when scan, else the positions stu[0..nu) --
-// and each is written straight to its slot: c.hist holds, per count, the number of P'
-// entries (filled by the caller's classification pass).  Masks are restricted to R' and,
-// when NARROW, compressed to |R'| bits; the per-bit tables follow.  Sets the layout fields
-// of C; false when the stack is full.
+// Its entries are the positions stu[0, nu) of the node's list, in list order: the first qn
+// (before i) form Q' and keep their order, the other pn (after i, 0 < |mask n R'| < |R'|)
+// form P', stably sorted by that count.  Each entry is written straight to its slot: c.hist
+// holds, per count, the number of P' entries (filled by the caller).  Masks are restricted
+// to R' and, when NARROW, compressed to |R'| bits; the tables and rows follow.  Sets the
+// layout fields of C; false when the stack is full.
 template <int WF, int W, bool NARROW, bool DIAG>
-__device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], bool scan,
-                            int nu, int i, int r, int qn, int pn, uint32_t post2, FrameState &C) {
+__device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int nu,
+                            int r, int qn, int pn, FrameState &C) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     const int n2 = qn + pn;
     constexpr int wf2 = NARROW ? 1 : W;
     const uint32_t off2 = F.top;
-    const uint32_t top2 = align2(off2 + frame_words_fixed(n2, wf2) + post2);
+    const uint32_t top2 = align2(off2 + frame_words_fixed(n2, wf2));
     if ((int64_t)top2 > c.scap) {
         if (ln == 0) atomicOr(c.flags, (unsigned int)FLAG_STACK_OVERFLOW);
         return false;
@@ -568,12 +546,10 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     }
     __builtin_amdgcn_wave_barrier();
     const int nbits = r <= 1 ? 1 : 32 - __clz(r - 1);
-    int qpos = 0;
     for (int base = 0; base < nu; base += 64) {
         const int j = base + ln;
-        bool act = j < nu;
-        const int k = act ? (scan ? j : (int)c.stu[j]) : 0;
-        act = act && k != i;
+        const bool act = j < nu;
+        const int k = act ? (int)c.stu[j] : 0;
         uint64_t x[WF];
         int cnt = 0;
 #pragma unroll
@@ -581,15 +557,11 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
             x[w] = act ? v.masks[(size_t)k * WF + w] & m[w] : 0ull;
             cnt += __popcll(x[w]);
         }
-        const bool inq = act && k < i && cnt > 0;
-        const bool inp = act && k > i && cnt > 0 && cnt < r;
-        const uint64_t qb = __ballot(inq);
-        uint32_t slot = (uint32_t)(qpos + __popcll(qb & below));
-        qpos += __popcll(qb);
-        const uint64_t pb = __ballot(inp);
-        if (pb) {
+        const bool inp = act && j >= qn;
+        uint32_t slot = (uint32_t)j;  // Q' entries keep their list order
+        if (__ballot(inp)) {
             // stable placement among equal counts: lanes with the same count, in lane order
-            uint64_t same = pb;
+            uint64_t same = __ballot(inp);
             for (int bit = 0; bit < nbits; ++bit) {
                 const bool on = (cnt >> bit) & 1;
                 const uint64_t bb = __ballot(inp && on);
@@ -604,7 +576,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (inq || inp) {
+        if (act) {
             if (DIAG) ids2[slot] = v.ids[k];
             const uint64_t h = v.hs[k];
             hs2[slot] = h;
@@ -631,7 +603,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     }
     wait_mem();
     if (NARROW) narrow_table_finish(c, v2, n2);
-    else build_tables<W>(c, v2, n2, c.cur);
+    else build_tables_wide<W>(v2, n2);
     C.off = off2;
     C.top = top2;
     C.n = n2;
@@ -642,6 +614,27 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     C.pad = 0;
     C.heavy = 0ull;
     return true;
+}
+
+// OR (u) and AND (a), over the bits b of R' listed in c.hist[0, r), of word wd of row b; a
+// is 0 when !in.  Rows are read four at a time.
+__device__ __forceinline__ void fold_rows(const Ctx &c, const FrameView &v, int r, int wd, bool in, uint64_t &u,
+                                          uint64_t &a) {
+    u = 0ull;
+    a = ~0ull;
+    for (int t = 0; t < r; t += 4) {
+        const uint32_t b0 = uni(c.hist[t]);
+        const uint32_t b1 = uni(c.hist[t + 1 < r ? t + 1 : t]);
+        const uint32_t b2 = uni(c.hist[t + 2 < r ? t + 2 : t]);
+        const uint32_t b3 = uni(c.hist[t + 3 < r ? t + 3 : t]);
+        if (in) {
+            const uint64_t x0 = v.rows[(size_t)b0 * v.nw + wd], x1 = v.rows[(size_t)b1 * v.nw + wd];
+            const uint64_t x2 = v.rows[(size_t)b2 * v.nw + wd], x3 = v.rows[(size_t)b3 * v.nw + wd];
+            u |= (x0 | x1) | (x2 | x3);
+            a &= (x0 & x1) & (x2 & x3);
+        }
+    }
+    if (!in) a = 0ull;
 }
 
 // The candidate at position i of frame F, |R'| = r >= 1, handled by the whole wave.
@@ -659,40 +652,36 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         r += __popcll(m[w]);
     }
 
-    // maximality: an earlier entry holding every bit of R' ends the node.  If some bit of R'
-    // first appears at i itself, nothing earlier can hold R'.
-    bool first_here = false;
-    uint32_t best = 0xFFFFFFFFu;  // (count << 12 | bit) of the rarest bit
-    uint32_t inc = 0;             // posting-list entries of this lane's bits
+    // the bits of R', ascending, in c.hist[0, r)
+    {
+        int t0 = 0;
 #pragma unroll
-    for (int w = 0; w < WF; ++w) {
-        if ((m[w] >> ln) & 1ull) {
-            const int b = 64 * w + ln;
-            if (v.first[b] == (uint32_t)i) first_here = true;
-            inc += v.cnt[b];
-            const uint32_t cb = v.cnt[b] < 0xFFFFFu ? v.cnt[b] : 0xFFFFFu;  // saturate: b stays exact
-            const uint32_t key = (cb << 12) | (uint32_t)b;
-            best = key < best ? key : best;
+        for (int w = 0; w < WF; ++w) {
+            const bool on = (m[w] >> ln) & 1ull;
+            const uint64_t bb = __ballot(on);
+            if (on) c.hist[t0 + __popcll(bb & below)] = (uint32_t)(64 * w + ln);
+            t0 += __popcll(bb);
         }
+        __builtin_amdgcn_wave_barrier();
     }
+
+    // maximality: an earlier entry holding every bit of R' ends the node -- a position below
+    // i in the AND of R''s rows.  If some bit of R' first appears at i itself, nothing
+    // earlier can hold R'.
+    bool first_here = false;
+#pragma unroll
+    for (int w = 0; w < WF; ++w)
+        if (((m[w] >> ln) & 1ull) && v.first[64 * w + ln] == (uint32_t)i) first_here = true;
     bool nonmax = false;
     uint64_t tp = DIAG ? clock64() : 0ull;
     if (!__ballot(first_here)) {
-        best = wave_min_u32(best);
-        const uint32_t b = best & 0xFFFu;
-        const uint32_t p0 = v.ptr[b], p1 = v.ptr[b + 1];
-        for (uint32_t q = p0; q < p1; q += 64) {
-            const uint32_t qq = q + (uint32_t)ln;
-            bool viol = false;
-            if (qq < p1) {
-                const uint32_t p = v.post[qq];
-                if (p < (uint32_t)i) {
-                    viol = true;
-#pragma unroll
-                    for (int w = 0; w < WF; ++w) viol = viol && ((v.masks[(size_t)p * WF + w] & m[w]) == m[w]);
-                }
-            }
-            if (__ballot(viol)) {
+        const int wl = i >> 6;  // the word holding position i
+        for (int base = 0; base <= wl; base += 64) {
+            const int wd = base + ln;
+            uint64_t u, a;
+            fold_rows(c, v, r, wd, wd <= wl, u, a);
+            if (wd == wl) a &= (1ull << (i & 63)) - 1ull;
+            if (__ballot(a != 0ull)) {
                 nonmax = true;
                 break;
             }
@@ -724,83 +713,59 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         return false;
     }
 
-    // maximal: classify every entry sharing a bit with R', in list order.  Short lists are
-    // scanned whole with coalesced loads; otherwise the entries are the union of R''s
-    // posting lists: each is taken once (from the list of its lowest bit in R'), marked in a
-    // position bitmap, and the bitmap is read back in list order into stu.  The P' counts
-    // are tallied per count value in c.hist for the child's stable sort.
-    int qn = 0, pn = 0, ne = 0;
+    // maximal.  Per word of positions: the OR of R''s rows gives the entries sharing a bit
+    // with R', the AND those holding all of it (after i only, the node being maximal; they
+    // join L').  The rest -- Q' before i, P' after -- are listed in stu in list order, and
+    // the P' counts |mask n R'| are tallied per value in c.hist for the child's stable sort.
+    int qn = 0, nu = 0;
+    int ne_l = 0, qn_l = 0;
     uint64_t exps = 0, fwc = 0;
-    uint32_t csum = 0;
-    const int incidences = wave_sum_i32((int)inc);
-    const bool scan = F.n <= kScanFactor * incidences + kScanMin;
-    int nu = F.n;
-    if (!scan) {
-#pragma unroll
-        for (int w = 0; w < WF; ++w) {
-            uint64_t mb = m[w];
-            while (mb) {  // uniform loop over the bits of R'
-                const int bit = __ffsll((unsigned long long)mb) - 1;
-                mb &= mb - 1ull;
-                const int b = 64 * w + bit;
-                const uint32_t p0 = v.ptr[b], p1 = v.ptr[b + 1];
-                for (uint32_t q = p0 + (uint32_t)ln; q < p1; q += 64) {
-                    const uint32_t p = v.post[q];
-                    if ((int)p == i) continue;
-                    // lowest bit of mask[p] & R'
-                    int low = -1;
-#pragma unroll
-                    for (int ww = 0; ww < WF; ++ww) {
-                        const uint64_t x = v.masks[(size_t)p * WF + ww] & m[ww];
-                        if (low < 0 && x) low = 64 * ww + __ffsll((unsigned long long)x) - 1;
-                    }
-                    if (low == b)
-                        atomicOr(reinterpret_cast<unsigned long long *>(&c.ubm[p >> 6]), 1ull << (p & 63));
-                }
-            }
-        }
-        see_atomics();
-        nu = 0;
-        const int nwords_n = (F.n + 63) >> 6;
-        for (int base = 0; base < nwords_n; base += 64) {
+    {
+        const int wi = i >> 6;
+        const uint64_t bi = 1ull << (i & 63);
+        for (int base = 0; base < v.nw; base += 64) {
             const int wd = base + ln;
-            uint64_t bits = 0;
-            // read and clear each word in L2, where the marks were made
-            if (wd < nwords_n) bits = atomicExch(reinterpret_cast<unsigned long long *>(&c.ubm[wd]), 0ull);
-            const int pc = __popcll(bits);
+            uint64_t u, a;
+            fold_rows(c, v, r, wd, wd < v.nw, u, a);
+            if (wd == wi) {
+                u &= ~bi;
+                a &= ~bi;
+            }
+            ne_l += __popcll(a);
+            for (uint64_t f = a; f;) {
+                const int b = __ffsll((unsigned long long)f) - 1;
+                f &= f - 1ull;
+                exps += v.hs[64 * wd + b];
+            }
+            uint64_t qp = u & ~a;
+            qn_l += __popcll(qp & (wd < wi ? ~0ull : (wd == wi ? bi - 1ull : 0ull)));
+            const int pc = __popcll(qp);
             const int incl = wave_incl_scan(pc);
             int at = nu + incl - pc;
-            while (bits) {
-                const int bb = __ffsll((unsigned long long)bits) - 1;
-                bits &= bits - 1ull;
-                c.stu[at++] = (uint32_t)(wd * 64 + bb);
+            while (qp) {
+                const int b = __ffsll((unsigned long long)qp) - 1;
+                qp &= qp - 1ull;
+                c.stu[at++] = (uint32_t)(64 * wd + b);
             }
             nu += last_lane(incl);
         }
-        wait_mem();
     }
+    const int ne = wave_sum_i32(ne_l);
+    qn = wave_sum_i32(qn_l);
+    const int pn = nu - qn;
+    wait_mem();  // stu is read by other lanes below
     for (int b = ln; b < r; b += 64) c.hist[b] = 0u;
     __builtin_amdgcn_wave_barrier();
-    for (int base = 0; base < nu; base += 64) {
+    for (int base = DIAG ? 0 : qn; base < nu; base += 64) {
         const int j = base + ln;
-        bool act = j < nu;
-        const int k = act ? (scan ? j : (int)c.stu[j]) : 0;
-        act = act && k != i;
-        int cnt = 0;
-        if (act) {
+        if (j < nu) {
+            const int k = (int)c.stu[j];
+            if (j >= qn) {
+                int cnt = 0;
 #pragma unroll
-            for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
-        }
-        const bool inq = act && k < i && cnt > 0;  // cnt < r: the node passed the check
-        const bool full = act && k > i && cnt == r;
-        const bool inp = act && k > i && cnt > 0 && cnt < r;
-        if (full) exps += v.hs[k];
-        ne += __popcll(__ballot(full));
-        qn += __popcll(__ballot(inq));
-        pn += __popcll(__ballot(inp));
-        if (inp) atomicAdd(&c.hist[cnt], 1u);
-        if (inq || inp) {
-            csum += (uint32_t)cnt;
+                for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
+                atomicAdd(&c.hist[cnt], 1u);
+            }
             if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
         }
     }
@@ -847,13 +812,12 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
 
     // child frame: Q' then P' stably sorted by count; masks restricted to R' and, when
     // |R'| <= 64, compressed to |R'| bits
-    const uint32_t post2 = (uint32_t)wave_sum_i32((int)csum);
     bool ok;
     if constexpr (WF == 1) {
-        ok = build_child<1, W, true, DIAG>(c, F, v, m, scan, nu, i, r, qn, pn, post2, C);
+        ok = build_child<1, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C);
     } else {
-        ok = r <= 64 ? build_child<WF, W, true, DIAG>(c, F, v, m, scan, nu, i, r, qn, pn, post2, C)
-                     : build_child<WF, W, false, DIAG>(c, F, v, m, scan, nu, i, r, qn, pn, post2, C);
+        ok = r <= 64 ? build_child<WF, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C)
+                     : build_child<WF, W, false, DIAG>(c, F, v, m, nu, r, qn, pn, C);
     }
     if (!ok) return false;
     C.level = F.level + 1;
@@ -874,7 +838,6 @@ struct WGShared {
     unsigned long long fw1;
     unsigned long long hvsum;
     unsigned long long rs1;
-    unsigned long long post1;
     int nexp;
     int graph;  // graph whose tallies the workgroup is holding
     int mode;   // 0 done, 1 own task, 2 stolen task
@@ -1002,7 +965,6 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     uint32_t *degl = reinterpret_cast<uint32_t *>(wg + a.lay.off_deg);
     uint32_t *t1v = reinterpret_cast<uint32_t *>(wg + a.lay.off_t1v);
     uint32_t *t1c = reinterpret_cast<uint32_t *>(wg + a.lay.off_t1c);
-    uint32_t *cur1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_cur1);
     uint32_t *s1 = reinterpret_cast<uint32_t *>(wg + a.lay.off_S1);
     uint64_t *hb = reinterpret_cast<uint64_t *>(wg + a.lay.off_hb);
     uint32_t *hpre = reinterpret_cast<uint32_t *>(wg + a.lay.off_hpre);
@@ -1018,20 +980,13 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     c.c_off = a.c_off;
     c.s1 = s1;
     c.stk = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_stack);
-    c.cur = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_cur);
     c.stu = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_u);
-    c.ubm = reinterpret_cast<uint64_t *>(wv + a.lay.off_w_bm);
-    // the position bitmap must start out clear: the slot's memory may hold an earlier call's
-    // data under another layout
-    for (int wd = ln; wd < (a.dims.ucap + 63) / 64; wd += 64) c.ubm[wd] = 0ull;
-    wait_mem();
     c.hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * BITS;
     {
         // narrow-child table scratch: first[64] cnt[64] cur[64] (u32) then H[64] (u64) per wave
         unsigned char *tb = lds_raw + sizeof(WGShared) + (size_t)nw * BITS * 4 + (size_t)wid * 1280;
         c.tl_first = reinterpret_cast<uint32_t *>(tb);
         c.tl_cnt = c.tl_first + 64;
-        c.tl_cur = c.tl_first + 128;
         c.tl_H = reinterpret_cast<uint64_t *>(tb + 768);
     }
     c.scap = a.dims.scap;
@@ -1163,7 +1118,6 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             sh->fw1 = 0;
             sh->hvsum = 0;
             sh->rs1 = 0;
-            sh->post1 = 0;
             sh->nexp = 0;
             sh->claim = 0;
             sh->gclaim = 0;
@@ -1234,7 +1188,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         {
             bool nm = false;
             int pc = 0, nexp = 0;
-            uint64_t ex = 0, fw = 0, post = 0;
+            uint64_t ex = 0, fw = 0;
             for (int li = tid; li < s0; li += nt) {
                 int cc = 0;
 #pragma unroll
@@ -1247,7 +1201,6 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                         nm = true;
                     } else {
                         fw += dg;
-                        post += (uint64_t)cc;
                     }
                 } else if (cc == d) {
                     ex += hl(c, g);
@@ -1255,13 +1208,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 } else {
                     ++pc;
                     fw += dg;
-                    post += (uint64_t)cc;
                 }
             }
             if (__ballot(nm) && ln == 0) atomicOr(&sh->nonmax, 1);
             ex = wave_sum_u64(ex);
             fw = wave_sum_u64(fw);
-            post = wave_sum_u64(post);
             pc = wave_sum_i32(pc);
             nexp = wave_sum_i32(nexp);
             if (ln == 0) {
@@ -1269,7 +1220,6 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 atomicAdd(&sh->nexp, nexp);
                 atomicAdd(reinterpret_cast<unsigned long long *>(&sh->exps), (unsigned long long)ex);
                 atomicAdd(reinterpret_cast<unsigned long long *>(&sh->fw1), (unsigned long long)fw);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&sh->post1), (unsigned long long)post);
             }
         }
         wait_mem();
@@ -1314,20 +1264,6 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
             continue;
         }
         const int n1 = nq0 + P1;
-        const uint64_t post1 = sh->post1;
-        if ((int64_t)post1 > a.dims.post_cap) {
-            if (tid == 0) {
-                atomicOr(a.flags, (unsigned int)FLAG_UNIVERSE_OVERFLOW);
-                atomicMax(&a.acc[ACC_NEED_POST], (unsigned long long)post1);
-            }
-            __syncthreads();
-            if (DIAG) {
-                const uint64_t now = clock64();
-                acc.ph[PH_ROOT] += now - t_mark;
-                t_mark = now;
-            }
-            continue;
-        }
 
         // -- the top-level child list as a frame: ids Q1 (earlier ranks) ++ P1 sorted by
         //    count, masks over the positions of N(x), per-bit tables
@@ -1380,30 +1316,11 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         }
         __syncthreads();
         see_atomics();  // the top-level tables were built with atomics
-        if (wid == 0) {
-            int carry = 0;
-            for (int base = 0; base < BITS; base += 64) {
-                const int b = base + ln;
-                const int h = (int)v1.cnt[b];
-                const int incl = wave_incl_scan(h);
-                v1.ptr[b] = (uint32_t)(carry + incl - h);
-                cur1[b] = (uint32_t)(carry + incl - h);
-                carry += last_lane(incl);
-            }
-            if (ln == 0) v1.ptr[BITS] = (uint32_t)carry;
-        }
-        wait_mem();
-        __syncthreads();
-        for (int j = tid; j < n1; j += nt) {
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                uint64_t mm = masks1[(size_t)j * W + w];
-                while (mm) {
-                    const int b = 64 * w + __ffsll((unsigned long long)mm) - 1;
-                    mm &= mm - 1ull;
-                    v1.post[atomicAdd(&cur1[b], 1u)] = (uint32_t)j;
-                }
-            }
+        // position rows of the top-level list, one (64-entry chunk, mask word) block per wave
+        for (int job = wid; job < v1.nw * W; job += nw) {
+            const int w = job / W, q = job - w * W;
+            const int j = 64 * w + ln;
+            store_rows(v1, q, w, j < n1 ? masks1[(size_t)j * W + q] : 0ull);
         }
         wait_mem();
         __syncthreads();
@@ -1608,9 +1525,8 @@ ArenaLayout search_layout(const SearchDims &d) {
     L.off_deg = take(bits * 4);
     L.off_t1v = take(ucap * 4);
     L.off_t1c = take(ucap * 4);
-    L.off_cur1 = take(bits * 4);
-    // ids | masks | first | cnt | H | ptr | orig | post (see frame_view)
-    L.s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 2 * bits + 2 * bits + bits + 1 + 64 + (size_t)d.post_cap + 2;
+    // ids | hs | masks | first, cnt | H | orig | rows (see frame_view)
+    L.s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 2 * bits + 2 * bits + 64 + 2 * bits * ((ucap + 63) / 64) + 2;
     L.off_S1 = take(L.s1_words * 4);
     L.off_hb = take((ucap / 64 + 1) * 8);
     L.off_hpre = take((ucap / 64 + 2) * 4);
@@ -1623,9 +1539,7 @@ ArenaLayout search_layout(const SearchDims &d) {
         return at;
     };
     L.off_w_stack = wtake((size_t)d.scap * 4);
-    L.off_w_cur = wtake(bits * 4);
     L.off_w_u = wtake(ucap * 4);
-    L.off_w_bm = wtake((ucap + 63) / 64 * 8);
     L.off_w_hdr = wtake((size_t)d.maxdepth * sizeof(FrameState));
     L.wave_bytes = w;
     L.wg_bytes = align_up(o + (size_t)d.waves * w, 4096);
