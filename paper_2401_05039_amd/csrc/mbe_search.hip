@@ -146,7 +146,7 @@ struct FrameState {
     int32_t wf;      // mask words per entry
     int32_t narrow;  // 1: bits are compressed positions of R, mapped by orig[] to N(x) positions
     int32_t chunk;   // base position of the current 64-candidate chunk
-    int32_t pad;
+    int32_t rbits;   // rows held by the frame: mask bits [0, rbits) can be set
     uint64_t heavy;  // lanes of the current chunk still to be handled one by one
     uint64_t sL;     // sum of the L-side hash terms of L
     uint64_t fw;     // sum over the list of (2 + deg v), byte tally only
@@ -163,7 +163,7 @@ __device__ __forceinline__ FrameState uni_frame(const FrameState &f) {
     u.wf = uni(f.wf);
     u.narrow = uni(f.narrow);
     u.chunk = uni(f.chunk);
-    u.pad = 0;
+    u.rbits = uni(f.rbits);
     u.heavy = uni(f.heavy);
     u.sL = uni(f.sL);
     u.fw = uni(f.fw);
@@ -172,11 +172,12 @@ __device__ __forceinline__ FrameState uni_frame(const FrameState &f) {
 
 // Word layout of a frame's data starting at a 2-aligned offset o:
 //   ids[n] | hs[n] (u64) | masks[n][wf] (u64) | first[64wf] | cnt[64wf] | H[64wf] (u64) |
-//   orig[64] | rows[64wf][nw] (u64), nw = ceil(n / 64)
+//   orig[64] | rows[rbits][nw] (u64), nw = ceil(n / 64)
 // ids are universe indices (kept for diagnostics), hs the L-side hash term of each entry.
 // Row b is the position bitmap of mask bit b: bit k % 64 of its word k / 64 is set when entry
-// k holds bit b.  first / cnt / H: per bit, the first position holding it, how many entries
-// hold it, and the sum of their hash terms.
+// k holds bit b; only bits [0, rbits) can be set (rbits = |R| for a compressed frame).
+// first / cnt / H: per bit, the first position holding it, how many entries hold it, and the
+// sum of their hash terms (valid for bits below rbits).
 struct FrameView {
     const uint32_t *ids;
     const uint64_t *hs;
@@ -189,7 +190,7 @@ struct FrameView {
     int nw;
 };
 
-__device__ __forceinline__ uint32_t frame_words_fixed(int n, int wf) {
+__device__ __forceinline__ uint32_t frame_words_fixed(int n, int wf, int rbits) {
     const uint32_t bits = 64u * (uint32_t)wf, nw = ((uint32_t)n + 63u) >> 6;
     uint32_t o = align2((uint32_t)n);
     o += 2u * (uint32_t)n;                 // hs
@@ -197,11 +198,11 @@ __device__ __forceinline__ uint32_t frame_words_fixed(int n, int wf) {
     o += 2u * bits;                        // first, cnt
     o += 2u * bits;                        // H
     o += 64u;                              // orig
-    o += 2u * bits * nw;                   // rows
+    o += 2u * (uint32_t)rbits * nw;        // rows
     return o;
 }
 
-__device__ __forceinline__ FrameView frame_view(uint32_t *base, int n, int wf) {
+__device__ __forceinline__ FrameView frame_view(uint32_t *base, int n, int wf, int rbits) {
     const uint32_t bits = 64u * (uint32_t)wf;
     FrameView v;
     v.nw = (n + 63) >> 6;
@@ -391,15 +392,18 @@ __device__ __forceinline__ void narrow_table_add(const Ctx &c, uint32_t slot, ui
         atomicAdd(reinterpret_cast<unsigned long long *>(&c.tl_H[b]), (unsigned long long)h);
     }
 }
-__device__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n) {
+__device__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n, int r) {
     const int ln = lane_id();
     __builtin_amdgcn_wave_barrier();
-    v.first[ln] = c.tl_first[ln];
-    v.cnt[ln] = c.tl_cnt[ln];
-    v.H[ln] = c.tl_H[ln];
+    if (ln < r) {
+        v.first[ln] = c.tl_first[ln];
+        v.cnt[ln] = c.tl_cnt[ln];
+        v.H[ln] = c.tl_H[ln];
+    }
     for (int base = 0; base < n; base += 64) {
         const int k = base + ln;
-        store_rows(v, 0, base >> 6, k < n ? v.masks[k] : 0ull);
+        const uint64_t t = wave_transpose64(k < n ? v.masks[k] : 0ull);
+        if (ln < r) v.rows[(size_t)ln * v.nw + (base >> 6)] = t;
     }
     wait_mem();
 }
@@ -513,13 +517,14 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     const int n2 = qn + pn;
     constexpr int wf2 = NARROW ? 1 : W;
     const uint32_t off2 = F.top;
-    const uint32_t top2 = align2(off2 + frame_words_fixed(n2, wf2));
+    const int rbits2 = NARROW ? r : 64 * W;
+    const uint32_t top2 = align2(off2 + frame_words_fixed(n2, wf2, rbits2));
     if ((int64_t)top2 > c.scap) {
         if (ln == 0) atomicOr(c.flags, (unsigned int)FLAG_STACK_OVERFLOW);
         return false;
     }
     uint32_t *cb = c.stk + off2;
-    FrameView v2 = frame_view(cb, n2, wf2);
+    FrameView v2 = frame_view(cb, n2, wf2, rbits2);
     uint32_t *ids2 = cb;
     uint64_t *hs2 = const_cast<uint64_t *>(v2.hs);
     uint64_t *masks2 = const_cast<uint64_t *>(v2.masks);
@@ -602,7 +607,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
         }
     }
     wait_mem();
-    if (NARROW) narrow_table_finish(c, v2, n2);
+    if (NARROW) narrow_table_finish(c, v2, n2, r);
     else build_tables_wide<W>(v2, n2);
     C.off = off2;
     C.top = top2;
@@ -611,7 +616,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     C.wf = wf2;
     C.narrow = NARROW ? 1 : 0;
     C.chunk = qn - 64;
-    C.pad = 0;
+    C.rbits = rbits2;
     C.heavy = 0ull;
     return true;
 }
@@ -1267,7 +1272,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
 
         // -- the top-level child list as a frame: ids Q1 (earlier ranks) ++ P1 sorted by
         //    count, masks over the positions of N(x), per-bit tables
-        FrameView v1 = frame_view(s1, n1, W);
+        FrameView v1 = frame_view(s1, n1, W, d);
         uint32_t *ids1 = s1;
         for (int li = tid; li < nq0; li += nt) ids1[li] = (uint32_t)li;
         if (wid == 0) {
@@ -1317,10 +1322,12 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         __syncthreads();
         see_atomics();  // the top-level tables were built with atomics
         // position rows of the top-level list, one (64-entry chunk, mask word) block per wave
-        for (int job = wid; job < v1.nw * W; job += nw) {
-            const int w = job / W, q = job - w * W;
+        const int qd = (d + 63) >> 6;  // mask words holding bits of N(x)
+        for (int job = wid; job < v1.nw * qd; job += nw) {
+            const int w = job / qd, q = job - w * qd;
             const int j = 64 * w + ln;
-            store_rows(v1, q, w, j < n1 ? masks1[(size_t)j * W + q] : 0ull);
+            const uint64_t t = wave_transpose64(j < n1 ? masks1[(size_t)j * W + q] : 0ull);
+            if (64 * q + ln < d) v1.rows[(size_t)(64 * q + ln) * v1.nw + w] = t;
         }
         wait_mem();
         __syncthreads();
@@ -1339,7 +1346,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         top.wf = W;
         top.narrow = 0;
         top.chunk = 0;
-        top.pad = 0;
+        top.rbits = d;
         top.heavy = 0ull;
         top.sL = hl(c, x) + sh->exps;
         top.fw = sh->fw1;
@@ -1396,7 +1403,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         FrameState cur = top;
         int depth = 0;
         while (!aborted) {
-            const FrameView v = frame_view(frame_base(c, cur.off), cur.n, cur.wf);
+            const FrameView v = frame_view(frame_base(c, cur.off), cur.n, cur.wf, cur.rbits);
             int i;
             if (depth == 0) {
                 int got = 0;
