@@ -21,6 +21,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
+# HBM bytes moved by the search launches of one power-law step, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters scaled by a 1 GiB reference copy (profiles/search_kernel_powerlaw_100k_50k.md),
+# taken on the kernel source with this sha256; reported only while the source is unchanged.
+MEASURED_TRAFFIC = {"source_sha256": "e31343f2fdd22a24864a37c1c0583f1143cf0b31830522966560079f6279dcb1",
+                    "bytes_per_step": 3.043e11}
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -44,7 +50,15 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(g, rng_range, threads, budget_s=25.0):
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2401_05039_amd", "csrc", "mbe_search.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return MEASURED_TRAFFIC["bytes_per_step"] if sha == MEASURED_TRAFFIC["source_sha256"] else None
+
+
+def cpu_baseline(g, rng_range, threads):
     """The oracle (serial MBEA, split by top-level rank over host threads) on a bounded
     sample of the same graph: evenly spaced chunks of top-level candidates."""
     import numpy as np
@@ -54,7 +68,7 @@ def cpu_baseline(g, rng_range, threads, budget_s=25.0):
     n = oracle.num_roots(g)
     lo0, hi0 = rng_range if rng_range else (0, n)
     span = hi0 - lo0
-    frac = 0.04 if rng_range is None else 1.0
+    frac = 0.2 if rng_range is None else 1.0
     chunks = 64 if rng_range is None else min(16, span)
     per = max(1, int(span * frac / chunks))
     starts = np.linspace(lo0, hi0 - per, chunks).astype(np.int64)
@@ -265,7 +279,10 @@ def main():
         "data": "synthetic",
         "config": dict(desc, count=diag["count"], hash=hex(diag["hash"]), search_nodes=diag["nodes"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.workload == "power-law" else None,
+                     "traffic_gbs": (measured_traffic() / (kavg / 1000.0) / 1e9
+                                     if args.workload == "power-law" and measured_traffic() else None),
                      "kernel": "search_kernel (all mask-width launches of one step)",
                      "kernel_ms": kavg, "bytes_alg": diag["bytes_alg"]},
         "phase_share": phase_share,
