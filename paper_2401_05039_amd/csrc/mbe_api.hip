@@ -205,7 +205,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         v_adj = d_vadj;
     }
 
-    // small device block: acc[16] | flags | counters[8] | stats[16]
+    // small device block: acc[16] | flags | counters[8] + live steal slots[8] | stats[16]
     MBE_TRY(st->small.ensure(4096));
     unsigned long long *acc = st->small.as<unsigned long long>(0);
     unsigned int *flags = st->small.as<unsigned int>(256);
@@ -408,13 +408,14 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         MBE_TRY(hipMemsetAsync(run_acc, 0, run_acc_bytes, s));
         if (graph_acc && graph_acc != run_acc) MBE_TRY(hipMemsetAsync(graph_acc, 0, graph_acc_bytes, s));
         MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
-        MBE_TRY(hipMemsetAsync(counters, 0, 8 * 4, s));
+        MBE_TRY(hipMemsetAsync(counters, 0, 16 * 4, s));
         MBE_TRY(hipEventRecord(st->ev0, s));
         if (!sequential) MBE_TRY(hipEventRecord(st->fork, s));
         for (int c = 4; c >= 0; --c) {
             if (cls_lo[c] >= cls_hi[c]) continue;
             SearchArgs ac = a;
             ac.steal = st->steal.as<StealSlot>() + (size_t)c * nslots;
+            ac.steal_live = counters + 8 + c;
             hipStream_t cs = s;
             if (!sequential) {
                 cs = st->cls_stream[c];

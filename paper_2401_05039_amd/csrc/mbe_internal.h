@@ -119,6 +119,7 @@ struct SearchArgs {
     ArenaLayout lay;
     StealSlot *steal;           // one per arena slot for this launch's mask class, zeroed first
     int32_t steal_on;           // 0: no stealing (each top-level candidate stays in one workgroup)
+    unsigned int *steal_live;   // number of this launch's slots currently published (zeroed first)
     int32_t nslots;             // arena slots shared by the concurrent launches
     unsigned int *slot_busy;    // nslots flags: a slot is held by a running workgroup
     // outputs

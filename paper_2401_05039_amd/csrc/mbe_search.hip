@@ -1015,38 +1015,73 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     __syncthreads();
 
     for (;;) {
-        if (tid == 0) {
-            // a fresh top-level candidate, else a share of another workgroup's child list;
+        if (wid == 0) {
+            // a fresh top-level candidate, else a share of another workgroup's item list;
             // stop once a capacity ran out (the host reruns with more room)
-            const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sh->mode = 0;
-            if (!(f & FLAG_RERUN)) {
-                const unsigned int t = atomicAdd(counter, 1u);
-                if (lo + (int64_t)t < hi) {
-                    sh->mode = 1;
-                    sh->task = t;
-                    sh->epoch = t + 1u;
-                } else if (a.steal_on) {
-                    for (int j = 1; j < a.nslots && sh->mode == 0; ++j) {
-                        const int vwg = (my_slot + j) % a.nslots;
-                        StealSlot *sl = &a.steal[vwg];
-                        const unsigned long long w1 = __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                        const unsigned int e = (unsigned int)(w1 >> 32);
-                        if (e == 0u) continue;
-                        const int sg = __hip_atomic_load(&sl->g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const int sk = __hip_atomic_load(&sl->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const int lim = __hip_atomic_load(&sl->limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __threadfence();
-                        const unsigned long long w2 = __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                        if ((unsigned int)(w2 >> 32) != e) continue;       // owner moved on meanwhile
-                        if ((int)(unsigned int)w2 + 2 > lim) continue;     // under two items left
-                        sh->mode = 2;
-                        sh->victim = vwg;
-                        sh->epoch = e;
-                        sh->sg = sg;
-                        sh->sk = sk;
+            int mode = 0;
+            unsigned int t = 0;
+            if (ln == 0) {
+                const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!(f & FLAG_RERUN)) {
+                    t = atomicAdd(counter, 1u);
+                    mode = lo + (int64_t)t < hi ? 1 : 0;
+                    if (mode == 0 && !(a.steal_on &&
+                                       __hip_atomic_load(a.steal_live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u))
+                        mode = -1;  // nothing published: no scan
+                } else {
+                    mode = -1;
+                }
+            }
+            mode = __builtin_amdgcn_readlane(mode, 0);
+            if (mode == 1 && ln == 0) {
+                sh->mode = 1;
+                sh->task = t;
+                sh->epoch = t + 1u;
+            } else if (mode != 1) {
+                // look for a published list with at least two unclaimed items, 64 slots at a time
+                bool found = false;
+                if (mode == 0) {
+                    for (int base = 1; base < a.nslots && !found; base += 64) {
+                        const int j = base + ln;
+                        bool ok = false;
+                        int vwg = 0, sg = 0, sk = 0;
+                        unsigned int e = 0;
+                        if (j < a.nslots) {
+                            vwg = (my_slot + j) % a.nslots;
+                            StealSlot *sl = &a.steal[vwg];
+                            const unsigned long long w1 =
+                                __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                            e = (unsigned int)(w1 >> 32);
+                            if (e != 0u) {
+                                sg = __hip_atomic_load(&sl->g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                sk = __hip_atomic_load(&sl->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                const int lim = __hip_atomic_load(&sl->limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                __threadfence();
+                                const unsigned long long w2 =
+                                    __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                                // the owner has not moved on, and two or more items are left
+                                ok = (unsigned int)(w2 >> 32) == e && (int)(unsigned int)w2 + 2 <= lim;
+                            }
+                        }
+                        const uint64_t okb = __ballot(ok);
+                        if (okb) {
+                            const int src = __ffsll((unsigned long long)okb) - 1;
+                            vwg = __builtin_amdgcn_readlane(vwg, src);
+                            sg = __builtin_amdgcn_readlane(sg, src);
+                            sk = __builtin_amdgcn_readlane(sk, src);
+                            e = (unsigned int)__builtin_amdgcn_readlane((int)e, src);
+                            if (ln == 0) {
+                                sh->mode = 2;
+                                sh->victim = vwg;
+                                sh->epoch = e;
+                                sh->sg = sg;
+                                sh->sk = sk;
+                            }
+                            found = true;
+                        }
                     }
                 }
+                if (!found && ln == 0) sh->mode = 0;
             }
         }
         __syncthreads();
@@ -1386,6 +1421,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
                 __threadfence();
                 __hip_atomic_store(&slot->word, (unsigned long long)sh->epoch << 32, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
+                atomicAdd(a.steal_live, 1u);
                 sh->gclaim = 1;
             }
         }
@@ -1452,8 +1488,10 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
         if (DIAG) t_mark = clock64();  // from here to the next task: waiting
         __syncthreads();
         // every chunk is claimed: withdraw the list (thieves still finish the chunks they hold)
-        if (tid == 0 && gclaim && !thief)
+        if (tid == 0 && gclaim && !thief) {
             __hip_atomic_store(&slot->word, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            atomicSub(a.steal_live, 1u);
+        }
     }
 
     // tallies of the last graph
