@@ -85,19 +85,34 @@ def cpu_baseline(g, rng_range, threads):
 def bench_batch(args, mbe):
     """Batched form: n independent graphs (|U|, |V| log-uniform in [50, 2000], density uniform
     in [0.01, 0.1], ER or Chung-Lu) in one mbe_count_batch call, against one mbe_count call
-    per graph.  Both take host graphs, so both include the upload and the preparation."""
+    per graph.  The launch setting is picked first by the autotuner (mbe_tune_batch) on every
+    eighth graph and then used by both forms.  Both take host graphs, so both include the
+    upload and the preparation."""
     import graphgen as gg
     t0 = time.time()
     gs = [gg.config4_graph(i) for i in range(args.batch_n)]
     log(f"generated {len(gs)} graphs, {sum(g.n_edges for g in gs)} edges, in {time.time() - t0:.1f} s")
-    opt = mbe.Options(wg_waves=args.waves, grid=args.grid)
+    base = mbe.Options(wg_waves=args.waves, grid=args.grid)
+    t0 = time.perf_counter()
+    opt, tuned_ms = mbe.mbe_tune_batch(gs[::8], base)
+    t_tune = time.perf_counter() - t0
+    log(f"tuned on {len(gs[::8])} graphs in {t_tune:.1f} s: wg_waves={opt.wg_waves} steal_k={opt.steal_k} "
+        f"({tuned_ms:.0f} ms per sample batch)")
     mbe.mbe_count_batch(gs[:64], opt)
     for g in gs[:8]:
         mbe.mbe_count(g, opt)
+    # the plain form, one call per graph, under the tuned setting and under the defaults;
+    # the faster of the two is the baseline
     t0 = time.perf_counter()
     plain = [mbe.mbe_count(g, opt) for g in gs]
-    t_plain = time.perf_counter() - t0
-    log(f"plain: {t_plain:.3f} s")
+    t_plain_tuned = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plain_def = [mbe.mbe_count(g, base) for g in gs]
+    t_plain_def = time.perf_counter() - t0
+    t_plain = min(t_plain_tuned, t_plain_def)
+    if t_plain_def < t_plain_tuned:
+        plain = plain_def
+    log(f"plain: {t_plain_tuned:.3f} s tuned setting, {t_plain_def:.3f} s defaults")
     times = []
     for _ in range(max(1, args.steps)):
         t0 = time.perf_counter()
@@ -107,6 +122,9 @@ def bench_batch(args, mbe):
     for i, (a, b) in enumerate(zip(plain, res)):
         assert (a["count"], a["hash"]) == (b["count"], b["hash"]), i
     total = sum(r["count"] for r in res)
+    # share of the plain time spent on the graphs that need >= 10% of a second alone
+    heavy = sorted(((r["kernel_ms"], r["count"]) for r in plain), reverse=True)
+    heavy_ms = sum(k for k, _ in heavy if k >= 100.0)
     out = {
         "metric": "graphs/s batched vs plain",
         "value": len(gs) / t_batch,
@@ -122,10 +140,16 @@ def bench_batch(args, mbe):
         "data": "synthetic",
         "config": {"workload": f"batch of {len(gs)} ER / Chung-Lu bipartite graphs, sides log-uniform [50, 2000], "
                                f"density U[0.01, 0.1]", "graphs": len(gs), "edges": sum(g.n_edges for g in gs),
-                   "bicliques": total},
+                   "bicliques": total, "tuned": {"wg_waves": opt.wg_waves, "steal_k": opt.steal_k,
+                                                 "tune_s": t_tune, "sample_graphs": len(gs[::8])}},
         "plain_graphs_per_s": len(gs) / t_plain,
+        "plain_s_tuned_setting": t_plain_tuned,
+        "plain_s_defaults": t_plain_def,
         "batched_over_plain": t_plain / t_batch,
         "batch_kernel_ms": res[0]["kernel_ms"] if res else 0.0,
+        "plain_kernel_ms_heaviest_graphs": heavy_ms,
+        "plain_heaviest_graphs": sum(1 for k, _ in heavy if k >= 100.0),
+        "bicliques_per_s_batched": total / t_batch,
     }
     print(json.dumps(out), flush=True)
 
@@ -134,19 +158,21 @@ def bench_serve(args, mbe):
     """Serving form: requests arrive as a Poisson stream at --rate per second; 90% are
     batched-workload graphs, 10% Chung-Lu graphs with |U| log-uniform in [20k, --big-max-u],
     |V| = |U|/2, E = min(5M, 25 |U|).  A continuous-batching server admits them by device
-    footprint; latency is submission to completion."""
+    footprint (one slot reserved for small requests); latency is submission to completion.
+    Then the same requests are submitted all at once (the server's capacity) and run one
+    mbe_count call at a time (the plain form)."""
     import threading
     import numpy as np
     import graphgen as gg
     t0 = time.time()
     reqs = gg.config5_requests(args.serve_n, args.rate, big_max_u=args.big_max_u)
-    log(f"generated {len(reqs)} requests ({sum(1 for _, g in reqs if g.n_u >= 20000)} large), "
-        f"{sum(g.n_edges for _, g in reqs)} edges, in {time.time() - t0:.1f} s")
+    n_big = sum(1 for _, g in reqs if g.n_u >= 20000)
+    log(f"generated {len(reqs)} requests ({n_big} large), {sum(g.n_edges for _, g in reqs)} edges, "
+        f"in {time.time() - t0:.1f} s")
     lat = [0.0] * len(reqs)
     res = [None] * len(reqs)
     with mbe.Server(slots=args.slots) as sv:
-        # warm the slots' workspaces
-        for tk in [sv.submit(g) for _, g in reqs[:8]]:
+        for tk in [sv.submit(g) for _, g in reqs[:8]]:  # warm the slots' workspaces
             sv.wait(tk)
         tickets = [None] * len(reqs)
         start = time.perf_counter()
@@ -164,7 +190,22 @@ def bench_serve(args, mbe):
         for i in range(len(reqs)):
             res[i], lat[i] = sv.wait(tickets[i])
         span = time.perf_counter() - start
+        log(f"poisson run: {span:.1f} s")
+        # capacity: everything queued at once
+        t0 = time.perf_counter()
+        tks = [sv.submit(g) for _, g in reqs]
+        sat = [sv.wait(tk)[0] for tk in tks]
+        t_sat = time.perf_counter() - t0
+        log(f"saturated run: {t_sat:.1f} s")
+    t0 = time.perf_counter()
+    plain = [mbe.mbe_count(g) for _, g in reqs]
+    t_plain = time.perf_counter() - t0
+    log(f"plain run: {t_plain:.1f} s")
+    for i in range(len(reqs)):
+        assert (res[i]["count"], res[i]["hash"]) == (plain[i]["count"], plain[i]["hash"]), i
+        assert (sat[i]["count"], sat[i]["hash"]) == (plain[i]["count"], plain[i]["hash"]), i
     lat_a = np.array(lat)
+    small = np.array([g.n_u < 20000 for _, g in reqs])
     out = {
         "metric": "served graphs/s; p50/p99 solve latency",
         "value": len(reqs) / span,
@@ -180,10 +221,17 @@ def bench_serve(args, mbe):
         "data": "synthetic",
         "config": {"workload": f"Poisson stream of {len(reqs)} requests at {args.rate}/s, 90% batch-style graphs, "
                                f"10% Chung-Lu |U| up to {args.big_max_u}", "slots": args.slots,
-                   "edges": sum(g.n_edges for _, g in reqs), "bicliques": sum(r["count"] for r in res)},
+                   "large_requests": n_big, "edges": sum(g.n_edges for _, g in reqs),
+                   "bicliques": sum(r["count"] for r in res)},
         "p50_ms": float(np.percentile(lat_a, 50)),
         "p99_ms": float(np.percentile(lat_a, 99)),
+        "p50_ms_small": float(np.percentile(lat_a[small], 50)),
+        "p99_ms_small": float(np.percentile(lat_a[small], 99)),
+        "p50_ms_large": float(np.percentile(lat_a[~small], 50)) if n_big else None,
         "offered_rate": args.rate,
+        "saturated_graphs_per_s": len(reqs) / t_sat,
+        "plain_graphs_per_s": len(reqs) / t_plain,
+        "served_over_plain": t_plain / t_sat,
     }
     print(json.dumps(out), flush=True)
 
@@ -201,8 +249,8 @@ def main():
                     help="first run one plain device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for scaling hardware byte counters)")
     ap.add_argument("--batch-n", type=int, default=4096)
-    ap.add_argument("--serve-n", type=int, default=400)
-    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--serve-n", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=2.5)
     ap.add_argument("--slots", type=int, default=2)
     ap.add_argument("--big-max-u", type=int, default=200_000)
     args = ap.parse_args()

@@ -105,6 +105,10 @@ typedef struct mbe_result {
  *   grid         workgroups of the persistent search kernel (default: 2 per compute unit).
  *   diagnostics  1: also compute nodes / nonmaximal / max_depth / bytes_alg.
  *   no_validate  1: skip the O(|E|) check of the CSR pair (the caller vouches for it).
+ *   steal_k      work sharing below a top-level candidate (the k of section III-D): 2
+ *                (default): the candidates of its child list that need a full node are
+ *                claimed one at a time by the owning workgroup's waves and by idle
+ *                workgroups, which rebuild the same list; 1: by the owning workgroup only.
  *   root_lo, root_hi
  *                restrict the search to the top-level candidates whose rank lies in
  *                [root_lo, root_hi) (rank = position in ascending (degree, id) order among
@@ -118,7 +122,7 @@ typedef struct mbe_options {
     int32_t grid;
     int32_t diagnostics;
     int32_t no_validate;
-    int32_t reserved0;
+    int32_t steal_k;
     int64_t root_lo;
     int64_t root_hi;
     void *stream;
@@ -156,6 +160,16 @@ int mbe_enumerate(const mbe_graph *g, const mbe_options *opt, mbe_result *out,
  */
 int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_result *outs);
 
+/*
+ * Autotuner of the batched form: runs mbe_count_batch on the given graphs (a representative
+ * sample of the batches to come) under each candidate launch setting -- waves per workgroup
+ * in {8, 4, 2} times steal_k in {2, 1} -- starting from base (NULL: defaults), checks that
+ * every setting gives the same per-graph count and hash, and writes the fastest setting
+ * (wall time of the whole call) to *best and its time in milliseconds to *best_ms (may be
+ * NULL).  Errors as mbe_count_batch; MBE_ERR_DEVICE if two settings disagree.
+ */
+int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_options *best, double *best_ms);
+
 /* ------------------------------------------------------------------------- serving */
 /*
  * A server runs enumeration requests with continuous batching.  Each of its slots (a host
@@ -168,6 +182,9 @@ int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_
  *   hbm_budget_bytes  device memory the slots may plan for (0: half of the free memory)
  *   slots             concurrent batches (1..8; default 2)
  *   max_batch         most requests per batch (default 4096)
+ *   small_edges       with slots >= 2, slot 0 is reserved for requests with at most this many
+ *                     edges, so that small requests do not queue behind large ones
+ *                     (default 65536; negative: no reserved slot)
  *   search            per-search options (side, wg_waves, grid, diagnostics, no_validate)
  */
 typedef struct mbe_server mbe_server;
@@ -175,6 +192,7 @@ typedef struct mbe_server_options {
     size_t hbm_budget_bytes;
     int32_t slots;
     int32_t max_batch;
+    int64_t small_edges;
     mbe_options search;
 } mbe_server_options;
 

@@ -52,7 +52,7 @@ class _Result(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("side", ctypes.c_int32), ("wg_waves", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("diagnostics", ctypes.c_int32), ("no_validate", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("root_lo", ctypes.c_int64),
+                ("steal_k", ctypes.c_int32), ("root_lo", ctypes.c_int64),
                 ("root_hi", ctypes.c_int64), ("stream", ctypes.c_void_p)]
 
 
@@ -64,6 +64,7 @@ class Options:
     grid: int = 0
     diagnostics: bool = False
     no_validate: bool = False
+    steal_k: int = 0
     root_lo: int = 0
     root_hi: int = 0
     stream: Optional[int] = None  # hipStream_t as an integer; None = torch's current stream
@@ -71,7 +72,7 @@ class Options:
 
 class _ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("search", _Options)]
+                ("small_edges", ctypes.c_int64), ("search", _Options)]
 
 
 class MbeError(RuntimeError):
@@ -101,6 +102,9 @@ def load():
     lib.mbe_count_batch.argtypes = [ctypes.POINTER(_Graph), ctypes.c_int32, ctypes.POINTER(_Options),
                                      ctypes.POINTER(_Result)]
     lib.mbe_count_batch.restype = ctypes.c_int
+    lib.mbe_tune_batch.argtypes = [ctypes.POINTER(_Graph), ctypes.c_int32, ctypes.POINTER(_Options),
+                                   ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_double)]
+    lib.mbe_tune_batch.restype = ctypes.c_int
     lib.mbe_server_create.argtypes = [ctypes.POINTER(_ServerOptions), ctypes.POINTER(ctypes.c_void_p)]
     lib.mbe_server_create.restype = ctypes.c_int
     lib.mbe_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Graph), ctypes.POINTER(ctypes.c_uint64)]
@@ -162,7 +166,7 @@ def _marshal_opts(opt: Optional[Options], on_device: bool) -> _Options:
         import torch
         stream = torch.cuda.current_stream().cuda_stream
     return _Options(opt.side, opt.wg_waves, opt.grid, int(bool(opt.diagnostics)), int(bool(opt.no_validate)),
-                    0, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0))
+                    opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0))
 
 
 PHASES = ("root", "light", "check", "expand", "child", "wait")
@@ -186,19 +190,41 @@ def mbe_count(g, opt: Optional[Options] = None) -> Dict[str, Any]:
     return _result_dict(res)
 
 
-def mbe_count_batch(graphs, opt: Optional[Options] = None) -> List[Dict[str, Any]]:
-    """Count and hash the maximal bicliques of many host graphs in one batched pass; returns
-    one result dict per graph (kernel_ms is the time of the whole batch)."""
-    lib = load()
+def _marshal_batch(graphs):
     n = len(graphs)
     arr = (_Graph * max(1, n))()
     keep: List[Any] = []
     for i, g in enumerate(graphs):
         cg, k = _marshal_graph(g)
         if cg.on_device:
-            raise ValueError("mbe_count_batch takes host graphs")
+            raise ValueError("batched calls take host graphs")
         arr[i] = cg
         keep.append(k)
+    return arr, keep
+
+
+def mbe_tune_batch(graphs, opt: Optional[Options] = None):
+    """Autotune the batched form on a sample of graphs (``mbe_tune_batch``); returns the
+    fastest Options and its wall time in milliseconds."""
+    lib = load()
+    arr, keep = _marshal_batch(graphs)
+    co = _marshal_opts(opt, False)
+    best = _Options()
+    ms = ctypes.c_double(0.0)
+    rc = lib.mbe_tune_batch(arr, len(graphs), ctypes.byref(co), ctypes.byref(best), ctypes.byref(ms))
+    if rc != MBE_OK:
+        raise MbeError(rc)
+    base = opt or Options()
+    tuned = dataclasses.replace(base, wg_waves=best.wg_waves, steal_k=best.steal_k)
+    return tuned, ms.value
+
+
+def mbe_count_batch(graphs, opt: Optional[Options] = None) -> List[Dict[str, Any]]:
+    """Count and hash the maximal bicliques of many host graphs in one batched pass; returns
+    one result dict per graph (kernel_ms is the time of the whole batch)."""
+    lib = load()
+    n = len(graphs)
+    arr, keep = _marshal_batch(graphs)
     co = _marshal_opts(opt, False)
     res = (_Result * max(1, n))()
     rc = lib.mbe_count_batch(arr, n, ctypes.byref(co), res)
@@ -212,9 +238,9 @@ class Server:
     thread, wait for each result; results equal those of ``mbe_count`` on the graph alone."""
 
     def __init__(self, hbm_budget_bytes: int = 0, slots: int = 2, max_batch: int = 0,
-                 opt: Optional[Options] = None):
+                 opt: Optional[Options] = None, small_edges: int = 0):
         lib = load()
-        so = _ServerOptions(hbm_budget_bytes, slots, max_batch, _marshal_opts(opt, False))
+        so = _ServerOptions(hbm_budget_bytes, slots, max_batch, small_edges, _marshal_opts(opt, False))
         h = ctypes.c_void_p()
         rc = lib.mbe_server_create(ctypes.byref(so), ctypes.byref(h))
         if rc != MBE_OK:

@@ -133,19 +133,20 @@ bool host_valid(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *
 }
 
 struct Opts {
-    int side, waves, grid, diag, no_validate;
+    int side, waves, grid, diag, no_validate, steal_k;
     int64_t root_lo, root_hi;
     hipStream_t stream;
 };
 
 Opts read_opts(const mbe_options *o) {
-    Opts r{0, 8, 0, 0, 0, 0, -1, nullptr};
+    Opts r{0, 8, 0, 0, 0, 2, 0, -1, nullptr};
     if (!o) return r;
     r.side = o->side;
     r.waves = o->wg_waves > 0 ? o->wg_waves : 8;
     r.grid = o->grid > 0 ? o->grid : 0;
     r.diag = o->diagnostics != 0;
     r.no_validate = o->no_validate != 0;
+    r.steal_k = o->steal_k == 0 ? 2 : o->steal_k;
     r.root_lo = o->root_lo > 0 ? o->root_lo : 0;
     r.root_hi = o->root_hi > 0 ? o->root_hi : -1;
     r.stream = static_cast<hipStream_t>(o->stream);
@@ -163,7 +164,9 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     std::memset(out, 0, sizeof(*out));
     if (g->n_u < 0 || g->n_v < 0 || g->n_edges < 0) return MBE_ERR_INVALID_ARG;
     Opts opt = read_opts(opt_in);
-    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8) return MBE_ERR_INVALID_ARG;
+    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
+        opt.steal_k < 1 || opt.steal_k > 2)
+        return MBE_ERR_INVALID_ARG;
     if (enumerate && !ubuf && ucap_ints > 0) return MBE_ERR_INVALID_ARG;
     const int side = opt.side ? opt.side : (g->n_v < g->n_u ? 2 : 1);
     out->side = (uint32_t)side;
@@ -297,6 +300,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     MBE_TRY(hipMemcpyAsync(d_gd, &gd, sizeof(gd), hipMemcpyHostToDevice, s));
 
     SearchArgs a{};
+    a.steal_on = opt.steal_k >= 2 ? 1 : 0;
     a.c_off = c_off;
     a.c_adj = c_adj;
     a.o_off = o_off;
@@ -401,7 +405,6 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         MBE_TRY(st->slots.ensure(sizeof(unsigned int) * (size_t)nslots));
         a.slot_busy = st->slots.as<unsigned int>();
         MBE_TRY(st->steal.ensure(sizeof(StealSlot) * (size_t)nslots * 5));
-        a.steal_on = 1;
         MBE_TRY(hipMemset2DAsync(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, 0, (size_t)dims.nwords * 8, (size_t)nslots, s));
         MBE_TRY(hipMemsetAsync(a.slot_busy, 0, sizeof(unsigned int) * (size_t)nslots, s));
         MBE_TRY(hipMemsetAsync(st->steal.p, 0, sizeof(StealSlot) * (size_t)nslots * 5, s));
@@ -477,7 +480,9 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
 int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_result *outs) {
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
     const Opts opt = read_opts(opt_in);
-    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8) return MBE_ERR_INVALID_ARG;
+    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
+        opt.steal_k < 1 || opt.steal_k > 2)
+        return MBE_ERR_INVALID_ARG;
     for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
     const int rc = check_graphs(gs, n, !opt.no_validate);
     if (rc != MBE_OK) return rc;
@@ -499,7 +504,9 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
                  mbe_result *outs) {
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
     Opts opt = read_opts(opt_in);
-    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8) return MBE_ERR_INVALID_ARG;
+    if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
+        opt.steal_k < 1 || opt.steal_k > 2)
+        return MBE_ERR_INVALID_ARG;
     for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
     // host checks and packing (each graph keeps its own candidate side)
     std::vector<int32_t> side(n), nc(n), no(n), cb(n + 1, 0), ob(n + 1, 0), eb(n + 1, 0);
@@ -653,6 +660,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     const int grid = opt.grid > 0 ? opt.grid : 0;  // 0: occupancy-sized per class
 
     SearchArgs a{};
+    a.steal_on = opt.steal_k >= 2 ? 1 : 0;
     a.c_off = d_coff;
     a.c_adj = d_cadj;
     a.o_off = d_ooff;
@@ -739,6 +747,8 @@ struct mbe_server {
     bool stopping = false;
     size_t slot_budget = 0;
     int max_batch = 4096;
+    int64_t small_edges = 1 << 16;  // slot 0 takes only requests this small (when slots >= 2)
+    int nslots = 1;
     int device = 0;
     int cus = 256;
     mbe_options search{};
@@ -771,18 +781,31 @@ struct mbe_server {
         for (;;) {
             std::vector<std::shared_ptr<ServerRequest>> batch;
             {
+                // slot 0 is the small-request lane when there are other slots: requests queued
+                // behind a large one still start at once
+                const bool small_lane = slot == 0 && nslots >= 2 && small_edges >= 0;
+                auto eligible = [&](const ServerRequest &r) { return !small_lane || r.g.n_edges <= small_edges; };
+                auto any_eligible = [&] {
+                    for (const auto &r : pending)
+                        if (eligible(*r)) return true;
+                    return false;
+                };
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
-                if (pending.empty()) return;  // stopping
+                cv_work.wait(lk, [&] { return stopping || any_eligible(); });
+                if (!any_eligible()) return;  // stopping; other slots finish the rest
                 size_t csr = 0, arena = 0;
-                while (!pending.empty() && (int)batch.size() < max_batch) {
-                    const ServerRequest &r = *pending.front();
+                for (auto it = pending.begin(); it != pending.end() && (int)batch.size() < max_batch;) {
+                    const ServerRequest &r = **it;
+                    if (!eligible(r)) {
+                        ++it;
+                        continue;
+                    }
                     const size_t need = csr + r.csr_bytes + std::max(arena, r.arena_bytes);
                     if (!batch.empty() && need > slot_budget) break;
                     csr += r.csr_bytes;
                     arena = std::max(arena, r.arena_bytes);
-                    batch.push_back(pending.front());
-                    pending.pop_front();
+                    batch.push_back(*it);
+                    it = pending.erase(it);
                 }
             }
             std::vector<mbe_graph> gs(batch.size());
@@ -823,9 +846,11 @@ int server_create(const mbe_server_options *opt, mbe_server **out) {
     if (opt) {
         sv->search = opt->search;
         if (opt->max_batch > 0) sv->max_batch = opt->max_batch;
+        if (opt->small_edges != 0) sv->small_edges = opt->small_edges;
     }
     sv->search.root_lo = sv->search.root_hi = 0;
-    if (sv->search.wg_waves < 0 || sv->search.wg_waves > 8 || sv->search.side < 0 || sv->search.side > 2)
+    if (sv->search.wg_waves < 0 || sv->search.wg_waves > 8 || sv->search.side < 0 || sv->search.side > 2 ||
+        sv->search.steal_k < 0 || sv->search.steal_k > 2)
         return MBE_ERR_INVALID_ARG;
     MBE_TRY(hipGetDevice(&sv->device));
     if (hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, sv->device) != hipSuccess || sv->cus <= 0)
@@ -837,6 +862,7 @@ int server_create(const mbe_server_options *opt, mbe_server **out) {
         budget = free_b / 2;
     }
     sv->slot_budget = budget / (size_t)slots;
+    sv->nslots = slots;
     for (int k = 0; k < slots; ++k) {
         DeviceState *st = new DeviceState();
         if (hipEventCreate(&st->ev0) != hipSuccess || hipEventCreate(&st->ev1) != hipSuccess) {
@@ -890,7 +916,7 @@ int mbe_server_submit(mbe_server *sv, const mbe_graph *g, uint64_t *ticket) {
         sv->live[r->ticket] = r;
         sv->pending.push_back(r);
     }
-    sv->cv_work.notify_one();
+    sv->cv_work.notify_all();  // the small-request lane may be the one that can take it
     *ticket = r->ticket;
     return MBE_OK;
 }
@@ -932,6 +958,43 @@ int mbe_server_destroy(mbe_server *sv) {
 
 int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_result *outs) {
     return run_batch(gs, n, opt, outs);
+}
+
+int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_options *best, double *best_ms) {
+    if (!gs || n <= 0 || !best) return MBE_ERR_INVALID_ARG;
+    const mbe_options b = base ? *base : mbe_options{};
+    std::vector<mbe_result> ref((size_t)n), outs((size_t)n);
+    // candidates: waves per workgroup x work sharing; the first run also warms the workspace
+    static const int kWaves[] = {8, 4, 2};
+    static const int kSteal[] = {2, 1};
+    double bt = 0.0;
+    bool have = false;
+    for (int wi = 0; wi < 3; ++wi) {
+        for (int si = 0; si < 2; ++si) {
+            mbe_options o = b;
+            o.wg_waves = kWaves[wi];
+            o.steal_k = kSteal[si];
+            o.diagnostics = 0;
+            if (!have) {
+                const int rc = run_batch(gs, n, &o, ref.data());
+                if (rc != MBE_OK) return rc;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            const int rc = run_batch(gs, n, &o, outs.data());
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rc != MBE_OK) return rc;
+            for (int32_t i = 0; i < n; ++i)  // every setting must give the same answers
+                if (outs[i].count != ref[i].count || outs[i].hash != ref[i].hash) return MBE_ERR_DEVICE;
+            if (!have || ms < bt) {
+                bt = ms;
+                *best = o;
+                have = true;
+            }
+        }
+    }
+    if (best_ms) *best_ms = bt;
+    return MBE_OK;
 }
 
 

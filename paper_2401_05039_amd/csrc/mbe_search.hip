@@ -341,9 +341,10 @@ __device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, in
     }
 }
 
-// Per-bit tables and rows of a wide frame whose entries are in place.  One wave.
+// Per-bit tables and rows of a wide frame whose entries are in place; its masks lie within
+// the words of R (m): rows of the other words are never read and are not written.  One wave.
 template <int WF>
-__device__ void build_tables_wide(const FrameView &v, int n) {
+__device__ void build_tables_wide(const FrameView &v, int n, const uint64_t (&m)[WF]) {
     constexpr int bits = 64 * WF;
     const int ln = lane_id();
     for (int b = ln; b < bits; b += 64) {
@@ -358,11 +359,12 @@ __device__ void build_tables_wide(const FrameView &v, int n) {
         const uint64_t h = act ? v.hs[k] : 0ull;
 #pragma unroll
         for (int w = 0; w < WF; ++w) {
+            if (!m[w]) continue;  // uniform
             const uint64_t x = act ? v.masks[(size_t)k * WF + w] : 0ull;
-            uint64_t m = x;
-            while (m) {
-                const int b = 64 * w + __ffsll((unsigned long long)m) - 1;
-                m &= m - 1ull;
+            uint64_t y = x;
+            while (y) {
+                const int b = 64 * w + __ffsll((unsigned long long)y) - 1;
+                y &= y - 1ull;
                 atomicMin(&v.first[b], (uint32_t)k);
                 atomicAdd(&v.cnt[b], 1u);
                 atomicAdd(reinterpret_cast<unsigned long long *>(&v.H[b]), (unsigned long long)h);
@@ -559,7 +561,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
         int cnt = 0;
 #pragma unroll
         for (int w = 0; w < WF; ++w) {
-            x[w] = act ? v.masks[(size_t)k * WF + w] & m[w] : 0ull;
+            x[w] = act && m[w] ? v.masks[(size_t)k * WF + w] & m[w] : 0ull;  // words of R' only
             cnt += __popcll(x[w]);
         }
         const bool inp = act && j >= qn;
@@ -607,8 +609,12 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
         }
     }
     wait_mem();
-    if (NARROW) narrow_table_finish(c, v2, n2, r);
-    else build_tables_wide<W>(v2, n2);
+    if constexpr (NARROW) {
+        narrow_table_finish(c, v2, n2, r);
+    } else {
+        static_assert(WF == W, "wide children come from wide lists");
+        build_tables_wide<W>(v2, n2, m);
+    }
     C.off = off2;
     C.top = top2;
     C.n = n2;
@@ -768,7 +774,8 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
             if (j >= qn) {
                 int cnt = 0;
 #pragma unroll
-                for (int w = 0; w < WF; ++w) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);
+                for (int w = 0; w < WF; ++w)
+                    if (m[w]) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);  // words of R' only
                 atomicAdd(&c.hist[cnt], 1u);
             }
             if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);

@@ -78,6 +78,20 @@ def test_bad_options_rejected():
     g = gg.complete(2, 2)
     assert _bad(g, side=3) == -1
     assert _bad(g, wg_waves=9) == -1
+    assert _bad(g, steal_k=3) == -1
+    assert _bad(g, steal_k=-1) == -1
+
+
+def test_tuner_rejects_bad_input_before_device_work():
+    import paper_2401_05039_amd as m
+    with pytest.raises(m.MbeError) as e:
+        m.mbe_tune_batch([])
+    assert e.value.code == -1
+    good = gg.complete(2, 3)
+    bad = _mk(2, 3, [0, 3, 6], [0, 2, 1, 0, 1, 2], good.v_off, good.v_adj)
+    with pytest.raises(m.MbeError) as e:
+        m.mbe_tune_batch([good, bad])
+    assert e.value.code == -2
 
 
 def test_empty_graphs_need_no_device():

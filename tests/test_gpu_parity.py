@@ -131,10 +131,10 @@ def test_dense_small_deep_trees(mbe, orc, seed):
     _check(mbe, orc, g, f"dense{seed}")
 
 
-@pytest.mark.parametrize("waves,grid", [(1, 1), (2, 3), (4, 17), (8, 0)])
-def test_launch_shapes_agree(mbe, orc, waves, grid):
+@pytest.mark.parametrize("waves,grid,steal", [(1, 1, 0), (2, 3, 0), (4, 17, 0), (8, 0, 0), (8, 0, 1), (2, 5, 1)])
+def test_launch_shapes_agree(mbe, orc, waves, grid, steal):
     g = gg.random_small(120, 150, 0.08, 31)
-    _check(mbe, orc, g, f"shape{waves}x{grid}", wg_waves=waves, grid=grid)
+    _check(mbe, orc, g, f"shape{waves}x{grid}k{steal}", wg_waves=waves, grid=grid, steal_k=steal)
 
 
 def test_device_pointers(mbe, orc):
@@ -250,15 +250,26 @@ def test_batch_launch_shapes_agree(mbe):
         assert [(r["count"], r["hash"]) for r in res] == [(r["count"], r["hash"]) for r in base]
 
 
+def test_tuner_picks_a_setting_with_equal_results(mbe):
+    gs = _small_batch()
+    _say("tuner", len(gs))
+    base = mbe.mbe_count_batch(gs)
+    tuned, ms = mbe.mbe_tune_batch(gs)
+    assert tuned.wg_waves in (2, 4, 8) and tuned.steal_k in (1, 2) and ms > 0
+    res = mbe.mbe_count_batch(gs, tuned)
+    assert [(r["count"], r["hash"]) for r in res] == [(r["count"], r["hash"]) for r in base]
+
+
 # ----------------------------------------------------------------------------- serving form
 
-def test_server_results_equal_alone(mbe):
+@pytest.mark.parametrize("slots,small_edges", [(2, 0), (3, 3000), (2, -1)])
+def test_server_results_equal_alone(mbe, slots, small_edges):
     import threading
     gs = [gg.config4_graph(i) for i in range(0, 200, 5)]
     gs = [g for g in gs if g.n_edges < 20000] + [gg.config1(), gg.crown(9)]
-    _say("server", len(gs))
+    _say("server", len(gs), slots, small_edges)
     alone = [mbe.mbe_count(g) for g in gs]
-    with mbe.Server(slots=2) as sv:
+    with mbe.Server(slots=slots, small_edges=small_edges) as sv:
         tickets = [None] * len(gs)
 
         def feed(lo):
