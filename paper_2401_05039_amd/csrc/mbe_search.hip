@@ -51,6 +51,8 @@ namespace {
 constexpr uint64_t kHashK = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kShared = 0xFFFFFFFFu;  // frame offset meaning "the workgroup's top-level list"
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kQKeep = 64;       // most incomparable Q' masks a compressed child keeps
+constexpr int kWaveLds = 1536;   // LDS bytes per wave besides the histogram
 
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -259,6 +261,7 @@ struct Ctx {
     uint32_t *stu;                    // a maximal node's Q' and P' positions in list order
     uint32_t *tl_first, *tl_cnt;           // this wave's LDS tables for narrow children
     uint64_t *tl_H;
+    uint64_t *qk;                     // this wave's LDS list of kept Q' masks (kQKeep)
     uint32_t *hist;                   // this wave's LDS histogram
     int64_t scap;
     int32_t x_root, s0, c_is_v, Wroot;
@@ -344,7 +347,7 @@ __device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, in
 // Per-bit tables and rows of a wide frame whose entries are in place; its masks lie within
 // the words of R (m): rows of the other words are never read and are not written.  One wave.
 template <int WF>
-__device__ void build_tables_wide(const FrameView &v, int n, const uint64_t (&m)[WF]) {
+__device__ void build_tables_wide(const FrameView &v, int n, int nq, const uint64_t (&m)[WF]) {
     constexpr int bits = 64 * WF;
     const int ln = lane_id();
     for (int b = ln; b < bits; b += 64) {
@@ -356,7 +359,7 @@ __device__ void build_tables_wide(const FrameView &v, int n, const uint64_t (&m)
     for (int base = 0; base < n; base += 64) {
         const int k = base + ln;
         const bool act = k < n;
-        const uint64_t h = act ? v.hs[k] : 0ull;
+        const uint64_t h = act && k >= nq ? v.hs[k] : 0ull;  // Q entries carry no hash term
 #pragma unroll
         for (int w = 0; w < WF; ++w) {
             if (!m[w]) continue;  // uniform
@@ -504,6 +507,80 @@ __device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameVi
     return __ballot(act && r >= 2);
 }
 
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The compression of entry k's mask to the |R'| bits of R' (bit t = the t-th bit of R').
+template <int WF>
+__device__ __forceinline__ uint64_t compress_mask(const FrameView &v, const uint64_t (&m)[WF], int k) {
+    uint64_t out = 0;
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < WF; ++w) {
+        if (!m[w]) continue;  // uniform
+        uint64_t mm = m[w];
+        const uint64_t xx = v.masks[(size_t)k * WF + w];
+        while (mm) {  // the same trip count on every lane: m is uniform
+            const int p = __ffsll((unsigned long long)mm) - 1;
+            mm &= mm - 1ull;
+            out |= ((xx >> p) & 1ull) << t;
+            ++t;
+        }
+    }
+    return out;
+}
+
+// Q' of a compressed child, reduced to its inclusion-maximal masks.  A Q entry only ever
+// serves as a witness that some later R'' (a subset of R') is not maximal, and an entry
+// whose mask over R' lies inside another's witnesses nothing the other does not, so only
+// one entry per maximal mask needs to stay.  The Q' entries are stu[0, qn); the kept
+// compressed masks go to c.qk.  Returns their number, or -1 when more than kQKeep are
+// incomparable (then nothing is dropped).
+template <int WF>
+__device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn) {
+    const int ln = lane_id();
+    const uint64_t below = lanes_below();
+    int nk = 0;
+    for (int base = 0; base < qn; base += 64) {
+        const int j = base + ln;
+        const bool act = j < qn;
+        const uint64_t x = act ? compress_mask<WF>(v, m, (int)c.stu[j]) : 0ull;
+        bool cand = act;
+        for (int t = 0; t < nk; ++t) {
+            const uint64_t y = c.qk[t];  // same address on every lane
+            if ((x & ~y) == 0ull) cand = false;
+        }
+        // among this chunk: drop x when another candidate holds more, or the same in a lower lane
+        bool keep = cand;
+        for (uint64_t q = __ballot(cand); q; q &= q - 1ull) {
+            const int l = __ffsll((unsigned long long)q) - 1;
+            const uint64_t y = readlane64(x, l);
+            if (l != ln && (x & ~y) == 0ull && (x != y || l < ln)) keep = false;
+        }
+        const uint64_t sb = __ballot(keep);
+        if (!sb) continue;
+        // kept masks inside a new survivor go; the survivors join
+        uint64_t y = ln < nk ? c.qk[ln] : 0ull;
+        bool stay = ln < nk;
+        for (uint64_t q = sb; q; q &= q - 1ull) {
+            const uint64_t xs = readlane64(x, __ffsll((unsigned long long)q) - 1);
+            if ((y & ~xs) == 0ull) stay = false;
+        }
+        const uint64_t stb = __ballot(stay);
+        const int ns = __popcll(stb), nn = ns + __popcll(sb);
+        if (nn > kQKeep) return -1;
+        __builtin_amdgcn_wave_barrier();
+        if (stay) c.qk[__popcll(stb & below)] = y;
+        if (keep) c.qk[ns + __popcll(sb & below)] = x;
+        __builtin_amdgcn_wave_barrier();
+        nk = nn;
+    }
+    return nk;
+}
+
 // Write the child frame of the maximal node at position i at the top of the wave's stack.
 // Its entries are the positions stu[0, nu) of the node's list, in list order: the first qn
 // (before i) form Q' and keep their order, the other pn (after i, 0 < |mask n R'| < |R'|)
@@ -516,7 +593,20 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
                             int r, int qn, int pn, FrameState &C) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
-    const int n2 = qn + pn;
+    // Q': with diagnostics off, a compressed child keeps only its inclusion-maximal masks
+    // (the tallies of diagnostics mode count the full Q' of the method)
+    int nq2 = qn;
+    bool pruned = false;
+    if constexpr (NARROW && !DIAG) {
+        if (qn > 1) {
+            const int nk = prune_q<WF>(c, v, m, qn);
+            if (nk >= 0) {
+                nq2 = nk;
+                pruned = true;
+            }
+        }
+    }
+    const int n2 = nq2 + pn;
     constexpr int wf2 = NARROW ? 1 : W;
     const uint32_t off2 = F.top;
     const int rbits2 = NARROW ? r : 64 * W;
@@ -541,9 +631,16 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
             t0 += __popcll(bb);
         }
         narrow_table_clear(c);
+        if (pruned) {
+            for (int t = ln; t < nq2; t += 64) {
+                const uint64_t x = c.qk[t];
+                masks2[t] = x;
+                narrow_table_add(c, (uint32_t)t, x, 0ull);
+            }
+        }
     }
     // first slot of each count among the P' entries
-    int carry = qn;
+    int carry = nq2;
     for (int base = 0; base < r; base += 64) {
         const int b = base + ln;
         const int h = b < r ? (int)c.hist[b] : 0;
@@ -553,7 +650,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     }
     __builtin_amdgcn_wave_barrier();
     const int nbits = r <= 1 ? 1 : 32 - __clz(r - 1);
-    for (int base = 0; base < nu; base += 64) {
+    for (int base = pruned ? qn : 0; base < nu; base += 64) {
         const int j = base + ln;
         const bool act = j < nu;
         const int k = act ? (int)c.stu[j] : 0;
@@ -585,8 +682,10 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
         }
         if (act) {
             if (DIAG) ids2[slot] = v.ids[k];
-            const uint64_t h = v.hs[k];
-            hs2[slot] = h;
+            // Q entries' hash terms are never read (a node whose bit some Q entry holds is
+            // not maximal), so they are not copied
+            const uint64_t h = inp ? v.hs[k] : 0ull;
+            if (inp) hs2[slot] = h;
             if (NARROW) {
                 uint64_t out = 0;
                 int t = 0;
@@ -613,15 +712,15 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
         narrow_table_finish(c, v2, n2, r);
     } else {
         static_assert(WF == W, "wide children come from wide lists");
-        build_tables_wide<W>(v2, n2, m);
+        build_tables_wide<W>(v2, n2, nq2, m);
     }
     C.off = off2;
     C.top = top2;
     C.n = n2;
-    C.nq = qn;
+    C.nq = nq2;
     C.wf = wf2;
     C.narrow = NARROW ? 1 : 0;
-    C.chunk = qn - 64;
+    C.chunk = nq2 - 64;
     C.rbits = rbits2;
     C.heavy = 0ull;
     return true;
@@ -995,11 +1094,12 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     c.stu = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_u);
     c.hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * BITS;
     {
-        // narrow-child table scratch: first[64] cnt[64] cur[64] (u32) then H[64] (u64) per wave
-        unsigned char *tb = lds_raw + sizeof(WGShared) + (size_t)nw * BITS * 4 + (size_t)wid * 1280;
+        // per wave: narrow-child tables first[64] cnt[64] (u32), H[64] (u64); kept Q' masks[64]
+        unsigned char *tb = lds_raw + sizeof(WGShared) + (size_t)nw * BITS * 4 + (size_t)wid * kWaveLds;
         c.tl_first = reinterpret_cast<uint32_t *>(tb);
         c.tl_cnt = c.tl_first + 64;
-        c.tl_H = reinterpret_cast<uint64_t *>(tb + 768);
+        c.tl_H = reinterpret_cast<uint64_t *>(tb + 512);
+        c.qk = reinterpret_cast<uint64_t *>(tb + 1024);
     }
     c.scap = a.dims.scap;
     c.c_is_v = 0;
@@ -1510,7 +1610,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, i
     }
 }
 
-size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + (size_t)waves * (64 * W * sizeof(uint32_t) + 1280); }
+size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + (size_t)waves * (64 * W * sizeof(uint32_t) + kWaveLds); }
 
 template <int W>
 hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, int64_t hi, unsigned int *counter,

@@ -31,6 +31,12 @@ def _check(mbe, orc, g, name, diag=True, side=0, **kw):
     keys = DIAG_KEYS if diag else ("count", "hash", "out_ints", "side")
     for k in keys:
         assert got[k] == want[k], (name, k, got[k], want[k])
+    if diag:
+        # the fast path (no diagnostics) keeps only inclusion-maximal Q masks in child lists;
+        # its answers must be the same
+        fast = mbe.mbe_count(g, mbe.Options(side=side, **kw))
+        for k in ("count", "hash", "out_ints", "side"):
+            assert fast[k] == want[k], (name, "fast", k, fast[k], want[k])
     return got
 
 
@@ -59,6 +65,9 @@ def test_workload1_full_list(mbe, orc):
     got = mbe.decode_records(flat)
     assert got == want["list"]
     assert len(flat) == want["out_ints"]
+    res, flat = mbe.mbe_enumerate(g)  # fast path
+    assert (res["count"], res["hash"]) == (want["count"], want["hash"])
+    assert mbe.decode_records(flat) == want["list"]
 
 
 def test_workload1_golden(mbe):
@@ -209,6 +218,9 @@ def test_workload3_samples(mbe):
         r = mbe.mbe_count(g, mbe.Options(diagnostics=True, root_lo=s["rank_lo"], root_hi=s["rank_hi"]))
         for k in ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "max_depth"):
             assert r[k] == s[k], (s["rank_lo"], k)
+        fast = mbe.mbe_count(g, mbe.Options(root_lo=s["rank_lo"], root_hi=s["rank_hi"]))
+        for k in ("count", "hash", "out_ints"):
+            assert fast[k] == s[k], (s["rank_lo"], "fast", k)
 
 
 # ----------------------------------------------------------------------------- batched form
@@ -225,10 +237,13 @@ def test_batch_equals_oracle_per_graph(mbe, orc):
     gs = _small_batch()
     _say("batch", len(gs))
     res = mbe.mbe_count_batch(gs, mbe.Options(diagnostics=True))
-    for i, (g, r) in enumerate(zip(gs, res)):
+    fast = mbe.mbe_count_batch(gs)
+    for i, (g, r, f) in enumerate(zip(gs, res, fast)):
         want = orc.mbea(g)
         for k in ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "max_depth", "side"):
             assert r[k] == want[k], (i, g.name, k, r[k], want[k])
+        for k in ("count", "hash", "out_ints"):
+            assert f[k] == want[k], (i, g.name, "fast", k, f[k], want[k])
 
 
 def test_batch_equals_single_calls(mbe):
