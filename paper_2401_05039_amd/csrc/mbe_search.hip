@@ -1044,8 +1044,10 @@ __device__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, in
     }
 }
 
+// The single-word class (the most top-level candidates, small lists) keeps four waves per
+// SIMD resident: its register budget is capped at 128.
 template <int W, bool DIAG, bool ENUM>
-__global__ __launch_bounds__(512) void search_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 : 2))) void search_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
     extern __shared__ unsigned char lds_raw[];
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
     const int tid = threadIdx.x, nt = blockDim.x, wid = uni(tid >> 6), nw = nt >> 6, ln = lane_id();
