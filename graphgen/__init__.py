@@ -342,6 +342,22 @@ def config5_requests(n: int, rate: float, seed: int = _BASE_SEED + 5,
 
 # ----------------------------------------------------------------------------- closed-form families
 
+def hub_lists(n: int) -> BiGraph:
+    """A hub u0 adjacent to n candidates v_0..v_{n-1} of degree 1 and to x = v_n, which is
+    also adjacent to u1; z = v_{n+1} is adjacent to u1 and u2.  |U| = n + 3 > |V| = n + 2, so
+    V holds the candidates, and the top-level list of x has n earlier-ranked entries.  Its
+    maximal bicliques are ({u0}, {v_0..v_n}), ({u1}, {x, z}), ({u0, u1}, {x}) and
+    ({u1, u2}, {z})."""
+    us = [0] * (n + 1) + [1, 1, 2]
+    vs = list(range(n + 1)) + [n, n + 1, n + 1]
+    return from_edges(n + 3, n + 2, us, vs, name=f"hub{n}")
+
+
+def hub_lists_bicliques(n: int) -> List[Tuple[Tuple[int, ...], Tuple[int, ...]]]:
+    """The four maximal bicliques of hub_lists(n), in canonical order."""
+    return sorted([((0,), tuple(range(n + 1))), ((1,), (n, n + 1)), ((0, 1), (n,)), ((1, 2), (n + 1,))])
+
+
 def complete(m: int, n: int) -> BiGraph:
     us = np.repeat(np.arange(m), n)
     vs = np.tile(np.arange(n), m)

@@ -959,6 +959,7 @@ struct WGShared {
     int slot;   // arena slot held by this workgroup
     int scan[16];
     unsigned long long red[16];  // per-graph tally reduction
+    unsigned long long cov[16];  // bits of N(x) held by a multi-bit top-level Q mask
 };
 
 // Add the workgroup's tallies to a graph's accumulators and clear them.  All threads call.
@@ -1014,7 +1015,8 @@ __device__ int claim_chunk(unsigned long long *word, unsigned int epoch, int lim
 }
 
 // Block-wide exclusive prefix of popcounts over nwords bitmap words into bpre; total in
-// sh->s0.  All threads call it.
+// sh->s0.  All threads call it; on return every thread sees all of bpre (a thread writes a
+// run of ceil(nwords / threads) entries, so callers read entries other threads wrote).
 __device__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, int nwords, WGShared *sh) {
     const int tid = threadIdx.x, nt = blockDim.x, wid = tid >> 6, nw = nt >> 6;
     const int per = (nwords + nt - 1) / nt;
@@ -1042,6 +1044,8 @@ __device__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, in
             run += __popcll(bitmap[b0 + q]);
         }
     }
+    wait_mem();
+    __syncthreads();
 }
 
 // The single-word class (the most top-level candidates, small lists) keeps four waves per
@@ -1199,14 +1203,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             acc.ph[PH_WAIT] += now - t_mark;
             t_mark = now;
         }
-        const int mode = sh->mode;
+        const int mode = uni(sh->mode);
         if (mode == 0) break;
         const bool thief = mode == 2;
         int g = 0;
         int64_t k;
         if (thief) {
-            g = sh->sg;
-            k = sh->sk;
+            g = uni(sh->sg);
+            k = uni(sh->sk);
         } else if (a.tasks) {
             const unsigned long long tk = a.tasks[lo + (int64_t)sh->task];
             g = (int)(tk >> 32);
@@ -1284,7 +1288,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         block_popcount_prefix(bitmap, bpre, nwords, sh);
         wait_mem();
         __syncthreads();
-        const int s0 = sh->s0;
+        const int s0 = uni(sh->s0);
         if (s0 > ucap) {
             // the universe does not fit: clear the bitmap, note the size, skip (rerun later)
             for (int wd = tid; wd < nwords; wd += nt) bitmap[wd] = 0ull;
@@ -1373,8 +1377,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         }
         wait_mem();
         __syncthreads();
-        const bool root_nonmax = sh->nonmax != 0;
-        const int P1 = sh->pcount;
+        const bool root_nonmax = uni(sh->nonmax) != 0;
+        const int P1 = uni(sh->pcount);
         if (tid == 0 && !thief) {  // a stolen task's top-level node belongs to its owner
             const uint64_t dx = (uint64_t)d;
             if (DIAG) {
@@ -1412,13 +1416,73 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             }
             continue;
         }
-        const int n1 = nq0 + P1;
+        // -- Q1 of the list: the universe entries ranked before x (all of them meet N(x)).
+        //    With diagnostics off, a single-bit mask is dropped when a Q1 mask of two or more
+        //    bits holds its bit, and of the other single-bit masks only the first per bit is
+        //    kept: a Q entry only witnesses that some R (a subset of N(x)) is not maximal, and
+        //    the dropped ones witness nothing the kept ones do not.  The count stays nq0 in
+        //    the tallies of diagnostics mode, which keep the method's full Q1.
+        uint32_t *ids1 = s1;
+        if (!DIAG && nq0 > 1) {
+            uint32_t *first1 = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared));  // BITS words
+            for (int b = tid; b < BITS; b += nt) first1[b] = kNone;
+            if (tid < W) sh->cov[tid] = 0ull;
+            __syncthreads();
+            for (int li = tid; li < nq0; li += nt)
+                if (cnt1[li] >= 2u) {
+#pragma unroll 1
+                    for (int w = 0; w < W; ++w) {
+                        const uint64_t y = M[(size_t)li * W + w];
+                        if (y) atomicOr(&sh->cov[w], (unsigned long long)y);
+                    }
+                }
+            __syncthreads();
+            auto single_bit = [&](int li) {
+                int b = 0;
+#pragma unroll 1
+                for (int w = 0; w < W; ++w) {
+                    const uint64_t y = M[(size_t)li * W + w];
+                    if (y) b = 64 * w + __ffsll((unsigned long long)y) - 1;
+                }
+                return b;
+            };
+            for (int li = tid; li < nq0; li += nt)
+                if (cnt1[li] == 1u) {
+                    const int b = single_bit(li);
+                    if (!((sh->cov[b >> 6] >> (b & 63)) & 1ull)) atomicMin(&first1[b], (uint32_t)li);
+                }
+            __syncthreads();
+            const int nwq = (nq0 + 63) >> 6;
+            for (int q = wid; q < nwq; q += nw) {
+                const int li = 64 * q + ln;
+                bool keep = false;
+                if (li < nq0) keep = cnt1[li] >= 2u || first1[single_bit(li)] == (uint32_t)li;
+                const uint64_t kb = __ballot(keep);
+                if (ln == 0) hb[q] = kb;
+            }
+            wait_mem();
+            __syncthreads();
+            block_popcount_prefix(hb, hpre, nwq, sh);
+            for (int q = tid; q < nwq; q += nt) {
+                uint64_t bits = hb[q];
+                uint32_t at = hpre[q];
+                while (bits) {
+                    const int bb = __ffsll((unsigned long long)bits) - 1;
+                    bits &= bits - 1ull;
+                    ids1[at++] = (uint32_t)(64 * q + bb);
+                }
+            }
+        } else {
+            for (int li = tid; li < nq0; li += nt) ids1[li] = (uint32_t)li;
+            if (tid == 0) sh->s0 = nq0;
+        }
+        __syncthreads();
+        const int nqk = uni(sh->s0);  // Q1 entries kept in the list
+        const int n1 = nqk + P1;
 
         // -- the top-level child list as a frame: ids Q1 (earlier ranks) ++ P1 sorted by
         //    count, masks over the positions of N(x), per-bit tables
         FrameView v1 = frame_view(s1, n1, W, d);
-        uint32_t *ids1 = s1;
-        for (int li = tid; li < nq0; li += nt) ids1[li] = (uint32_t)li;
         if (wid == 0) {
             int pn = 0;
             for (int base = nq0; base < s0; base += 64) {
@@ -1435,7 +1499,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                 pn += __popcll(pb);
             }
             wait_mem();
-            wave_sort_by_key(t1v, t1c, pn, d, c.hist, [&](uint32_t slot, uint32_t li) { ids1[nq0 + slot] = li; });
+            wave_sort_by_key(t1v, t1c, pn, d, c.hist, [&](uint32_t slot, uint32_t li) { ids1[nqk + slot] = li; });
         }
         for (int b = tid; b < BITS; b += nt) {
             v1.first[b] = kNone;
@@ -1484,7 +1548,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         top.off = kShared;
         top.top = 0;
         top.n = n1;
-        top.nq = nq0;
+        top.nq = nqk;
         top.level = 2;
         top.nL = 1 + sh->nexp;
         top.wf = W;
@@ -1493,11 +1557,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         top.rbits = d;
         top.heavy = 0ull;
         top.sL = hl(c, x) + sh->exps;
-        top.fw = sh->fw1;
+        top.fw = uni((uint64_t)sh->fw1);
         const int nch = (P1 + 63) >> 6;
         for (int q = wid; q < nch; q += nw) {
             const uint64_t tl = DIAG ? clock64() : 0ull;
-            const uint64_t hm = light_chunk<W, DIAG, ENUM>(c, top, v1, nq0 + 64 * q, acc, !thief);
+            const uint64_t hm = light_chunk<W, DIAG, ENUM>(c, top, v1, nqk + 64 * q, acc, !thief);
             if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
             if (ln == 0) hb[q] = hm;
         }
@@ -1510,12 +1574,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             while (bits) {
                 const int bb = __ffsll((unsigned long long)bits) - 1;
                 bits &= bits - 1ull;
-                hpos[at++] = (uint32_t)(nq0 + 64 * q + bb);
+                hpos[at++] = (uint32_t)(nqk + 64 * q + bb);
             }
         }
         wait_mem();
         __syncthreads();
-        const int H = sh->s0;
+        const int H = uni(sh->s0);
 
         // -- share the items: with more than one per wave, claims go through the global steal
         //    slot so that idle workgroups can take some (they rebuild the same list)
@@ -1535,8 +1599,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             }
         }
         __syncthreads();
-        const bool gclaim = sh->gclaim != 0;
-        const unsigned int epoch = sh->epoch;
+        const bool gclaim = uni(sh->gclaim) != 0;
+        const unsigned int epoch = uni(sh->epoch);
         if (DIAG) {
             const uint64_t now = clock64();
             acc.ph[PH_ROOT] += now - t_mark;

@@ -140,6 +140,22 @@ def test_dense_small_deep_trees(mbe, orc, seed):
     _check(mbe, orc, g, f"dense{seed}")
 
 
+def test_long_top_level_lists(mbe, orc):
+    """x's top-level list has 40000 earlier-ranked entries, so its bitmaps span more than one
+    word per thread of the workgroup (the prefix over them is split across threads)."""
+    n = 40000
+    g = gg.hub_lists(n)
+    _say("hub lists", n)
+    want = gg.hub_lists_bicliques(n)
+    h = 0
+    for a, b in want:
+        h = (h + orc.hash_pair(a, b)) % (1 << 64)
+    for diag in (False, True):
+        r = mbe.mbe_count(g, mbe.Options(diagnostics=diag))
+        assert (r["count"], r["hash"]) == (4, h), diag
+        assert r["out_ints"] == sum(2 + len(a) + len(b) for a, b in want)
+
+
 @pytest.mark.parametrize("waves,grid,steal", [(1, 1, 0), (2, 3, 0), (4, 17, 0), (8, 0, 0), (8, 0, 1), (2, 5, 1)])
 def test_launch_shapes_agree(mbe, orc, waves, grid, steal):
     g = gg.random_small(120, 150, 0.08, 31)

@@ -186,3 +186,13 @@ def test_degree_zero_vertices_are_skipped(orc):
     h = gg.from_edges(5, 6, us, vs)
     assert orc.mbea(h, want_list=True)["list"] == orc.mbea(g, want_list=True)["list"]
     assert orc.brute(h)["list"] == orc.mbea(h, want_list=True)["list"]
+
+
+def test_hub_lists_closed_form(orc):
+    """hub_lists(n): the closure (definition) and the MBEA oracle give the four bicliques."""
+    for n in (1, 3, 6, 20):
+        g = gg.hub_lists(n)
+        want = gg.hub_lists_bicliques(n)
+        assert orc.closure(g)["list"] == want
+        r = orc.mbea(g, want_list=True)
+        assert r["list"] == want and r["count"] == 4
