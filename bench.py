@@ -24,8 +24,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # HBM bytes moved by the search launches of one power-law step, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters scaled by a 1 GiB reference copy (profiles/search_kernel_powerlaw_100k_50k.md),
 # taken on the kernel source with this sha256; reported only while the source is unchanged.
-MEASURED_TRAFFIC = {"source_sha256": "e31343f2fdd22a24864a37c1c0583f1143cf0b31830522966560079f6279dcb1",
-                    "bytes_per_step": 3.043e11}
+MEASURED_TRAFFIC = {"source_sha256": "b8beba51a834f2144edd771c294acce81bc35f1c77ad73cddce3db62306bf2fc",
+                    "bytes_per_step": 6.098e10}
 
 
 def log(*a):
