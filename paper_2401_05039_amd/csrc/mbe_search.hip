@@ -51,8 +51,8 @@ namespace {
 constexpr uint64_t kHashK = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kShared = 0xFFFFFFFFu;  // frame offset meaning "the workgroup's top-level list"
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr int kQKeep = 64;       // most incomparable Q' masks a compressed child keeps
-constexpr int kWaveLds = 1536;   // LDS bytes per wave besides the histogram
+constexpr int kQKeep = 256;      // most incomparable Q' masks a compressed child keeps
+constexpr int kWaveLds = 1024 + 8 * kQKeep;  // LDS bytes per wave besides the histogram
 
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -538,7 +538,8 @@ __device__ __forceinline__ uint64_t compress_mask(const FrameView &v, const uint
 // whose mask over R' lies inside another's witnesses nothing the other does not, so only
 // one entry per maximal mask needs to stay.  The Q' entries are stu[0, qn); the kept
 // compressed masks go to c.qk.  Returns their number, or -1 when more than kQKeep are
-// incomparable (then nothing is dropped).
+// incomparable (then nothing is dropped).  Cost per chunk of 64 entries: one pass over the
+// kept masks, and one over the chunk's candidates.
 template <int WF>
 __device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn) {
     const int ln = lane_id();
@@ -562,18 +563,25 @@ __device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF]
         }
         const uint64_t sb = __ballot(keep);
         if (!sb) continue;
-        // kept masks inside a new survivor go; the survivors join
-        uint64_t y = ln < nk ? c.qk[ln] : 0ull;
-        bool stay = ln < nk;
-        for (uint64_t q = sb; q; q &= q - 1ull) {
-            const uint64_t xs = readlane64(x, __ffsll((unsigned long long)q) - 1);
-            if ((y & ~xs) == 0ull) stay = false;
+        // kept masks inside a new survivor go (compacted in place, 64 at a time: an entry
+        // only moves down, past entries already read); the survivors join
+        int ns = 0;
+        for (int blk = 0; blk < nk; blk += 64) {
+            const int t = blk + ln;
+            const uint64_t y = t < nk ? c.qk[t] : 0ull;
+            bool stay = t < nk;
+            for (uint64_t q = sb; q; q &= q - 1ull) {
+                const uint64_t xs = readlane64(x, __ffsll((unsigned long long)q) - 1);
+                if ((y & ~xs) == 0ull) stay = false;
+            }
+            const uint64_t stb = __ballot(stay);
+            __builtin_amdgcn_wave_barrier();
+            if (stay) c.qk[ns + __popcll(stb & below)] = y;
+            __builtin_amdgcn_wave_barrier();
+            ns += __popcll(stb);
         }
-        const uint64_t stb = __ballot(stay);
-        const int ns = __popcll(stb), nn = ns + __popcll(sb);
+        const int nn = ns + __popcll(sb);
         if (nn > kQKeep) return -1;
-        __builtin_amdgcn_wave_barrier();
-        if (stay) c.qk[__popcll(stb & below)] = y;
         if (keep) c.qk[ns + __popcll(sb & below)] = x;
         __builtin_amdgcn_wave_barrier();
         nk = nn;
@@ -1100,7 +1108,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
     c.stu = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_u);
     c.hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * BITS;
     {
-        // per wave: narrow-child tables first[64] cnt[64] (u32), H[64] (u64); kept Q' masks[64]
+        // per wave: narrow-child tables first[64] cnt[64] (u32), H[64] (u64); kept Q' masks
         unsigned char *tb = lds_raw + sizeof(WGShared) + (size_t)nw * BITS * 4 + (size_t)wid * kWaveLds;
         c.tl_first = reinterpret_cast<uint32_t *>(tb);
         c.tl_cnt = c.tl_first + 64;
