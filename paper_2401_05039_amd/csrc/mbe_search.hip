@@ -54,6 +54,12 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kQKeep = 256;      // most incomparable Q' masks a compressed child keeps
 constexpr int kWaveLds = 1024 + 8 * kQKeep;  // LDS bytes per wave besides the histogram
 
+// LDS after the workgroup header: the waves' histograms (4 bytes per bit each), which the
+// top-level list build reuses for its tables (16 bytes per bit), hence at least that much.
+__host__ __device__ constexpr size_t hist_region_bytes(int bits, int waves) {
+    return (size_t)bits * (waves >= 4 ? 4 * (size_t)waves : 16);
+}
+
 // SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z ^= z >> 30;
@@ -133,6 +139,34 @@ __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
 __device__ __forceinline__ void see_atomics() {
     __builtin_amdgcn_s_waitcnt(0);
     asm volatile("buffer_inv sc0" ::: "memory");
+}
+
+// Workgroup memory (LDS) pointers carry their address space, so that accesses and atomics
+// through them are LDS instructions even where the compiler cannot trace them to the shared
+// array (through a generic pointer they would be flat instructions).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+template <typename T>
+__device__ __forceinline__ T *lds_at(unsigned char *base, size_t off) {
+    return (T *)(base + off);
+}
+__device__ __forceinline__ uint32_t lds_add32(lds_u32 *p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_min32(lds_u32 *p, uint32_t v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add64(lds_u64 *p, uint64_t v) {
+    __hip_atomic_fetch_add(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(void *p, uint64_t v) {
+    __hip_atomic_fetch_add((lds_u64 *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_max(void *p, uint64_t v) {
+    __hip_atomic_fetch_max((lds_u64 *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_or(void *p, uint64_t v) {
+    __hip_atomic_fetch_or((lds_u64 *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // ------------------------------------------------------------------------------ frames
@@ -259,10 +293,10 @@ struct Ctx {
     uint32_t *s1;                     // the workgroup's top-level list frame
     uint32_t *stk;                    // this wave's stack
     uint32_t *stu;                    // a maximal node's Q' and P' positions in list order
-    uint32_t *tl_first, *tl_cnt;           // this wave's LDS tables for narrow children
-    uint64_t *tl_H;
-    uint64_t *qk;                     // this wave's LDS list of kept Q' masks (kQKeep)
-    uint32_t *hist;                   // this wave's LDS histogram
+    lds_u32 *tl_first, *tl_cnt;       // this wave's LDS tables for narrow children
+    lds_u64 *tl_H;
+    lds_u64 *qk;                      // this wave's LDS list of kept Q' masks (kQKeep)
+    lds_u32 *hist;                    // this wave's LDS histogram
     int64_t scap;
     int32_t x_root, s0, c_is_v, Wroot;
     int32_t cbase, obase;  // first packed id of the current graph's candidate / other side
@@ -301,7 +335,7 @@ __device__ __forceinline__ uint64_t deg_of(const Ctx &c, uint32_t li) {
 // Stable counting sort of n staged (parent position, key) pairs by key (keys in [1, nbins));
 // sorted slot s receives parent position p through put(s, p).  One wave.
 template <typename Put>
-__device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, int n, int nbins, uint32_t *hist,
+__device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, int n, int nbins, lds_u32 *hist,
                                  Put put) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
@@ -309,7 +343,7 @@ __device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, in
     __builtin_amdgcn_wave_barrier();
     for (int base = 0; base < n; base += 64) {
         const int j = base + ln;
-        if (j < n) atomicAdd(&hist[key_of[j]], 1u);
+        if (j < n) lds_add32(&hist[key_of[j]], 1u);
     }
     __builtin_amdgcn_wave_barrier();
     int carry = 0;
@@ -392,9 +426,9 @@ __device__ __forceinline__ void narrow_table_add(const Ctx &c, uint32_t slot, ui
     while (m) {
         const int b = __ffsll((unsigned long long)m) - 1;
         m &= m - 1ull;
-        atomicMin(&c.tl_first[b], slot);
-        atomicAdd(&c.tl_cnt[b], 1u);
-        atomicAdd(reinterpret_cast<unsigned long long *>(&c.tl_H[b]), (unsigned long long)h);
+        lds_min32(&c.tl_first[b], slot);
+        lds_add32(&c.tl_cnt[b], 1u);
+        lds_add64(&c.tl_H[b], h);
     }
 }
 __device__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n, int r) {
@@ -883,7 +917,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
 #pragma unroll
                 for (int w = 0; w < WF; ++w)
                     if (m[w]) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);  // words of R' only
-                atomicAdd(&c.hist[cnt], 1u);
+                lds_add32(&c.hist[cnt], 1u);
             }
             if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
         }
@@ -984,11 +1018,11 @@ __device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) 
     v[6] = DIAG ? (uint64_t)wave_max_u32(acc.max_depth) : 0ull;
     if (ln == 0) {
         for (int q = 0; q < 6; ++q)
-            if (v[q]) atomicAdd(&sh->red[q], (unsigned long long)v[q]);
-        if (v[6]) atomicMax(&sh->red[6], (unsigned long long)v[6]);
+            if (v[q]) lds_add(&sh->red[q], v[q]);
+        if (v[6]) lds_max(&sh->red[6], v[6]);
         if (DIAG)
             for (int q = 0; q < PH_COUNT; ++q)
-                if (acc.ph[q]) atomicAdd(&sh->red[8 + q], (unsigned long long)acc.ph[q]);
+                if (acc.ph[q]) lds_add(&sh->red[8 + q], acc.ph[q]);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1106,14 +1140,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
     c.s1 = s1;
     c.stk = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_stack);
     c.stu = reinterpret_cast<uint32_t *>(wv + a.lay.off_w_u);
-    c.hist = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared)) + (size_t)wid * BITS;
+    c.hist = lds_at<lds_u32>(lds_raw, sizeof(WGShared) + (size_t)wid * BITS * 4);
     {
         // per wave: narrow-child tables first[64] cnt[64] (u32), H[64] (u64); kept Q' masks
-        unsigned char *tb = lds_raw + sizeof(WGShared) + (size_t)nw * BITS * 4 + (size_t)wid * kWaveLds;
-        c.tl_first = reinterpret_cast<uint32_t *>(tb);
+        const size_t tb = sizeof(WGShared) + hist_region_bytes(BITS, nw) + (size_t)wid * kWaveLds;
+        c.tl_first = lds_at<lds_u32>(lds_raw, tb);
         c.tl_cnt = c.tl_first + 64;
-        c.tl_H = reinterpret_cast<uint64_t *>(tb + 512);
-        c.qk = reinterpret_cast<uint64_t *>(tb + 1024);
+        c.tl_H = lds_at<lds_u64>(lds_raw, tb + 512);
+        c.qk = lds_at<lds_u64>(lds_raw, tb + 1024);
     }
     c.scap = a.dims.scap;
     c.c_is_v = 0;
@@ -1288,8 +1322,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         hv_local = wave_sum_u64(hv_local);
         rs_local = wave_sum_u64(rs_local);
         if (ln == 0) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(&sh->hvsum), (unsigned long long)hv_local);
-            atomicAdd(reinterpret_cast<unsigned long long *>(&sh->rs1), (unsigned long long)rs_local);
+            lds_add(&sh->hvsum, hv_local);
+            lds_add(&sh->rs1, rs_local);
         }
 
         // -- universe numbering: prefix of bitmap popcounts (rank order)
@@ -1379,8 +1413,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             if (ln == 0) {
                 atomicAdd(&sh->pcount, pc);
                 atomicAdd(&sh->nexp, nexp);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&sh->exps), (unsigned long long)ex);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&sh->fw1), (unsigned long long)fw);
+                lds_add(&sh->exps, ex);
+                lds_add(&sh->fw1, fw);
             }
         }
         wait_mem();
@@ -1432,7 +1466,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         //    the tallies of diagnostics mode, which keep the method's full Q1.
         uint32_t *ids1 = s1;
         if (!DIAG && nq0 > 1) {
-            uint32_t *first1 = reinterpret_cast<uint32_t *>(lds_raw + sizeof(WGShared));  // BITS words
+            lds_u32 *first1 = lds_at<lds_u32>(lds_raw, sizeof(WGShared));  // BITS words
             for (int b = tid; b < BITS; b += nt) first1[b] = kNone;
             if (tid < W) sh->cov[tid] = 0ull;
             __syncthreads();
@@ -1441,7 +1475,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
 #pragma unroll 1
                     for (int w = 0; w < W; ++w) {
                         const uint64_t y = M[(size_t)li * W + w];
-                        if (y) atomicOr(&sh->cov[w], (unsigned long long)y);
+                        if (y) lds_or(&sh->cov[w], y);
                     }
                 }
             __syncthreads();
@@ -1457,7 +1491,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             for (int li = tid; li < nq0; li += nt)
                 if (cnt1[li] == 1u) {
                     const int b = single_bit(li);
-                    if (!((sh->cov[b >> 6] >> (b & 63)) & 1ull)) atomicMin(&first1[b], (uint32_t)li);
+                    if (!((sh->cov[b >> 6] >> (b & 63)) & 1ull)) lds_min32(&first1[b], (uint32_t)li);
                 }
             __syncthreads();
             const int nwq = (nq0 + 63) >> 6;
@@ -1509,10 +1543,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             wait_mem();
             wave_sort_by_key(t1v, t1c, pn, d, c.hist, [&](uint32_t slot, uint32_t li) { ids1[nqk + slot] = li; });
         }
+        // per-bit tables accumulated in LDS (the histograms' space, idle here, 16 bytes per
+        // bit), then written out
+        lds_u64 *lH = lds_at<lds_u64>(lds_raw, sizeof(WGShared));
+        lds_u32 *lfirst = lds_at<lds_u32>(lds_raw, sizeof(WGShared) + (size_t)BITS * 8);
+        lds_u32 *lcnt = lfirst + BITS;
+        __syncthreads();  // wave 0's sort is done with its histogram
         for (int b = tid; b < BITS; b += nt) {
-            v1.first[b] = kNone;
-            v1.cnt[b] = 0u;
-            v1.H[b] = 0ull;
+            lfirst[b] = kNone;
+            lcnt[b] = 0u;
+            lH[b] = 0ull;
         }
         wait_mem();
         __syncthreads();
@@ -1522,21 +1562,26 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             const uint32_t li = ids1[j];
             const uint64_t h = hl(c, gid[li]);
             hs1[j] = h;
-#pragma unroll
+            const uint64_t ht = j < nqk ? 0ull : h;  // Q entries carry no hash term
+#pragma unroll 1
             for (int w = 0; w < W; ++w) {
                 uint64_t mm = M[(size_t)li * W + w];
                 masks1[(size_t)j * W + w] = mm;
                 while (mm) {
                     const int b = 64 * w + __ffsll((unsigned long long)mm) - 1;
                     mm &= mm - 1ull;
-                    atomicMin(&v1.first[b], (uint32_t)j);
-                    atomicAdd(&v1.cnt[b], 1u);
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&v1.H[b]), (unsigned long long)h);
+                    lds_min32(&lfirst[b], (uint32_t)j);
+                    lds_add32(&lcnt[b], 1u);
+                    lds_add64(&lH[b], ht);
                 }
             }
         }
         __syncthreads();
-        see_atomics();  // the top-level tables were built with atomics
+        for (int b = tid; b < BITS; b += nt) {
+            v1.first[b] = lfirst[b];
+            v1.cnt[b] = lcnt[b];
+            v1.H[b] = lH[b];
+        }
         // position rows of the top-level list, one (64-entry chunk, mask word) block per wave
         const int qd = (d + 63) >> 6;  // mask words holding bits of N(x)
         for (int job = wid; job < v1.nw * qd; job += nw) {
@@ -1617,6 +1662,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
 
         // -- second level and below: each wave claims one top-level item at a time, expands
         //    it and searches depth-first below it
+        hdr[0] = top;  // every lane stores the same header
+        wait_mem();
         FrameState cur = top;
         int depth = 0;
         while (!aborted) {
@@ -1633,7 +1680,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                     const int base = cur.chunk + 64;
                     if (base >= cur.n) {
                         --depth;
-                        cur = depth > 0 ? uni_frame(hdr[depth]) : top;
+                        cur = uni_frame(hdr[depth]);  // hdr[0] holds the top-level list
                         continue;
                     }
                     cur.chunk = base;
@@ -1684,7 +1731,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
     }
 }
 
-size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + (size_t)waves * (64 * W * sizeof(uint32_t) + kWaveLds); }
+size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + hist_region_bytes(64 * W, waves) + (size_t)waves * kWaveLds; }
 
 template <int W>
 hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, int64_t hi, unsigned int *counter,
