@@ -1279,15 +1279,63 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         c.row = row;
         c.x_root = x;
 
+        // -- the 2-hop walk of x, spread over the whole workgroup: walk index t belongs to the
+        //    neighbour w_j with woff[j] <= t < woff[j+1] and reads entry wbase[j] + t - woff[j]
+        //    of the other side's CSR (a hub neighbour no longer holds up one wave alone)
+        // (wide classes keep one neighbour per wave: their registers are spent elsewhere)
+        constexpr bool kFlatWalk = W <= 2;
+        lds_u32 *woff = lds_at<lds_u32>(lds_raw, sizeof(WGShared));
+        lds_u32 *wbase = woff + (BITS + 1);
+        if (kFlatWalk && wid == 0) {
+            int carry = 0;
+            for (int base = 0; base < d; base += 64) {
+                const int j = base + ln;
+                int dw = 0;
+                if (j < d) {
+                    const int32_t w = row[j];
+                    const int32_t e0 = a.o_off[w];
+                    dw = a.o_off[w + 1] - e0;
+                    wbase[j] = (uint32_t)e0;
+                }
+                const int incl = wave_incl_scan(dw);
+                if (j < d) woff[j] = (uint32_t)(carry + incl - dw);
+                carry += last_lane(incl);
+            }
+            if (ln == 0) woff[d] = (uint32_t)carry;
+        }
+        if (kFlatWalk) __syncthreads();
+        const int walk = kFlatWalk ? (int)uni(woff[d]) : 0;
+        auto walk_at = [&](int t, int &j) {
+            int lo = 0, hi = d - 1;  // the last neighbour whose walk starts at or before t
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((int)woff[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            j = lo;
+            return a.o_adj[wbase[lo] + (uint32_t)(t - (int)woff[lo])];
+        };
+
         // -- reverse scan 1: mark the ranks of all 2-hop neighbours of x
-        for (int j = wid; j < d; j += nw) {
-            const int32_t w = row[j];
-            const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
-            for (int p = e0 + ln; p < e1; p += 64) {
-                const int32_t v = a.o_adj[p];
+        if constexpr (kFlatWalk) {
+            for (int t = tid; t < walk; t += nt) {
+                int j;
+                const int32_t v = walk_at(t, j);
                 if (v != x) {
                     const int32_t rk = a.rank[v];
                     atomicOr(reinterpret_cast<unsigned long long *>(&bitmap[rk >> 6]), 1ull << (rk & 63));
+                }
+            }
+        } else {
+            for (int j = wid; j < d; j += nw) {
+                const int32_t w = row[j];
+                const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
+                for (int p = e0 + ln; p < e1; p += 64) {
+                    const int32_t v = a.o_adj[p];
+                    if (v != x) {
+                        const int32_t rk = a.rank[v];
+                        atomicOr(reinterpret_cast<unsigned long long *>(&bitmap[rk >> 6]), 1ull << (rk & 63));
+                    }
                 }
             }
         }
@@ -1362,16 +1410,29 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         __syncthreads();
 
         // -- reverse scan 2: M[v] gets bit j for every w_j in N(x) adjacent to v
-        for (int j = wid; j < d; j += nw) {
-            const int32_t w = row[j];
-            const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
-            for (int p = e0 + ln; p < e1; p += 64) {
-                const int32_t v = a.o_adj[p];
+        if constexpr (kFlatWalk) {
+            for (int t = tid; t < walk; t += nt) {
+                int j;
+                const int32_t v = walk_at(t, j);
                 if (v != x) {
                     const int32_t rk = a.rank[v];
                     const uint32_t li =
                         bpre[rk >> 6] + (uint32_t)__popcll(bitmap[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
                     atomicOr(reinterpret_cast<unsigned long long *>(&M[(size_t)li * W + (j >> 6)]), 1ull << (j & 63));
+                }
+            }
+        } else {
+            for (int j = wid; j < d; j += nw) {
+                const int32_t w = row[j];
+                const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
+                for (int p = e0 + ln; p < e1; p += 64) {
+                    const int32_t v = a.o_adj[p];
+                    if (v != x) {
+                        const int32_t rk = a.rank[v];
+                        const uint32_t li =
+                            bpre[rk >> 6] + (uint32_t)__popcll(bitmap[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
+                        atomicOr(reinterpret_cast<unsigned long long *>(&M[(size_t)li * W + (j >> 6)]), 1ull << (j & 63));
+                    }
                 }
             }
         }
