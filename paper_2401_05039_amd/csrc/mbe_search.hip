@@ -52,6 +52,10 @@ constexpr uint64_t kHashK = 0x9E3779B97F4A7C15ull;
 constexpr uint32_t kShared = 0xFFFFFFFFu;  // frame offset meaning "the workgroup's top-level list"
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kQKeep = 256;      // most incomparable Q' masks a compressed child keeps
+// classes that reduce Q' through the presence word when |R'| <= 6 (the widest class runs out
+// of scalar registers with it)
+template <int W>
+constexpr bool kSmallRPrune = W <= 4;
 constexpr int kWaveLds = 1024 + 8 * kQKeep;  // LDS bytes per wave besides the histogram
 
 // LDS after the workgroup header: the waves' histograms (4 bytes per bit each), which the
@@ -574,10 +578,39 @@ __device__ __forceinline__ uint64_t compress_mask(const FrameView &v, const uint
 // compressed masks go to c.qk.  Returns their number, or -1 when more than kQKeep are
 // incomparable (then nothing is dropped).  Cost per chunk of 64 entries: one pass over the
 // kept masks, and one over the chunk's candidates.
-template <int WF>
-__device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn) {
+template <int WF, bool SMALL_R>
+__device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn, int r) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
+    if (SMALL_R && r <= 6) {
+        // every compressed mask is a value below 64: the set of values present is one word,
+        // its superset closure takes six shift-and-mask rounds, and the maximal values are
+        // the present ones no strictly larger present value contains
+        uint64_t pres = 0;
+        for (int base = 0; base < qn; base += 64) {
+            const int j = base + ln;
+            if (j < qn) pres |= 1ull << compress_mask<WF>(v, m, (int)c.stu[j]);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pres |= __shfl_xor(pres, o);
+        pres = uni(pres);
+        // value T: some present S contains T (round t adds the sets that differ in bit t)
+        uint64_t sup = pres;
+        sup |= (sup >> 1) & 0x5555555555555555ull;
+        sup |= (sup >> 2) & 0x3333333333333333ull;
+        sup |= (sup >> 4) & 0x0F0F0F0F0F0F0F0Full;
+        sup |= (sup >> 8) & 0x00FF00FF00FF00FFull;
+        sup |= (sup >> 16) & 0x0000FFFF0000FFFFull;
+        sup |= (sup >> 32) & 0x00000000FFFFFFFFull;
+        // value T: some present S strictly contains T (T plus one more bit, then any superset)
+        const uint64_t above = ((sup >> 1) & 0x5555555555555555ull) | ((sup >> 2) & 0x3333333333333333ull) |
+                               ((sup >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((sup >> 8) & 0x00FF00FF00FF00FFull) |
+                               ((sup >> 16) & 0x0000FFFF0000FFFFull) | ((sup >> 32) & 0x00000000FFFFFFFFull);
+        const uint64_t mx = pres & ~above;
+        if ((mx >> ln) & 1ull) c.qk[__popcll(mx & below)] = (uint64_t)ln;
+        __builtin_amdgcn_wave_barrier();
+        return __popcll(mx);
+    }
     int nk = 0;
     for (int base = 0; base < qn; base += 64) {
         const int j = base + ln;
@@ -641,7 +674,7 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     bool pruned = false;
     if constexpr (NARROW && !DIAG) {
         if (qn > 1) {
-            const int nk = prune_q<WF>(c, v, m, qn);
+            const int nk = prune_q<WF, kSmallRPrune<W>>(c, v, m, qn, r);
             if (nk >= 0) {
                 nq2 = nk;
                 pruned = true;
