@@ -665,14 +665,19 @@ __device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF]
 // layout fields of C; false when the stack is full.
 template <int WF, int W, bool NARROW, bool DIAG>
 __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int nu,
-                            int r, int qn, int pn, FrameState &C) {
+                            int r, int qn, int pn, FrameState &C, int preq) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     // Q': with diagnostics off, a compressed child keeps only its inclusion-maximal masks
-    // (the tallies of diagnostics mode count the full Q' of the method)
+    // (the tallies of diagnostics mode count the full Q' of the method).  preq >= 0: the
+    // caller already left them in c.qk, and stu[0, pn) packs each P' entry's position (low
+    // 26 bits) with its compressed mask
     int nq2 = qn;
     bool pruned = false;
-    if constexpr (NARROW && !DIAG) {
+    if (preq >= 0) {
+        nq2 = preq;
+        pruned = true;
+    } else if constexpr (NARROW && !DIAG) {
         if (qn > 1) {
             const int nk = prune_q<WF, kSmallRPrune<W>>(c, v, m, qn, r);
             if (nk >= 0) {
@@ -728,13 +733,20 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
     for (int base = pruned ? qn : 0; base < nu; base += 64) {
         const int j = base + ln;
         const bool act = j < nu;
-        const int k = act ? (int)c.stu[j] : 0;
+        const uint32_t e = act ? c.stu[j] : 0u;
+        const int k = preq >= 0 ? (int)(e & 0x3FFFFFFu) : (int)e;
         uint64_t x[WF];
         int cnt = 0;
+        if (preq >= 0) {
 #pragma unroll
-        for (int w = 0; w < WF; ++w) {
-            x[w] = act && m[w] ? v.masks[(size_t)k * WF + w] & m[w] : 0ull;  // words of R' only
-            cnt += __popcll(x[w]);
+            for (int w = 0; w < WF; ++w) x[w] = 0ull;
+            cnt = __popc(e >> 26);
+        } else {
+#pragma unroll
+            for (int w = 0; w < WF; ++w) {
+                x[w] = act && m[w] ? v.masks[(size_t)k * WF + w] & m[w] : 0ull;  // words of R' only
+                cnt += __popcll(x[w]);
+            }
         }
         const bool inp = act && j >= qn;
         uint32_t slot = (uint32_t)j;  // Q' entries keep their list order
@@ -763,15 +775,19 @@ __device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &
             if (inp) hs2[slot] = h;
             if (NARROW) {
                 uint64_t out = 0;
-                int t = 0;
+                if (preq >= 0) {
+                    out = (uint64_t)(e >> 26);
+                } else {
+                    int t = 0;
 #pragma unroll
-                for (int w = 0; w < WF; ++w) {
-                    uint64_t mm = m[w];
-                    while (mm) {  // the same trip count on every lane: m is uniform
-                        const int p = __ffsll((unsigned long long)mm) - 1;
-                        mm &= mm - 1ull;
-                        out |= ((x[w] >> p) & 1ull) << t;
-                        ++t;
+                    for (int w = 0; w < WF; ++w) {
+                        uint64_t mm = m[w];
+                        while (mm) {  // the same trip count on every lane: m is uniform
+                            const int p = __ffsll((unsigned long long)mm) - 1;
+                            mm &= mm - 1ull;
+                            out |= ((x[w] >> p) & 1ull) << t;
+                            ++t;
+                        }
                     }
                 }
                 masks2[slot] = out;
@@ -902,10 +918,93 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     // with R', the AND those holding all of it (after i only, the node being maximal; they
     // join L').  The rest -- Q' before i, P' after -- are listed in stu in list order, and
     // the P' counts |mask n R'| are tallied per value in c.hist for the child's stable sort.
+    //
+    // When |R'| <= 6 (and diagnostics are off) the rows give each entry's compressed mask
+    // directly (its bit in each of R''s rows), so no entry is read: Q' is reduced to its
+    // maximal masks through the presence word (as in prune_q) and only P' is listed, each
+    // stu word packing the position (low 26 bits) with the compressed mask.
     int qn = 0, nu = 0;
     int ne_l = 0, qn_l = 0;
     uint64_t exps = 0, fwc = 0;
-    {
+    // (the two-word class takes it on its own two-word lists only: register budget)
+    const bool fastq = !DIAG && kSmallRPrune<W> && (W != 2 || WF == W) && r <= 6 && F.n < (1 << 26);
+    int preq = -1;  // with fastq: the number of maximal Q' masks left in c.qk
+    if (fastq) {
+        int bl[6];  // the bits of R'
+#pragma unroll
+        for (int t = 0; t < 6; ++t) bl[t] = t < r ? (int)uni(c.hist[t]) : 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int b = ln; b < r; b += 64) c.hist[b] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        const int wi = i >> 6;
+        const uint64_t bi = 1ull << (i & 63);
+        uint64_t pres = 0;
+        for (int base = 0; base < v.nw; base += 64) {
+            const int wd = base + ln;
+            const bool in = wd < v.nw;
+            uint64_t x[6];
+            uint64_t u = 0ull, a = in ? ~0ull : 0ull;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                x[t] = (t < r && in) ? v.rows[(size_t)bl[t] * v.nw + wd] : 0ull;
+                if (t < r) {
+                    u |= x[t];
+                    a &= x[t];
+                }
+            }
+            if (wd == wi) {
+                u &= ~bi;
+                a &= ~bi;
+            }
+            ne_l += __popcll(a);
+            for (uint64_t f = a; f;) {
+                const int b = __ffsll((unsigned long long)f) - 1;
+                f &= f - 1ull;
+                exps += v.hs[64 * wd + b];
+            }
+            const uint64_t qp = u & ~a;
+            const uint64_t before = wd < wi ? ~0ull : (wd == wi ? bi - 1ull : 0ull);
+            auto cmask = [&](int p) {
+                uint32_t cm = 0;
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    if (t < r) cm |= (uint32_t)((x[t] >> p) & 1ull) << t;
+                return cm;
+            };
+            for (uint64_t q = qp & before; q; q &= q - 1ull) pres |= 1ull << cmask(__ffsll((unsigned long long)q) - 1);
+            uint64_t pm = qp & ~before;
+            const int pc = __popcll(pm);
+            const int incl = wave_incl_scan(pc);
+            int at = nu + incl - pc;
+            while (pm) {
+                const int b = __ffsll((unsigned long long)pm) - 1;
+                pm &= pm - 1ull;
+                const uint32_t cm = cmask(b);
+                c.stu[at++] = (uint32_t)(64 * wd + b) | (cm << 26);
+                lds_add32(&c.hist[__popc(cm)], 1u);
+            }
+            nu += last_lane(incl);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pres |= __shfl_xor(pres, o);
+        pres = uni(pres);
+        uint64_t sup = pres;
+        sup |= (sup >> 1) & 0x5555555555555555ull;
+        sup |= (sup >> 2) & 0x3333333333333333ull;
+        sup |= (sup >> 4) & 0x0F0F0F0F0F0F0F0Full;
+        sup |= (sup >> 8) & 0x00FF00FF00FF00FFull;
+        sup |= (sup >> 16) & 0x0000FFFF0000FFFFull;
+        sup |= (sup >> 32) & 0x00000000FFFFFFFFull;
+        const uint64_t above = ((sup >> 1) & 0x5555555555555555ull) | ((sup >> 2) & 0x3333333333333333ull) |
+                               ((sup >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((sup >> 8) & 0x00FF00FF00FF00FFull) |
+                               ((sup >> 16) & 0x0000FFFF0000FFFFull) | ((sup >> 32) & 0x00000000FFFFFFFFull);
+        const uint64_t mx = pres & ~above;
+        if ((mx >> ln) & 1ull) c.qk[__popcll(mx & below)] = (uint64_t)ln;
+        preq = __popcll(mx);
+        qn = 0;
+        wait_mem();  // stu is read by other lanes below
+        __builtin_amdgcn_wave_barrier();
+    } else {
         const int wi = i >> 6;
         const uint64_t bi = 1ull << (i & 63);
         for (int base = 0; base < v.nw; base += 64) {
@@ -934,27 +1033,27 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
             }
             nu += last_lane(incl);
         }
-    }
-    const int ne = wave_sum_i32(ne_l);
-    qn = wave_sum_i32(qn_l);
-    const int pn = nu - qn;
-    wait_mem();  // stu is read by other lanes below
-    for (int b = ln; b < r; b += 64) c.hist[b] = 0u;
-    __builtin_amdgcn_wave_barrier();
-    for (int base = DIAG ? 0 : qn; base < nu; base += 64) {
-        const int j = base + ln;
-        if (j < nu) {
-            const int k = (int)c.stu[j];
-            if (j >= qn) {
-                int cnt = 0;
+        qn = wave_sum_i32(qn_l);
+        wait_mem();  // stu is read by other lanes below
+        for (int b = ln; b < r; b += 64) c.hist[b] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        for (int base = DIAG ? 0 : qn; base < nu; base += 64) {
+            const int j = base + ln;
+            if (j < nu) {
+                const int k = (int)c.stu[j];
+                if (j >= qn) {
+                    int cnt = 0;
 #pragma unroll
-                for (int w = 0; w < WF; ++w)
-                    if (m[w]) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);  // words of R' only
-                lds_add32(&c.hist[cnt], 1u);
+                    for (int w = 0; w < WF; ++w)
+                        if (m[w]) cnt += __popcll(v.masks[(size_t)k * WF + w] & m[w]);  // words of R' only
+                    lds_add32(&c.hist[cnt], 1u);
+                }
+                if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
             }
-            if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
         }
     }
+    const int ne = wave_sum_i32(ne_l);
+    const int pn = nu - qn;
 
     // report (L', R')
     const uint64_t sL = F.sL + v.hs[i] + wave_sum_u64(exps);
@@ -1000,10 +1099,10 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     // |R'| <= 64, compressed to |R'| bits
     bool ok;
     if constexpr (WF == 1) {
-        ok = build_child<1, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C);
+        ok = build_child<1, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C, preq);
     } else {
-        ok = r <= 64 ? build_child<WF, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C)
-                     : build_child<WF, W, false, DIAG>(c, F, v, m, nu, r, qn, pn, C);
+        ok = r <= 64 ? build_child<WF, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C, preq)
+                     : build_child<WF, W, false, DIAG>(c, F, v, m, nu, r, qn, pn, C, preq);
     }
     if (!ok) return false;
     C.level = F.level + 1;
