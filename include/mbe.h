@@ -81,6 +81,8 @@ typedef struct mbe_graph {
  *            candidate set-up, [1] settling single-vertex nodes, [2] maximality tests of the
  *            other nodes, [3] scans of maximal nodes, [4] building child lists, [5] waiting,
  *            stealing and claiming
+ * shared_chunks  64-candidate chunks of third-level lists searched by a wave other than the
+ *            list's owner (steal_k = 3; for a batch, the whole call's); counted in every mode
  */
 typedef struct mbe_result {
     uint64_t count;
@@ -93,6 +95,7 @@ typedef struct mbe_result {
     uint32_t side;
     double kernel_ms;
     uint64_t phase_cycles[6];
+    uint64_t shared_chunks;
 } mbe_result;
 
 /* ------------------------------------------------------------------------- options */
@@ -105,10 +108,16 @@ typedef struct mbe_result {
  *   grid         workgroups of the persistent search kernel (default: 2 per compute unit).
  *   diagnostics  1: also compute nodes / nonmaximal / max_depth / bytes_alg.
  *   no_validate  1: skip the O(|E|) check of the CSR pair (the caller vouches for it).
- *   steal_k      work sharing below a top-level candidate (the k of section III-D): 2
- *                (default): the candidates of its child list that need a full node are
- *                claimed one at a time by the owning workgroup's waves and by idle
- *                workgroups, which rebuild the same list; 1: by the owning workgroup only.
+ *   steal_k      work sharing below a top-level candidate (the k of section III-D): 2: the
+ *                candidates of its child list that need a full node are claimed one at a
+ *                time by the owning workgroup's waves and by idle workgroups, which rebuild
+ *                the same list; 1: by the owning workgroup only; 3 (default): as 2, and in
+ *                the classes of degree above 64 the child lists of
+ *                second-level nodes are shared too: a wave publishes the rest of such a list
+ *                (in 64-candidate chunks) once a wave or workgroup is idle, and idle waves of
+ *                its workgroup and idle workgroups (after every launch's top-level
+ *                candidates are handed out) claim chunks and rebuild the list themselves.
+ *                Results never depend on it.
  *   root_lo, root_hi
  *                restrict the search to the top-level candidates whose rank lies in
  *                [root_lo, root_hi) (rank = position in ascending (degree, id) order among
@@ -163,7 +172,7 @@ int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_
 /*
  * Autotuner of the batched form: runs mbe_count_batch on the given graphs (a representative
  * sample of the batches to come) under each candidate launch setting -- waves per workgroup
- * in {8, 4, 2} times steal_k in {2, 1} -- starting from base (NULL: defaults), checks that
+ * in {8, 4, 2} times steal_k in {3, 1} -- starting from base (NULL: defaults), checks that
  * every setting gives the same per-graph count and hash, and writes the fastest setting
  * (wall time of the whole call) to *best and its time in milliseconds to *best_ms (may be
  * NULL).  Errors as mbe_count_batch; MBE_ERR_DEVICE if two settings disagree.

@@ -139,14 +139,14 @@ struct Opts {
 };
 
 Opts read_opts(const mbe_options *o) {
-    Opts r{0, 8, 0, 0, 0, 2, 0, -1, nullptr};
+    Opts r{0, 8, 0, 0, 0, 3, 0, -1, nullptr};
     if (!o) return r;
     r.side = o->side;
     r.waves = o->wg_waves > 0 ? o->wg_waves : 8;
     r.grid = o->grid > 0 ? o->grid : 0;
     r.diag = o->diagnostics != 0;
     r.no_validate = o->no_validate != 0;
-    r.steal_k = o->steal_k == 0 ? 2 : o->steal_k;
+    r.steal_k = o->steal_k == 0 ? 3 : o->steal_k;
     r.root_lo = o->root_lo > 0 ? o->root_lo : 0;
     r.root_hi = o->root_hi > 0 ? o->root_hi : -1;
     r.stream = static_cast<hipStream_t>(o->stream);
@@ -165,7 +165,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     if (g->n_u < 0 || g->n_v < 0 || g->n_edges < 0) return MBE_ERR_INVALID_ARG;
     Opts opt = read_opts(opt_in);
     if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
-        opt.steal_k < 1 || opt.steal_k > 2)
+        opt.steal_k < 1 || opt.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
     if (enumerate && !ubuf && ucap_ints > 0) return MBE_ERR_INVALID_ARG;
     const int side = opt.side ? opt.side : (g->n_v < g->n_u ? 2 : 1);
@@ -208,7 +208,8 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         v_adj = d_vadj;
     }
 
-    // small device block: acc[16] | flags | counters[8] + live steal slots[8] | stats[16]
+    // small device block: acc[16] | flags | counters[8] + live steal slots[8] + third-level
+    // sharing counters[48] | stats[16]
     MBE_TRY(st->small.ensure(4096));
     unsigned long long *acc = st->small.as<unsigned long long>(0);
     unsigned int *flags = st->small.as<unsigned int>(256);
@@ -301,6 +302,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
 
     SearchArgs a{};
     a.steal_on = opt.steal_k >= 2 ? 1 : 0;
+    a.k3 = opt.steal_k >= 3 ? 1 : 0;
     a.c_off = c_off;
     a.c_adj = c_adj;
     a.o_off = o_off;
@@ -338,6 +340,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     out->max_depth = (uint32_t)hacc[ACC_MAX_DEPTH];
     out->kernel_ms = ms;
     for (int q = 0; q < PH_COUNT; ++q) out->phase_cycles[q] = hacc[ACC_PHASE + q];
+    out->shared_chunks = hacc[ACC_SHARED];
 
     if (!enumerate) return MBE_OK;
     if ((hflags & FLAG_RECORD_OVERFLOW) || out->out_ints > ucap_ints) return MBE_ERR_BUFFER_TOO_SMALL;
@@ -404,14 +407,17 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         if (st->arena.fresh) MBE_TRY(hipMemsetAsync(st->arena.p, 0, st->arena.bytes, s));
         MBE_TRY(st->slots.ensure(sizeof(unsigned int) * (size_t)nslots));
         a.slot_busy = st->slots.as<unsigned int>();
-        MBE_TRY(st->steal.ensure(sizeof(StealSlot) * (size_t)nslots * 5));
+        // per class: nslots top-level slots, then nslots * waves third-level slots
+        const size_t steal_bytes = sizeof(StealSlot) * (size_t)nslots * 5;
+        const size_t pub_bytes = sizeof(PubSlot) * (size_t)nslots * (size_t)waves * 5;
+        MBE_TRY(st->steal.ensure(steal_bytes + pub_bytes));
         MBE_TRY(hipMemset2DAsync(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, 0, (size_t)dims.nwords * 8, (size_t)nslots, s));
         MBE_TRY(hipMemsetAsync(a.slot_busy, 0, sizeof(unsigned int) * (size_t)nslots, s));
-        MBE_TRY(hipMemsetAsync(st->steal.p, 0, sizeof(StealSlot) * (size_t)nslots * 5, s));
+        MBE_TRY(hipMemsetAsync(st->steal.p, 0, steal_bytes + (a.k3 ? pub_bytes : 0), s));
         MBE_TRY(hipMemsetAsync(run_acc, 0, run_acc_bytes, s));
         if (graph_acc && graph_acc != run_acc) MBE_TRY(hipMemsetAsync(graph_acc, 0, graph_acc_bytes, s));
         MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
-        MBE_TRY(hipMemsetAsync(counters, 0, 16 * 4, s));
+        MBE_TRY(hipMemsetAsync(counters, 0, 64 * 4, s));
         MBE_TRY(hipEventRecord(st->ev0, s));
         if (!sequential) MBE_TRY(hipEventRecord(st->fork, s));
         for (int c = 4; c >= 0; --c) {
@@ -419,6 +425,15 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
             SearchArgs ac = a;
             ac.steal = st->steal.as<StealSlot>() + (size_t)c * nslots;
             ac.steal_live = counters + 8 + c;
+            ac.pub = st->steal.as<PubSlot>(steal_bytes) + (size_t)c * nslots * (size_t)waves;
+            ac.pubw = waves;
+            ac.pub_live = counters + 16 + c;
+            ac.busy = counters + 24 + c;
+            ac.hungry = counters + 32 + c;
+            ac.epoch_ctr = counters + 40 + c;
+            ac.cls = c;
+            ac.cls_ctr = counters;
+            for (int q = 0; q < 5; ++q) ac.cls_n[q] = std::max<int64_t>(0, cls_hi[q] - cls_lo[q]);
             hipStream_t cs = s;
             if (!sequential) {
                 cs = st->cls_stream[c];
@@ -435,6 +450,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         MBE_TRY(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, s));
         MBE_TRY(hipStreamSynchronize(s));
         MBE_TRY(hipEventElapsedTime(ms, st->ev0, st->ev1));
+        if (hflags & FLAG_SHARE_MISMATCH) return MBE_ERR_DEVICE;
         if (!(hflags & FLAG_RERUN)) break;
         if (attempt >= 8) return MBE_ERR_OUT_OF_MEMORY;
         if (hflags & FLAG_NO_SLOT) sequential = true;
@@ -481,7 +497,7 @@ int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_res
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
     const Opts opt = read_opts(opt_in);
     if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
-        opt.steal_k < 1 || opt.steal_k > 2)
+        opt.steal_k < 1 || opt.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
     for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
     const int rc = check_graphs(gs, n, !opt.no_validate);
@@ -505,7 +521,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
     Opts opt = read_opts(opt_in);
     if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
-        opt.steal_k < 1 || opt.steal_k > 2)
+        opt.steal_k < 1 || opt.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
     for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
     // host checks and packing (each graph keeps its own candidate side)
@@ -661,6 +677,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
 
     SearchArgs a{};
     a.steal_on = opt.steal_k >= 2 ? 1 : 0;
+    a.k3 = opt.steal_k >= 3 ? 1 : 0;
     a.c_off = d_coff;
     a.c_adj = d_cadj;
     a.o_off = d_ooff;
@@ -690,6 +707,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         outs[i].max_depth = (uint32_t)q[ACC_MAX_DEPTH];
         outs[i].kernel_ms = ms;
         for (int ph = 0; ph < PH_COUNT; ++ph) outs[i].phase_cycles[ph] = q[ACC_PHASE + ph];
+        outs[i].shared_chunks = hacc[ACC_SHARED];  // (the whole call's)
     }
     return MBE_OK;
 }
@@ -850,7 +868,7 @@ int server_create(const mbe_server_options *opt, mbe_server **out) {
     }
     sv->search.root_lo = sv->search.root_hi = 0;
     if (sv->search.wg_waves < 0 || sv->search.wg_waves > 8 || sv->search.side < 0 || sv->search.side > 2 ||
-        sv->search.steal_k < 0 || sv->search.steal_k > 2)
+        sv->search.steal_k < 0 || sv->search.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
     MBE_TRY(hipGetDevice(&sv->device));
     if (hipDeviceGetAttribute(&sv->cus, hipDeviceAttributeMultiprocessorCount, sv->device) != hipSuccess || sv->cus <= 0)
@@ -966,7 +984,7 @@ int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_
     std::vector<mbe_result> ref((size_t)n), outs((size_t)n);
     // candidates: waves per workgroup x work sharing; the first run also warms the workspace
     static const int kWaves[] = {8, 4, 2};
-    static const int kSteal[] = {2, 1};
+    static const int kSteal[] = {3, 1};
     double bt = 0.0;
     bool have = false;
     for (int wi = 0; wi < 3; ++wi) {

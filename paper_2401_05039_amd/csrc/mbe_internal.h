@@ -20,7 +20,7 @@ enum AccSlot : int {
     ACC_RECORDS = 7,    // records reserved in the record arena
     ACC_REC_INTS = 8,   // ints reserved in the record arena
     ACC_NEED_UCAP = 9,  // largest universe met (max), for resizing after an overflow
-    ACC_RESERVED10 = 10,
+    ACC_SHARED = 10,    // third-level chunks searched by a wave other than the list's owner
     ACC_PHASE = 11,     // 6 slots: shader-clock cycles per search phase (diagnostics only)
     ACC_SLOTS = 24,
 };
@@ -45,6 +45,7 @@ enum FlagBits : unsigned int {
     FLAG_DEGREE = 1u << 4,             // candidate degree above the supported mask width
     FLAG_UNIVERSE_OVERFLOW = 1u << 5,  // a local universe or its posting lists did not fit
     FLAG_NO_SLOT = 1u << 6,            // a workgroup found no free arena slot: rerun one class at a time
+    FLAG_SHARE_MISMATCH = 1u << 7,     // a rebuilt third-level list was not its owner's (internal error)
 };
 constexpr unsigned int FLAG_RERUN = FLAG_STACK_OVERFLOW | FLAG_DEPTH_OVERFLOW | FLAG_UNIVERSE_OVERFLOW | FLAG_NO_SLOT;
 
@@ -105,6 +106,20 @@ struct StealSlot {
     unsigned long long pad2;
 };
 
+// Third-level sharing slot of one wave (steal_k >= 3): while the wave searches the child list
+// of a second-level node and others are idle, word = (epoch << 32) | 64-candidate chunks of
+// that list claimed so far, and the other fields name the list: graph g, top-level rank k,
+// limit = number of chunks, position i1 of the second-level node in the top-level list, first
+// = list position of chunk 0.  word = 0 otherwise.  Epochs come from a per-launch counter, so
+// a claim against a withdrawn list always fails.  word, g, k and limit sit where they sit in a
+// StealSlot, and the two have the same size: idle workgroups scan both kinds with one loop.
+struct PubSlot {
+    unsigned long long word;
+    int32_t g, k, limit, i1, first, pad;
+};
+static_assert(sizeof(PubSlot) == sizeof(StealSlot), "slot kinds share a stride");
+static_assert(offsetof(PubSlot, limit) == offsetof(StealSlot, limit), "slot kinds share a head");
+
 struct SearchArgs {
     // packed graph(s) in candidate orientation: rows of c_off / c_adj are candidates, ids in
     // c_adj are other-side ids and vice versa
@@ -121,6 +136,16 @@ struct SearchArgs {
     int32_t steal_on;           // 0: no stealing (each top-level candidate stays in one workgroup)
     unsigned int *steal_live;   // number of this launch's slots currently published (zeroed first)
     int32_t nslots;             // arena slots shared by the concurrent launches
+    int32_t k3;                 // 1: third-level lists are shared too (steal_k >= 3)
+    PubSlot *pub;               // nslots * pubw third-level slots of this launch (zeroed first)
+    int32_t pubw;               // slots per arena slot (waves per workgroup)
+    unsigned int *pub_live;     // third-level slots currently published (zeroed first)
+    unsigned int *busy;         // workgroups holding a task (zeroed first)
+    unsigned int *hungry;       // workgroups waiting for work while others are busy (zeroed first)
+    unsigned int *epoch_ctr;    // source of third-level epochs (zeroed first)
+    int32_t cls;                // mask class of this launch
+    const unsigned int *cls_ctr;  // top-level candidate counters of the five class launches
+    int64_t cls_n[5];           // top-level candidates of each class launch
     unsigned int *slot_busy;    // nslots flags: a slot is held by a running workgroup
     // outputs
     unsigned long long *acc;    // run-wide slots (overflow sizes, record cursors)

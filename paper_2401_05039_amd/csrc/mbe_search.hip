@@ -339,7 +339,7 @@ __device__ __forceinline__ uint64_t deg_of(const Ctx &c, uint32_t li) {
 // Stable counting sort of n staged (parent position, key) pairs by key (keys in [1, nbins));
 // sorted slot s receives parent position p through put(s, p).  One wave.
 template <typename Put>
-__device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, int n, int nbins, lds_u32 *hist,
+__device__ __forceinline__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, int n, int nbins, lds_u32 *hist,
                                  Put put) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
@@ -385,7 +385,7 @@ __device__ void wave_sort_by_key(const uint32_t *src, const uint32_t *key_of, in
 // Per-bit tables and rows of a wide frame whose entries are in place; its masks lie within
 // the words of R (m): rows of the other words are never read and are not written.  One wave.
 template <int WF>
-__device__ void build_tables_wide(const FrameView &v, int n, int nq, const uint64_t (&m)[WF]) {
+__device__ __forceinline__ void build_tables_wide(const FrameView &v, int n, int nq, const uint64_t (&m)[WF]) {
     constexpr int bits = 64 * WF;
     const int ln = lane_id();
     for (int b = ln; b < bits; b += 64) {
@@ -435,7 +435,7 @@ __device__ __forceinline__ void narrow_table_add(const Ctx &c, uint32_t slot, ui
         lds_add64(&c.tl_H[b], h);
     }
 }
-__device__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n, int r) {
+__device__ __forceinline__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n, int r) {
     const int ln = lane_id();
     __builtin_amdgcn_wave_barrier();
     if (ln < r) {
@@ -454,7 +454,7 @@ __device__ void narrow_table_finish(const Ctx &c, const FrameView &v, int n, int
 // Write the record of the maximal biclique (L', R') of a node.  R' is given as positions of
 // N(x_root) (Rr, Wroot words).  L' = {x_root} u {universe v : M[v] contains R'}: every vertex
 // adjacent to all of R'.  Sides are sorted later by the canonicaliser.
-__device__ void write_record(const Ctx &c, const uint64_t *Rr, int nL, int r) {
+__device__ __forceinline__ void write_record(const Ctx &c, const uint64_t *Rr, int nL, int r) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     const unsigned long long len = 2ull + (unsigned long long)nL + (unsigned long long)r;
@@ -504,7 +504,7 @@ __device__ void write_record(const Ctx &c, const uint64_t *Rr, int nL, int r) {
 // Candidates [base, base+64) of frame F: lanes with |R'| = 1 are settled here; the rest are
 // returned as a lane mask.
 template <int WF, bool DIAG, bool ENUM>
-__device__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameView &v, int base, WaveAcc &acc,
+__device__ __forceinline__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameView &v, int base, WaveAcc &acc,
                                 bool settle = true) {
     const int ln = lane_id();
     const int i = base + ln;
@@ -579,7 +579,7 @@ __device__ __forceinline__ uint64_t compress_mask(const FrameView &v, const uint
 // incomparable (then nothing is dropped).  Cost per chunk of 64 entries: one pass over the
 // kept masks, and one over the chunk's candidates.
 template <int WF, bool SMALL_R>
-__device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn, int r) {
+__device__ __forceinline__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn, int r) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     if (SMALL_R && r <= 6) {
@@ -664,7 +664,7 @@ __device__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF]
 // to R' and, when NARROW, compressed to |R'| bits; the tables and rows follow.  Sets the
 // layout fields of C; false when the stack is full.
 template <int WF, int W, bool NARROW, bool DIAG>
-__device__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int nu,
+__device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int nu,
                             int r, int qn, int pn, FrameState &C, int preq) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
@@ -839,10 +839,11 @@ __device__ __forceinline__ void fold_rows(const Ctx &c, const FrameView &v, int 
 }
 
 // The candidate at position i of frame F, |R'| = r >= 1, handled by the whole wave.
-// Returns true when a child frame was written (its state in C).
+// Returns true when a child frame was written (its state in C).  report = false rebuilds the
+// child frame of a node another wave owns: nothing is counted or recorded.
 template <int WF, int W, bool DIAG, bool ENUM>
-__device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v, int i, FrameState &C,
-                           WaveAcc &acc) {
+__device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v, int i, FrameState &C,
+                           WaveAcc &acc, bool report) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     uint64_t m[WF];
@@ -900,13 +901,13 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         for (int w = 0; w < WF; ++w)
             if ((m[w] >> ln) & 1ull) t += 2ull + (uint64_t)c.degl[root_pos(F, v, (uint32_t)(64 * w + ln))];
         rs = wave_sum_u64(t);
-        if (ln == 0) {
+        if (ln == 0 && report) {
             acc.nodes += 1;
             if ((uint32_t)F.level > acc.max_depth) acc.max_depth = (uint32_t)F.level;
         }
     }
     if (nonmax) {
-        if (DIAG && ln == 0) {
+        if (DIAG && ln == 0 && report) {
             acc.nonmax += 1;
             const uint64_t fw = F.fw - (2ull + dx);
             acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r);
@@ -1063,12 +1064,12 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         if ((m[w] >> ln) & 1ull) sr += c.hvl[root_pos(F, v, (uint32_t)(64 * w + ln))];
     sr = wave_sum_u64(sr);
     const int nL = F.nL + 1 + ne;
-    if (ln == 0) {
+    if (ln == 0 && report) {
         acc.count += 1;
         acc.hash += pair_hash(c.c_is_v, sL, sr);
         acc.out_ints += 2ull + (uint64_t)nL + (uint64_t)r;
     }
-    if (ENUM) {
+    if (ENUM && report) {
         uint64_t Rr[16];
         for (int w = 0; w < 16; ++w) Rr[w] = 0ull;
 #pragma unroll
@@ -1083,7 +1084,7 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
         }
         write_record(c, Rr, nL, r);
     }
-    if (DIAG && ln == 0) {
+    if (DIAG && ln == 0 && report) {
         const uint64_t fw = F.fw - (2ull + dx);
         acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r + (uint64_t)pn +
                              (uint64_t)qn);
@@ -1113,6 +1114,21 @@ __device__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v
     return true;
 }
 
+// A wave's third-level sharing state (kept in LDS: it is needed only between chunks).
+struct WaveShare {
+    int cdepth;   // depth whose chunks are claimed through slot cidx (-1: none)
+    int cidx;     // that slot (index into the launch's third-level slots)
+    unsigned int cepoch;
+    int cfirst;   // list position of chunk 0, and the number of chunks
+    int climit;
+    int pend;     // a chunk claimed before the list was rebuilt (-1: none)
+    int hitem;    // top-level position of the node whose list is rebuilt
+    int item1;    // top-level position of the node whose list is at depth 1
+    int cown;     // 1: this wave published slot cidx
+    int pad[3];
+};
+typedef __attribute__((address_space(3))) WaveShare lds_ws;
+
 struct WGShared {
     unsigned long long task;
     int s0;
@@ -1125,7 +1141,7 @@ struct WGShared {
     unsigned long long rs1;
     int nexp;
     int graph;  // graph whose tallies the workgroup is holding
-    int mode;   // 0 done, 1 own task, 2 stolen task
+    int mode;   // 0 done, 1 own task, 2 stolen top-level list, 3 stolen third-level list
     int victim; // workgroup whose child list a stolen task shares
     unsigned int epoch;
     int gclaim; // chunks are claimed through the global steal slot
@@ -1134,11 +1150,22 @@ struct WGShared {
     int scan[16];
     unsigned long long red[16];  // per-graph tally reduction
     unsigned long long cov[16];  // bits of N(x) held by a multi-bit top-level Q mask
+    int held;            // the workgroup counts in a.busy
+    int roots_done;      // this launch's top-level candidates are all handed out
+    uint32_t busyw;      // waves holding work in the current task
+    uint32_t idlew;      // waves looking for a third-level list to help with
+    uint32_t npub;       // third-level lists published by the workgroup's waves
+    int others_done;     // (wave 0) the other launches' top-level candidates are all handed out
+    int vpub;            // mode 3: the third-level slot taken, and its epoch
+    unsigned int vepoch;
+    int tg, tk;          // graph and top-level rank of the current task
+    FrameState topf;     // the top-level frame of the current task
+    WaveShare ws[16];
 };
 
 // Add the workgroup's tallies to a graph's accumulators and clear them.  All threads call.
 template <bool DIAG>
-__device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) {
+__device__ __forceinline__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) {
     const int ln = lane_id();
     uint64_t v[7];
     v[0] = wave_sum_u64(acc.count);
@@ -1176,7 +1203,7 @@ __device__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) 
 
 // Claim the next step items of a published list: returns the first one's index, or -1 once
 // the list is used up or its owner has moved on (epoch changed).
-__device__ int claim_chunk(unsigned long long *word, unsigned int epoch, int limit, unsigned int step) {
+__device__ __forceinline__ int claim_chunk(unsigned long long *word, unsigned int epoch, int limit, unsigned int step) {
     unsigned long long old = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         if ((unsigned int)(old >> 32) != epoch) return -1;
@@ -1191,7 +1218,7 @@ __device__ int claim_chunk(unsigned long long *word, unsigned int epoch, int lim
 // Block-wide exclusive prefix of popcounts over nwords bitmap words into bpre; total in
 // sh->s0.  All threads call it; on return every thread sees all of bpre (a thread writes a
 // run of ceil(nwords / threads) entries, so callers read entries other threads wrote).
-__device__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, int nwords, WGShared *sh) {
+__device__ __forceinline__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, int nwords, WGShared *sh) {
     const int tid = threadIdx.x, nt = blockDim.x, wid = tid >> 6, nw = nt >> 6;
     const int per = (nwords + nt - 1) / nt;
     const int b0 = tid * per;
@@ -1222,6 +1249,78 @@ __device__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, in
     __syncthreads();
 }
 
+// A wave without work looks for a published third-level list with a chunk left -- the one its
+// workgroup took (thief3), else one published by a wave of its workgroup -- and claims a
+// chunk.  On success the claim and the list are left in the wave's share record (the list
+// sits at depth 1 once rebuilt).  Returns false once no wave of the workgroup holds work, or
+// a capacity ran out.  Every exit of its loop is wave-uniform.
+__device__ __forceinline__ bool find_shared_list(const SearchArgs &a, WGShared *sh, lds_ws *me, lds_u32 *busyw,
+                                              lds_u32 *idlew, lds_u32 *npub, int my_slot, int nw, bool thief3) {
+    const int ln = lane_id();
+    if (ln == 0) lds_add32(idlew, 1u);
+    bool got_one = false;
+    for (bool first = true;; first = false) {
+        if (uni(__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & FLAG_RERUN) break;
+        // the slots are read only while the workgroup has lists out (the list it took is
+        // looked at once: its owner is in another workgroup)
+        if (!(thief3 && first) && uni(__hip_atomic_load(npub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == 0u) {
+            if (uni(__hip_atomic_load(busyw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == 0u) break;
+            __builtin_amdgcn_s_sleep(8);
+            continue;
+        }
+        // lane 0: the list this workgroup took; lanes 1..nw: its waves' slots
+        int idx = -1;
+        if (ln == 0) idx = thief3 && first ? sh->vpub : -1;
+        else if (ln <= nw) idx = my_slot * a.pubw + (ln - 1);
+        bool ok = false;
+        unsigned int e = 0;
+        int lim = 0, fi = 0, it = 0;
+        if (idx >= 0) {
+            PubSlot *ps = &a.pub[idx];
+            const unsigned long long w1 = __hip_atomic_load(&ps->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            e = (unsigned int)(w1 >> 32);
+            if (e != 0u && (ln != 0 || e == sh->vepoch)) {
+                lim = __hip_atomic_load(&ps->limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fi = __hip_atomic_load(&ps->first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                it = __hip_atomic_load(&ps->i1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const unsigned long long w2 = __hip_atomic_load(&ps->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                ok = (unsigned int)(w2 >> 32) == e && (int)(unsigned int)w2 < lim;
+            }
+        }
+        const uint64_t okb = __ballot(ok);
+        if (okb) {
+            const int src = __ffsll((unsigned long long)okb) - 1;
+            idx = __builtin_amdgcn_readlane(idx, src);
+            e = (unsigned int)__builtin_amdgcn_readlane((int)e, src);
+            lim = __builtin_amdgcn_readlane(lim, src);
+            if (ln == 0) lds_add32(busyw, 1u);  // before the claim: waiting waves see work
+            int got = 0;
+            if (ln == 0) got = claim_chunk(&a.pub[idx].word, e, lim, 1u);
+            got = __builtin_amdgcn_readlane(got, 0);
+            if (got >= 0) {
+                if (ln == 0) atomicAdd(&a.acc[ACC_SHARED], 1ull);
+                me->cidx = idx;
+                me->cepoch = e;
+                me->cfirst = __builtin_amdgcn_readlane(fi, src);
+                me->climit = lim;
+                me->hitem = __builtin_amdgcn_readlane(it, src);
+                me->pend = got;
+                me->cdepth = 1;
+                got_one = true;
+                break;
+            }
+            if (ln == 0) lds_add32(busyw, ~0u);
+            continue;
+        }
+        // nothing to take: done once no wave of the workgroup holds work
+        if (uni(__hip_atomic_load(busyw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) == 0u) break;
+        __builtin_amdgcn_s_sleep(8);
+    }
+    if (ln == 0) lds_add32(idlew, ~0u);
+    return got_one;
+}
+
 // The single-word class (the most top-level candidates, small lists) keeps four waves per
 // SIMD resident: its register budget is capped at 128.
 template <int W, bool DIAG, bool ENUM>
@@ -1230,6 +1329,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
     const int tid = threadIdx.x, nt = blockDim.x, wid = uni(tid >> 6), nw = nt >> 6, ln = lane_id();
     constexpr int BITS = 64 * W;
+    // third-level sharing is built into the multi-word classes only: the single-word class
+    // (small top-level lists, register budget capped for residency) never publishes or helps
+    constexpr bool kShare3 = W >= 2;
+    const bool k3 = kShare3 && a.k3;
 
     // take a free arena slot (the launches of all mask classes share the slots; there are as
     // many as workgroups that can be resident at once, so one is always free)
@@ -1298,44 +1401,74 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
     const int ucap = a.dims.ucap;
     if (tid < 16) sh->red[tid] = 0ull;
     uint64_t t_mark = DIAG ? clock64() : 0ull;  // start of the phase being timed
-    if (tid == 0) sh->graph = -1;
+    if (tid == 0) {
+        sh->graph = -1;
+        sh->held = 0;
+        sh->roots_done = 0;
+        sh->others_done = 0;
+        sh->npub = 0u;
+    }
     __syncthreads();
 
     for (;;) {
         if (wid == 0) {
-            // a fresh top-level candidate, else a share of another workgroup's item list;
-            // stop once a capacity ran out (the host reruns with more room)
-            int mode = 0;
-            unsigned int t = 0;
+            // a fresh top-level candidate, else a share of another workgroup's top-level list,
+            // else (third-level sharing) a third-level list; with third-level sharing on, a
+            // workgroup that finds none waits while others of its launch are busy, once no
+            // launch has top-level candidates left (before that, leaving frees the CU for
+            // the other launches).  Stop once a capacity ran out (the host reruns).
             if (ln == 0) {
-                const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (!(f & FLAG_RERUN)) {
-                    t = atomicAdd(counter, 1u);
-                    mode = lo + (int64_t)t < hi ? 1 : 0;
-                    if (mode == 0 && !(a.steal_on &&
-                                       __hip_atomic_load(a.steal_live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u))
-                        mode = -1;  // nothing published: no scan
-                } else {
-                    mode = -1;
-                }
+                if (sh->held) atomicSub(a.busy, 1u);
+                sh->held = 0;
             }
-            mode = __builtin_amdgcn_readlane(mode, 0);
-            if (mode == 1 && ln == 0) {
-                sh->mode = 1;
-                sh->task = t;
-                sh->epoch = t + 1u;
-            } else if (mode != 1) {
-                // look for a published list with at least two unclaimed items, 64 slots at a time
+            bool waited = false;
+            for (;;) {
+                int mode = 0;
+                unsigned int t = 0;
+                if (ln == 0) {
+                    const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (f & FLAG_RERUN) {
+                        mode = -1;
+                    } else if (!sh->roots_done) {
+                        t = atomicAdd(counter, 1u);
+                        if (lo + (int64_t)t < hi) mode = 1;
+                        else sh->roots_done = 1;
+                    }
+                }
+                mode = __builtin_amdgcn_readlane(mode, 0);
+                if (mode == 1) {
+                    if (ln == 0) {
+                        sh->mode = 1;
+                        sh->task = t;
+                        sh->epoch = t + 1u;
+                    }
+                    break;
+                }
+                if (mode < 0) {
+                    if (ln == 0) sh->mode = 0;
+                    break;
+                }
+                // a published top-level list with at least two unclaimed items, else (third-level
+                // sharing) a published third-level list with at least two unclaimed chunks; 64
+                // slots at a time (the two slot kinds share their head fields and stride)
                 bool found = false;
-                if (mode == 0) {
-                    for (int base = 1; base < a.nslots && !found; base += 64) {
+#pragma unroll 1
+                for (int kind = 0; kind < 2 && !found; ++kind) {
+                    const bool on = kind == 0 ? a.steal_on != 0 : k3;
+                    if (!on || __hip_atomic_load(kind == 0 ? a.steal_live : a.pub_live, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT) == 0u)
+                        continue;
+                    char *arr = kind == 0 ? reinterpret_cast<char *>(a.steal) : reinterpret_cast<char *>(a.pub);
+                    const int total = kind == 0 ? a.nslots : a.nslots * a.pubw;
+                    const int start = kind == 0 ? my_slot : my_slot * a.pubw;
+                    for (int base = 1 - kind; base < total && !found; base += 64) {  // (not its own slot)
                         const int j = base + ln;
                         bool ok = false;
-                        int vwg = 0, sg = 0, sk = 0;
+                        int idx = 0, sg = 0, sk = 0;
                         unsigned int e = 0;
-                        if (j < a.nslots) {
-                            vwg = (my_slot + j) % a.nslots;
-                            StealSlot *sl = &a.steal[vwg];
+                        if (j < total) {
+                            idx = (start + j) % total;
+                            StealSlot *sl = reinterpret_cast<StealSlot *>(arr + (size_t)idx * sizeof(StealSlot));
                             const unsigned long long w1 =
                                 __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                             e = (unsigned int)(w1 >> 32);
@@ -1343,24 +1476,26 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                                 sg = __hip_atomic_load(&sl->g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                                 sk = __hip_atomic_load(&sl->k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                                 const int lim = __hip_atomic_load(&sl->limit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                __threadfence();
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                                 const unsigned long long w2 =
                                     __hip_atomic_load(&sl->word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                                // the owner has not moved on, and two or more items are left
+                                // the owner has not moved on, and two or more are left
                                 ok = (unsigned int)(w2 >> 32) == e && (int)(unsigned int)w2 + 2 <= lim;
                             }
                         }
                         const uint64_t okb = __ballot(ok);
                         if (okb) {
                             const int src = __ffsll((unsigned long long)okb) - 1;
-                            vwg = __builtin_amdgcn_readlane(vwg, src);
+                            idx = __builtin_amdgcn_readlane(idx, src);
                             sg = __builtin_amdgcn_readlane(sg, src);
                             sk = __builtin_amdgcn_readlane(sk, src);
                             e = (unsigned int)__builtin_amdgcn_readlane((int)e, src);
                             if (ln == 0) {
-                                sh->mode = 2;
-                                sh->victim = vwg;
+                                sh->mode = 2 + kind;
+                                sh->victim = idx;
+                                sh->vpub = idx;
                                 sh->epoch = e;
+                                sh->vepoch = e;
                                 sh->sg = sg;
                                 sh->sk = sk;
                             }
@@ -1368,7 +1503,33 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                         }
                     }
                 }
-                if (!found && ln == 0) sh->mode = 0;
+                if (found) break;
+                int wait = 0;
+                if (ln == 0 && k3 && __hip_atomic_load(a.busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u) {
+                    wait = 1;
+                    if (!sh->others_done) {
+#pragma unroll
+                        for (int q = 0; q < 5; ++q)
+                            if (q != a.cls && (int64_t)__hip_atomic_load(&a.cls_ctr[q], __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT) < a.cls_n[q])
+                                wait = 0;
+                        if (wait) sh->others_done = 1;  // (they stay handed out)
+                    }
+                }
+                if (!__builtin_amdgcn_readlane(wait, 0)) {
+                    if (ln == 0) sh->mode = 0;
+                    break;
+                }
+                if (ln == 0 && !waited) atomicAdd(a.hungry, 1u);
+                waited = true;
+                __builtin_amdgcn_s_sleep(64);
+            }
+            if (ln == 0) {
+                if (waited) atomicSub(a.hungry, 1u);
+                if (sh->mode != 0) {
+                    atomicAdd(a.busy, 1u);
+                    sh->held = 1;
+                }
             }
         }
         __syncthreads();
@@ -1379,7 +1540,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         }
         const int mode = uni(sh->mode);
         if (mode == 0) break;
-        const bool thief = mode == 2;
+        const bool thief = mode >= 2;  // the top-level node belongs to another workgroup
+        const bool thief3 = kShare3 && mode == 3;
         int g = 0;
         int64_t k;
         if (thief) {
@@ -1804,7 +1966,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         top.heavy = 0ull;
         top.sL = hl(c, x) + sh->exps;
         top.fw = uni((uint64_t)sh->fw1);
-        const int nch = (P1 + 63) >> 6;
+        const int nch = thief3 ? 0 : (P1 + 63) >> 6;  // a third-level thief takes no top-level item
         for (int q = wid; q < nch; q += nw) {
             const uint64_t tl = DIAG ? clock64() : 0ull;
             const uint64_t hm = light_chunk<W, DIAG, ENUM>(c, top, v1, nqk + 64 * q, acc, !thief);
@@ -1829,9 +1991,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
 
         // -- share the items: with more than one per wave, claims go through the global steal
         //    slot so that idle workgroups can take some (they rebuild the same list)
-        StealSlot *slot = thief ? &a.steal[sh->victim] : &a.steal[my_slot];
+        StealSlot *slot = mode == 2 ? &a.steal[sh->victim] : &a.steal[my_slot];
         if (tid == 0) {
-            if (thief) {
+            sh->topf = top;
+            sh->tg = g;
+            sh->tk = (int)k;
+            sh->busyw = thief3 ? 0u : (uint32_t)nw;
+            sh->idlew = 0u;
+            if (mode == 2) {
                 sh->gclaim = 1;
             } else if (a.steal_on && H > nw) {
                 slot->g = g;
@@ -1853,58 +2020,163 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             t_mark = now;
         }
 
-        // -- second level and below: each wave claims one top-level item at a time, expands
-        //    it and searches depth-first below it
+        // -- second level and below.  Each wave claims one top-level item at a time, expands
+        //    it and searches depth-first below it.  With third-level sharing, a wave whose
+        //    second-level list (depth 1) still has two or more chunks to go publishes it in
+        //    its slot once some wave or workgroup is idle, and from then on takes that list's
+        //    chunks through the slot like anyone else.  A wave left without work helps: it
+        //    claims a chunk of a list published by a wave of its workgroup (or of the
+        //    third-level list this workgroup took), rebuilds the list from the top-level frame
+        //    (the owner's own node call, reporting nothing; lists are built deterministically)
+        //    and searches the chunks it claims.  Nobody waits for a helper: every chunk is
+        //    searched by the wave that claimed it, and an owner claims until none is left.
+        lds_u32 *busyw = lds_at<lds_u32>(lds_raw, offsetof(WGShared, busyw));
+        lds_u32 *idlew = lds_at<lds_u32>(lds_raw, offsetof(WGShared, idlew));
+        lds_u32 *npub = lds_at<lds_u32>(lds_raw, offsetof(WGShared, npub));
+        lds_ws *me = lds_at<lds_ws>(lds_raw, offsetof(WGShared, ws) + (size_t)wid * sizeof(WaveShare));
+        me->cdepth = -1;
+        me->cown = 0;
+        me->hitem = -1;
+        me->pend = -1;
         hdr[0] = top;  // every lane stores the same header
         wait_mem();
-        FrameState cur = top;
-        int depth = 0;
-        while (!aborted) {
-            const FrameView v = frame_view(frame_base(c, cur.off), cur.n, cur.wf, cur.rbits);
-            int i;
-            if (depth == 0) {
-                int got = 0;
-                if (ln == 0) got = gclaim ? claim_chunk(&slot->word, epoch, H, 1u) : atomicAdd(&sh->claim, 1);
-                got = __builtin_amdgcn_readlane(got, 0);
-                if (got < 0 || got >= H) break;
-                i = (int)uni(hpos[got]);
-            } else {
-                if (cur.heavy == 0ull) {
-                    const int base = cur.chunk + 64;
-                    if (base >= cur.n) {
-                        --depth;
-                        cur = uni_frame(hdr[depth]);  // hdr[0] holds the top-level list
+        bool src_top = !thief3;  // the current source: top-level items (else one published list)
+        // idle workgroups of this launch, as read at the previous check (the load is issued
+        // one check ahead, so its latency hides under the chunk in between)
+        uint32_t hungry_seen = 0u;
+        for (;;) {
+            if (!src_top && !find_shared_list(a, sh, me, busyw, idlew, npub, my_slot, nw, thief3)) break;
+            FrameState cur = uni_frame(sh->topf);
+            int depth = 0;
+            while (!aborted) {
+                const FrameView v = frame_view(frame_base(c, cur.off), cur.n, cur.wf, cur.rbits);
+                int i;
+                if (depth == 0) {
+                    if (src_top) {
+                        int got = 0;
+                        if (ln == 0) got = gclaim ? claim_chunk(&slot->word, epoch, H, 1u) : atomicAdd(&sh->claim, 1);
+                        got = __builtin_amdgcn_readlane(got, 0);
+                        if (got < 0 || got >= H) break;
+                        i = (int)uni(hpos[got]);
+                        if (k3) me->item1 = i;
+                    } else {
+                        // a helped list: rebuild it once (the node call below reports nothing)
+                        i = uni(me->hitem);
+                        if (i < 0) break;
+                        me->hitem = -1;
+                    }
+                } else {
+                    if (cur.heavy == 0ull) {
+                        int base = cur.chunk + 64;
+                        if (k3 && depth == 1) {
+                            if (uni(me->cdepth) == 1) {
+                                int got = uni(me->pend);
+                                me->pend = -1;
+                                if (got < 0) {
+                                    if (ln == 0) {
+                                        got = claim_chunk(&a.pub[me->cidx].word, me->cepoch, me->climit, 1u);
+                                        if (got >= 0 && !me->cown) atomicAdd(&a.acc[ACC_SHARED], 1ull);
+                                    }
+                                    got = __builtin_amdgcn_readlane(got, 0);
+                                }
+                                if (got >= 0) {
+                                    base = uni(me->cfirst) + 64 * got;
+                                } else {
+                                    // every chunk is claimed: the owner withdraws the list
+                                    base = cur.n;
+                                    if (ln == 0 && me->cown) {
+                                        __hip_atomic_store(&a.pub[me->cidx].word, 0ull, __ATOMIC_RELEASE,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                                        atomicSub(a.pub_live, 1u);
+                                        lds_add32(npub, ~0u);
+                                    }
+                                    me->cown = 0;
+                                    me->cdepth = -1;
+                                }
+                            } else if (src_top && cur.n - base > 64 && [&] {
+                                           const bool want = uni(hungry_seen) > 0u;
+                                           hungry_seen = __hip_atomic_load(a.hungry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                           return want;
+                                       }()) {
+                                // publish the rest of this list, then claim its chunks like a helper
+                                const int idx = my_slot * a.pubw + wid;
+                                const int lim = (cur.n - base + 63) >> 6;
+                                if (ln == 0) {
+                                    PubSlot *mp = &a.pub[idx];
+                                    const unsigned int e = atomicAdd(a.epoch_ctr, 1u) + 1u;
+                                    mp->g = sh->tg;
+                                    mp->k = sh->tk;
+                                    mp->i1 = me->item1;
+                                    mp->first = base;
+                                    mp->limit = lim;
+                                    __threadfence();
+                                    __hip_atomic_store(&mp->word, (unsigned long long)e << 32, __ATOMIC_RELEASE,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                                    atomicAdd(a.pub_live, 1u);
+                                    lds_add32(npub, 1u);
+                                    me->cepoch = e;
+                                }
+                                me->cidx = idx;
+                                me->cfirst = base;
+                                me->climit = lim;
+                                me->cdepth = 1;
+                                me->cown = 1;
+                                continue;
+                            }
+                        }
+                        if (base >= cur.n) {
+                            --depth;
+                            cur = uni_frame(hdr[depth]);  // hdr[0] holds the top-level list
+                            continue;
+                        }
+                        cur.chunk = base;
+                        const uint64_t tl = DIAG ? clock64() : 0ull;
+                        cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM>(c, cur, v, base, acc)
+                                                  : light_chunk<W, DIAG, ENUM>(c, cur, v, base, acc);
+                        if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
                         continue;
                     }
-                    cur.chunk = base;
-                    const uint64_t tl = DIAG ? clock64() : 0ull;
-                    cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM>(c, cur, v, base, acc)
-                                              : light_chunk<W, DIAG, ENUM>(c, cur, v, base, acc);
-                    if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
-                    continue;
+                    const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
+                    cur.heavy &= cur.heavy - 1ull;
+                    i = cur.chunk + lane;
                 }
-                const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
-                cur.heavy &= cur.heavy - 1ull;
-                i = cur.chunk + lane;
-            }
-            FrameState ch;
-            const bool pushed = (cur.wf == 1) ? heavy_node<1, W, DIAG, ENUM>(c, cur, v, i, ch, acc)
-                                              : heavy_node<W, W, DIAG, ENUM>(c, cur, v, i, ch, acc);
-            if (pushed) {
-                if (depth >= a.dims.maxdepth) {
-                    if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
+                FrameState ch;
+                const bool report = src_top || depth > 0;
+                const bool pushed = (cur.wf == 1) ? heavy_node<1, W, DIAG, ENUM>(c, cur, v, i, ch, acc, report)
+                                                  : heavy_node<W, W, DIAG, ENUM>(c, cur, v, i, ch, acc, report);
+                if (pushed) {
+                    if (depth >= a.dims.maxdepth) {
+                        if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
+                        aborted = true;
+                        break;
+                    }
+                    if (depth > 0) {
+                        hdr[depth] = cur;  // every lane stores the same header
+                        wait_mem();
+                    }
+                    ++depth;
+                    cur = ch;
+                } else if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_STACK_OVERFLOW) {
                     aborted = true;
-                    break;
                 }
-                if (depth > 0) {
-                    hdr[depth] = cur;  // every lane stores the same header
-                    wait_mem();
-                }
-                ++depth;
-                cur = ch;
-            } else if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_STACK_OVERFLOW) {
-                aborted = true;
             }
+            if (!k3) break;
+            // a helped list whose rebuild pushed no frame (the owner's call did; never reached)
+            if (!src_top && !aborted && uni(me->pend) >= 0 && ln == 0)
+                atomicOr(a.flags, (unsigned int)FLAG_SHARE_MISMATCH);
+            // (after an abort) a list still published is withdrawn
+            if (ln == 0 && me->cown) {
+                __hip_atomic_store(&a.pub[me->cidx].word, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                atomicSub(a.pub_live, 1u);
+                lds_add32(npub, ~0u);
+            }
+            me->cown = 0;
+            me->cdepth = -1;
+            me->pend = -1;
+            me->hitem = -1;
+            if (ln == 0) lds_add32(busyw, ~0u);  // this wave's work in the source is done
+            if (aborted) break;
+            src_top = false;
         }
         if (DIAG) t_mark = clock64();  // from here to the next task: waiting
         __syncthreads();

@@ -78,7 +78,7 @@ def test_bad_options_rejected():
     g = gg.complete(2, 2)
     assert _bad(g, side=3) == -1
     assert _bad(g, wg_waves=9) == -1
-    assert _bad(g, steal_k=3) == -1
+    assert _bad(g, steal_k=4) == -1
     assert _bad(g, steal_k=-1) == -1
 
 
