@@ -83,6 +83,9 @@ typedef struct mbe_graph {
  *            stealing and claiming
  * shared_chunks  64-candidate chunks of third-level lists searched by a wave other than the
  *            list's owner (steal_k = 3; for a batch, the whole call's); counted in every mode
+ * attempts   search launches the call needed: a launch whose wave stacks or frame-header
+ *            arrays run out is repeated with twice the room (a device remembers the largest
+ *            room an earlier call needed and starts there)
  */
 typedef struct mbe_result {
     uint64_t count;
@@ -96,6 +99,8 @@ typedef struct mbe_result {
     double kernel_ms;
     uint64_t phase_cycles[6];
     uint64_t shared_chunks;
+    uint32_t attempts;
+    uint32_t reserved;
 } mbe_result;
 
 /* ------------------------------------------------------------------------- options */

@@ -46,7 +46,8 @@ class _Result(ctypes.Structure):
                 ("nodes", ctypes.c_uint64), ("nonmaximal", ctypes.c_uint64),
                 ("bytes_alg", ctypes.c_uint64), ("max_depth", ctypes.c_uint32),
                 ("side", ctypes.c_uint32), ("kernel_ms", ctypes.c_double),
-                ("phase_cycles", ctypes.c_uint64 * 6), ("shared_chunks", ctypes.c_uint64)]
+                ("phase_cycles", ctypes.c_uint64 * 6), ("shared_chunks", ctypes.c_uint64),
+                ("attempts", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class _Options(ctypes.Structure):

@@ -63,6 +63,10 @@ struct DeviceState {
     // one stream per mask class, so the class launches overlap (created on first use)
     hipStream_t cls_stream[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork = nullptr, join[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // the largest wave-stack and frame-header capacities an earlier call had to grow to:
+    // later calls start there instead of repeating a launch that runs out
+    int64_t scap_floor = 0;
+    int32_t depth_floor = 0;
 };
 
 hipError_t ensure_class_streams(DeviceState *st) {
@@ -156,7 +160,7 @@ Opts read_opts(const mbe_options *o) {
 int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
                bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
-               unsigned long long *graph_acc, size_t graph_acc_bytes);
+               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts);
 
 int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t *ubuf, uint64_t ucap_ints,
         int ubuf_on_device, bool enumerate) {
@@ -326,8 +330,10 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         cls_b[c] = std::min(cls_hi[c], hi);
     }
     {
+        int attempts = 0;
         const int rc = run_search(st, a, dims, cls_a, cls_b, opt.diag, enumerate, grid, waves, acc, ACC_SLOTS * 8, hacc,
-                                  &hflags, &ms, s, nullptr, 0);
+                                  &hflags, &ms, s, nullptr, 0, &attempts);
+        out->attempts = (uint32_t)attempts;
         if (rc != MBE_OK) return rc;
     }
 
@@ -373,7 +379,9 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
 int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
                bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
-               unsigned long long *graph_acc, size_t graph_acc_bytes) {
+               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts) {
+    dims.scap = std::max<int64_t>(dims.scap, st->scap_floor);
+    dims.maxdepth = std::max<int32_t>(dims.maxdepth, st->depth_floor);
     unsigned int *flags = a.flags;
     unsigned int *counters = st->small.as<unsigned int>(512);
     unsigned int hflags = 0;
@@ -451,6 +459,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         MBE_TRY(hipStreamSynchronize(s));
         MBE_TRY(hipEventElapsedTime(ms, st->ev0, st->ev1));
         if (hflags & FLAG_SHARE_MISMATCH) return MBE_ERR_DEVICE;
+        if (attempts) *attempts = attempt + 1;
         if (!(hflags & FLAG_RERUN)) break;
         if (attempt >= 8) return MBE_ERR_OUT_OF_MEMORY;
         if (hflags & FLAG_NO_SLOT) sequential = true;
@@ -461,6 +470,8 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
             dims.scap = std::max<int64_t>(dims.scap, 4 * (int64_t)dims.ucap + 16384);
         }
     }
+    st->scap_floor = std::max<int64_t>(st->scap_floor, dims.scap);
+    st->depth_floor = std::max<int32_t>(st->depth_floor, dims.maxdepth);
     *hflags_out = hflags;
     return MBE_OK;
 }
@@ -690,8 +701,9 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     unsigned long long hacc[ACC_SLOTS];
     unsigned int hflags = 0;
     float ms = 0.f;
+    int attempts = 0;
     int rc = run_search(st, a, dims, cls_lo, cls_hi, opt.diag, false, grid, opt.waves, acc, ACC_SLOTS * 8, hacc, &hflags,
-                        &ms, s, gacc, (size_t)n * ACC_SLOTS * 8);
+                        &ms, s, gacc, (size_t)n * ACC_SLOTS * 8, &attempts);
     if (rc != MBE_OK) return rc;
     std::vector<unsigned long long> hga((size_t)n * ACC_SLOTS);
     MBE_TRY(hipMemcpyAsync(hga.data(), gacc, hga.size() * 8, hipMemcpyDeviceToHost, s));
@@ -708,6 +720,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         outs[i].kernel_ms = ms;
         for (int ph = 0; ph < PH_COUNT; ++ph) outs[i].phase_cycles[ph] = q[ACC_PHASE + ph];
         outs[i].shared_chunks = hacc[ACC_SHARED];  // (the whole call's)
+        outs[i].attempts = (uint32_t)attempts;
     }
     return MBE_OK;
 }
