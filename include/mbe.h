@@ -152,6 +152,20 @@ typedef struct mbe_options {
 int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out);
 
 /*
+ * Device memory a mbe_count of g with these options holds: *bytes receives the sum of the
+ * graph upload (host graphs), the preparation arrays (ranking keys, order, rank, sort
+ * temporaries) and the search arena (per-workgroup universe, top-level list and per-wave
+ * stacks, sized from the largest 2-hop neighbourhood of a candidate) with its work-sharing
+ * slots.  It runs the preparation (validation and ranking, which give the neighbourhood
+ * bound) on the device but no search.  Later calls on a device start from the largest stack
+ * room earlier ones needed, which is included.  mbe_enumerate adds its record staging:
+ * about 12 bytes per int of buf_cap_ints plus the sort temporaries.  The memory stays with
+ * the library (per device) for later calls.  Errors as mbe_count; MBE_ERR_INVALID_ARG if
+ * bytes is NULL.  An empty side or zero edges gives 0.
+ */
+int mbe_workspace_size(const mbe_graph *g, const mbe_options *opt, size_t *bytes);
+
+/*
  * As mbe_count, and also write the bicliques to buf as records
  *     [|A|, |B|, a_1 < ... < a_|A|, b_1 < ... < b_|B|]     (A in U, B in V)
  * sorted by A lexicographically (a total order: A determines B).  buf holds buf_cap_ints

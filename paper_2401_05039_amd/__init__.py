@@ -97,6 +97,8 @@ def load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.mbe_count.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
     lib.mbe_count.restype = ctypes.c_int
+    lib.mbe_workspace_size.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]
+    lib.mbe_workspace_size.restype = ctypes.c_int
     lib.mbe_enumerate.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result),
                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32]
     lib.mbe_enumerate.restype = ctypes.c_int
@@ -189,6 +191,18 @@ def mbe_count(g, opt: Optional[Options] = None) -> Dict[str, Any]:
     if rc != MBE_OK:
         raise MbeError(rc, _result_dict(res))
     return _result_dict(res)
+
+
+def mbe_workspace_size(g, opt: Optional[Options] = None) -> int:
+    """Device bytes a ``mbe_count`` of g with these options holds (preparation runs, no search)."""
+    lib = load()
+    cg, keep = _marshal_graph(g)
+    co = _marshal_opts(opt, bool(cg.on_device))
+    out = ctypes.c_size_t(0)
+    rc = lib.mbe_workspace_size(ctypes.byref(cg), ctypes.byref(co), ctypes.byref(out))
+    if rc != MBE_OK:
+        raise MbeError(rc, {})
+    return int(out.value)
 
 
 def _marshal_batch(graphs):

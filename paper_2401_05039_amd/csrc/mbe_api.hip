@@ -162,8 +162,13 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
                unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts);
 
+size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi, bool diag,
+                        bool enumerate, int grid, int waves);
+
+// mbe_count / mbe_enumerate; with ws_out, only the preparation runs and *ws_out receives the
+// device bytes the search of this call would hold
 int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t *ubuf, uint64_t ucap_ints,
-        int ubuf_on_device, bool enumerate) {
+        int ubuf_on_device, bool enumerate, size_t *ws_out = nullptr) {
     if (!g || !out) return MBE_ERR_INVALID_ARG;
     std::memset(out, 0, sizeof(*out));
     if (g->n_u < 0 || g->n_v < 0 || g->n_edges < 0) return MBE_ERR_INVALID_ARG;
@@ -282,6 +287,20 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     dims.scap = 4 * (int64_t)dims.ucap + 16384;
     dims.maxdepth = 64 * Wmax + 2;
 
+    if (ws_out) {
+        int64_t cls_a[5], cls_b[5];
+        for (int c = 0; c < 5; ++c) {
+            cls_a[c] = std::max(cls_lo[c], lo);
+            cls_b[c] = std::min(cls_hi[c], hi);
+        }
+        size_t bytes = 4096 + 2 * b_keys + 2 * b_i32 + tmp_bytes;
+        if (!g->on_device)
+            bytes += align_up(((size_t)nu + 1) * 4, 256) + align_up(((size_t)nv + 1) * 4, 256) +
+                     2 * align_up((size_t)ne * 4, 256);
+        *ws_out = bytes + search_footprint(st, dims, cls_a, cls_b, opt.diag, enumerate, grid, waves);
+        return MBE_OK;
+    }
+
     // record arena for mbe_enumerate
     unsigned long long rec_cap = 0, offs_cap = 0;
     if (enumerate) {
@@ -373,6 +392,40 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     return MBE_OK;
 }
 
+// Arena slots of a search: concurrent class launches need no more than fit on the device at
+// once or than the launches have workgroups; one class at a time, the largest of each class's
+// grid and residency.  cls_grid / cls_res receive each class's grid and residency.
+int search_slots(DeviceState *st, const int64_t *cls_lo, const int64_t *cls_hi, bool diag, bool enumerate, int grid,
+                 int waves, bool sequential, int *cls_grid, int *cls_res) {
+    int64_t cap = 1, sum_grid = 0;
+    for (int c = 0; c < 5; ++c) {
+        cls_grid[c] = cls_res[c] = 0;
+        if (cls_lo[c] >= cls_hi[c]) continue;
+        cls_res[c] = st->cus * search_occupancy(1 << c, diag, enumerate, waves);
+        cls_grid[c] = grid > 0 ? grid : cls_res[c];
+        cap = std::max<int64_t>(cap, cls_res[c]);
+        sum_grid += cls_grid[c];
+    }
+    int nslots = (int)std::max<int64_t>(1, std::min(cap, sum_grid));
+    if (sequential) {
+        nslots = 1;
+        for (int c = 0; c < 5; ++c) nslots = std::max(nslots, std::min(cls_grid[c], cls_res[c]));
+    }
+    return nslots;
+}
+
+// Device bytes the search of a call holds: the arena slots, the slot flags and the sharing
+// slots (with the capacities the device has already grown to).
+size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi, bool diag,
+                        bool enumerate, int grid, int waves) {
+    dims.scap = std::max<int64_t>(dims.scap, st->scap_floor);
+    dims.maxdepth = std::max<int32_t>(dims.maxdepth, st->depth_floor);
+    int cls_grid[5], cls_res[5];
+    const size_t nslots = (size_t)search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, false, cls_grid, cls_res);
+    return search_layout(dims).wg_bytes * nslots + sizeof(unsigned int) * nslots + sizeof(StealSlot) * nslots * 5 +
+           sizeof(PubSlot) * nslots * (size_t)waves * 5;
+}
+
 // Search run shared by the single-graph and batched calls: sizes the arena, launches one
 // persistent kernel per mask-width class (widest first) and reruns with larger capacities
 // when a kernel reports an overflow.  hacc / hflags receive the run-wide slots and flags.
@@ -388,24 +441,10 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
     MBE_TRY(ensure_class_streams(st));
     // persistent grids: as many workgroups per class as fit on the device at once (unless the
     // caller fixed the grid); the arena has one slot per workgroup that can be resident
-    int cls_grid[5] = {0, 0, 0, 0, 0}, cls_res[5] = {0, 0, 0, 0, 0};
-    int64_t cap = 1, sum_grid = 0;
-    for (int c = 0; c < 5; ++c) {
-        if (cls_lo[c] >= cls_hi[c]) continue;
-        cls_res[c] = st->cus * search_occupancy(1 << c, diag, enumerate, waves);
-        cls_grid[c] = grid > 0 ? grid : cls_res[c];
-        cap = std::max<int64_t>(cap, cls_res[c]);
-        sum_grid += cls_grid[c];
-    }
+    int cls_grid[5], cls_res[5];
     bool sequential = false;
     for (int attempt = 0;; ++attempt) {
-        // concurrent launches: no more workgroups can hold slots than fit on the device or
-        // than the launches have; one class at a time: the largest of its grid and residency
-        int nslots = (int)std::max<int64_t>(1, std::min(cap, sum_grid));
-        if (sequential) {
-            nslots = 1;
-            for (int c = 0; c < 5; ++c) nslots = std::max(nslots, std::min(cls_grid[c], cls_res[c]));
-        }
+        const int nslots = search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, sequential, cls_grid, cls_res);
         a.dims = dims;
         a.lay = search_layout(dims);
         a.nslots = nslots;
@@ -1031,6 +1070,13 @@ int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_
 
 int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out) {
     return run(g, opt, out, nullptr, 0, 0, false);
+}
+
+int mbe_workspace_size(const mbe_graph *g, const mbe_options *opt, size_t *bytes) {
+    if (!bytes) return MBE_ERR_INVALID_ARG;
+    *bytes = 0;
+    mbe_result r;
+    return run(g, opt, &r, nullptr, 0, 0, false, bytes);
 }
 
 int mbe_enumerate(const mbe_graph *g, const mbe_options *opt, mbe_result *out, int32_t *buf,

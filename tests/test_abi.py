@@ -101,6 +101,18 @@ def test_empty_graphs_need_no_device():
         assert r["count"] == 0 and r["hash"] == 0
 
 
+def test_workspace_size_needs_no_device_for_trivial_input(lib):
+    import paper_2401_05039_amd as m
+    _, so = lib
+    g, keep = m._marshal_graph(gg.complete(2, 2))
+    assert so.mbe_workspace_size(ctypes.byref(g), None, None) == -1
+    for e in (gg.edgeless(4, 5), gg.edgeless(0, 3)):
+        assert m.mbe_workspace_size(e) == 0
+    with pytest.raises(m.MbeError) as err:
+        m.mbe_workspace_size(gg.complete(2, 2), m.Options(steal_k=9))
+    assert err.value.code == -1
+
+
 def test_batch_rejects_bad_input_before_device_work():
     import paper_2401_05039_amd as m
     good = gg.complete(2, 3)

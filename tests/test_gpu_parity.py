@@ -171,6 +171,18 @@ def test_third_level_sharing_dense(mbe, orc, waves, grid):
         _check(mbe, orc, g, f"k3 {g.name} {waves}x{grid}", wg_waves=waves, grid=grid, steal_k=3)
 
 
+@pytest.mark.parametrize("grid", [0, 2])
+def test_third_level_sharing_records(mbe, orc, grid):
+    # records written while lists are shared: a helper's rebuild of a list writes nothing, so
+    # the record list must be the oracle's exactly
+    g = gg.random_small(70, 400, 0.25, 3)
+    _say("k3 records", g.name, "grid", grid)
+    want = orc.mbea(g, want_list=True)
+    res, flat = mbe.mbe_enumerate(g, mbe.Options(steal_k=3, grid=grid))
+    assert (res["count"], res["hash"], res["out_ints"]) == (want["count"], want["hash"], want["out_ints"])
+    assert mbe.decode_records(flat) == want["list"]
+
+
 def test_workload3_third_level_sharing(mbe):
     # single top-level candidates with subtrees of 5.8M-88M nodes: the lists below them are
     # shared; every tally must still equal the oracle's, and some chunks must have been
@@ -191,6 +203,20 @@ def test_workload3_third_level_sharing(mbe):
                 assert r[k] == s[k], (s["rank_lo"], diag, grid, k)
             shared += r["shared_chunks"]
     assert shared > 0
+
+
+def test_workspace_size(mbe):
+    import torch
+    for g in (gg.config1(), gg.random_small(70, 400, 0.25, 3)):
+        _say("workspace size", g.name)
+        ws = mbe.mbe_workspace_size(g)
+        csr = 4 * (g.n_u + g.n_v + 2 + 2 * g.n_edges)
+        assert ws > csr  # the upload, preparation arrays and search arena
+        dg = gg.BiGraph(g.n_u, g.n_v, *[torch.from_numpy(np.asarray(a)).cuda() for a in
+                                        (g.u_off, g.u_adj, g.v_off, g.v_adj)])
+        wd = mbe.mbe_workspace_size(dg)
+        assert 0 < wd < ws  # no upload for device arrays
+        assert mbe.mbe_count(g)["count"] == mbe.mbe_count(dg)["count"]
 
 
 def test_device_pointers(mbe, orc):
