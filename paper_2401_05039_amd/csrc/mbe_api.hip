@@ -227,7 +227,6 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     if (!opt.no_validate && g->on_device) {
         MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
         MBE_TRY(launch_validate(nu, nv, ne, u_off, u_adj, v_off, v_adj, flags, s));
-        MBE_TRY(launch_validate(nv, nu, ne, v_off, v_adj, u_off, u_adj, flags, s));
         unsigned int hf = 0;
         MBE_TRY(hipMemcpyAsync(&hf, flags, 4, hipMemcpyDeviceToHost, s));
         MBE_TRY(hipStreamSynchronize(s));

@@ -170,9 +170,8 @@ hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, 
                          int64_t hi, unsigned int *counter, int grid, int waves, hipStream_t s);
 
 // Graph preparation and validation (mbe_prep.hip).
-hipError_t launch_validate(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *off,
-                           const int32_t *adj, const int32_t *t_off, const int32_t *t_adj,
-                           unsigned int *flags, hipStream_t s);
+hipError_t launch_validate(int32_t n_u, int32_t n_v, int32_t n_edges, const int32_t *u_off, const int32_t *u_adj,
+                           const int32_t *v_off, const int32_t *v_adj, unsigned int *flags, hipStream_t s);
 // keys[v] = (deg v << 32) | v for every candidate; also counts candidates per mask class and
 // bounds the local universes (see mbe_prep.hip).
 hipError_t launch_rank_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,

@@ -15,39 +15,55 @@ namespace {
 
 // Offsets: off[0] = 0, non-decreasing, off[n] = n_edges.  Rows: ids in [0, n_cols), strictly
 // ascending.  Transpose: every (r, c) in this CSR appears as (c, r) in the other one (with
-// equal edge counts and duplicate-free rows on both sides this makes them transposes).
-__global__ void validate_kernel(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *off,
-                                const int32_t *adj, const int32_t *t_off, const int32_t *t_adj,
+// equal edge counts and duplicate-free rows on both sides this makes them transposes).  Both
+// directions in one launch (blockIdx.y = 1: the V-side CSR against the U-side one), one
+// thread per offset and one per edge: an edge finds its row by binary search over the
+// offsets (a hub row no longer rests on one thread).  Every read stays in bounds whatever
+// the offsets hold; offsets that break the rules flag the graph whatever the edges say.
+__global__ void validate_kernel(int32_t n_u, int32_t n_v, int32_t n_edges, const int32_t *u_off,
+                                const int32_t *u_adj, const int32_t *v_off, const int32_t *v_adj,
                                 unsigned int *flags) {
+    const bool rev = blockIdx.y == 1;
+    const int32_t n_rows = rev ? n_v : n_u, n_cols = rev ? n_u : n_v;
+    const int32_t *off = rev ? v_off : u_off, *adj = rev ? v_adj : u_adj;
+    const int32_t *t_off = rev ? u_off : v_off, *t_adj = rev ? u_adj : v_adj;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows; r += stride) {
-        const int32_t b = off[r], e = off[r + 1];
-        bool bad = (r == 0 && b != 0) || (r == n_rows - 1 && e != n_edges) || b > e || b < 0 || e > n_edges;
-        if (!bad) {
-            int32_t prev = -1;
-            for (int32_t p = b; p < e && !bad; ++p) {
-                const int32_t cidx = adj[p];
-                if (cidx <= prev || cidx >= n_cols) {
-                    bad = true;
-                    break;
-                }
-                prev = cidx;
-                // binary search r in the transposed row of cidx
-                int32_t lo = t_off[cidx], hi = t_off[cidx + 1];
-                if (lo < 0 || hi > n_edges || lo > hi) {
-                    bad = true;
-                    break;
-                }
-                while (lo < hi) {
-                    const int32_t mid = lo + (hi - lo) / 2;
-                    if (t_adj[mid] < r) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (lo >= t_off[cidx + 1] || t_adj[lo] != r) bad = true;
-            }
-        }
-        if (bad) atomicOr(flags, (unsigned int)FLAG_BAD_GRAPH);
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    for (int64_t r = t0; r <= n_rows; r += stride) {
+        const int32_t o = off[r];
+        if (o < 0 || o > n_edges || (r == 0 && o != 0) || (r == n_rows && o != n_edges) || (r > 0 && off[r - 1] > o))
+            bad = true;
     }
+    for (int64_t p = t0; p < n_edges; p += stride) {
+        // the last row whose first edge is at or before p
+        int32_t lo = 0, hi = n_rows - 1;
+        while (lo < hi) {
+            const int32_t mid = (int32_t)(((int64_t)lo + hi + 1) >> 1);
+            if (off[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t r = lo;
+        const int32_t cidx = adj[p];
+        if (cidx < 0 || cidx >= n_cols) {
+            bad = true;
+            continue;
+        }
+        if (p > 0 && p > off[r] && adj[p - 1] >= cidx) bad = true;  // (same row: ascending)
+        int32_t a = t_off[cidx], b = t_off[cidx + 1];
+        if (a < 0 || b > n_edges || a > b) {
+            bad = true;
+            continue;
+        }
+        const int32_t end = b;
+        while (a < b) {
+            const int32_t mid = a + (b - a) / 2;
+            if (t_adj[mid] < r) a = mid + 1;
+            else b = mid;
+        }
+        if (a >= end || t_adj[a] != r) bad = true;
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, (unsigned int)FLAG_BAD_GRAPH);
 }
 
 // keys[v] = (deg << 32) | v; stats[0] = number of degree-0 vertices, stats[1 + c] = number of
@@ -55,26 +71,46 @@ __global__ void validate_kernel(int32_t n_rows, int32_t n_cols, int32_t n_edges,
 // candidates of the 2-hop walk count sum_{w in N(v)} deg w (bounds a local universe).
 __global__ void rank_keys_kernel(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
                                  unsigned long long *keys, unsigned long long *stats) {
+    // tallied per thread over its candidates, then summed (or maxed) over the wave: one atomic
+    // per wave and statistic instead of one per candidate
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // [0] degree 0, [1 + c] class c (c <= 6)
+    unsigned long long dmax = 0, wmax = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nc; v += stride) {
         const int32_t b = c_off[v], e = c_off[v + 1];
         const uint32_t d = (uint32_t)(e - b);
         keys[v] = ((unsigned long long)d << 32) | (unsigned long long)(uint32_t)v;
         if (d == 0) {
-            atomicAdd(&stats[0], 1ull);
+            ++cnt[0];
         } else {
             int cls = 0;
             while (cls < 6 && d > (64u << cls)) ++cls;
-            atomicAdd(&stats[1 + cls], 1ull);
-            atomicMax(&stats[8], (unsigned long long)d);
+#pragma unroll
+            for (int q = 0; q < 7; ++q)
+                if (q == cls) ++cnt[1 + q];
+            dmax = d > dmax ? d : dmax;
             unsigned long long walks = 0;
             for (int32_t p = b; p < e; ++p) {
                 const int32_t w = c_adj[p];
                 walks += (unsigned long long)(o_off[w + 1] - o_off[w]);
             }
-            atomicMax(&stats[9], walks);
+            wmax = walks > wmax ? walks : wmax;
         }
     }
+    const bool lead = (threadIdx.x & 63) == 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        unsigned long long x = cnt[q];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lead && x) atomicAdd(&stats[q], x);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(dmax, o), z = __shfl_xor(wmax, o);
+        dmax = y > dmax ? y : dmax;
+        wmax = z > wmax ? z : wmax;
+    }
+    if (lead && dmax) atomicMax(&stats[8], dmax);
+    if (lead && wmax) atomicMax(&stats[9], wmax);
 }
 
 __global__ void rank_scatter_kernel(int32_t nc, int32_t nzero, const unsigned long long *sorted,
@@ -157,12 +193,12 @@ int grid_for(int64_t n, int block) {
 
 }  // namespace
 
-hipError_t launch_validate(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *off,
-                           const int32_t *adj, const int32_t *t_off, const int32_t *t_adj,
-                           unsigned int *flags, hipStream_t s) {
-    if (n_rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(validate_kernel, dim3(grid_for(n_rows, 256)), dim3(256), 0, s, n_rows, n_cols,
-                       n_edges, off, adj, t_off, t_adj, flags);
+hipError_t launch_validate(int32_t n_u, int32_t n_v, int32_t n_edges, const int32_t *u_off, const int32_t *u_adj,
+                           const int32_t *v_off, const int32_t *v_adj, unsigned int *flags, hipStream_t s) {
+    if (n_u == 0 || n_v == 0) return hipSuccess;
+    const int64_t work = std::max<int64_t>(n_edges, (int64_t)std::max(n_u, n_v) + 1);
+    hipLaunchKernelGGL(validate_kernel, dim3(grid_for(work, 256), 2), dim3(256), 0, s, n_u, n_v, n_edges, u_off,
+                       u_adj, v_off, v_adj, flags);
     return hipGetLastError();
 }
 

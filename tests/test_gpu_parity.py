@@ -260,6 +260,34 @@ def test_enumerate_small_buffer(mbe, orc):
     assert e.value.result["count"] == want["count"] and e.value.result["out_ints"] == want["out_ints"]
 
 
+_BAD_DEVICE = {
+    # (n_u, n_v, u_off, u_adj, v_off, v_adj); every array has exactly its declared length
+    "valid": (3, 3, [0, 2, 4, 6], [0, 1, 1, 2, 0, 2], [0, 2, 4, 6], [0, 2, 0, 1, 1, 2]),
+    "unsorted": (3, 3, [0, 2, 4, 6], [1, 0, 1, 2, 0, 2], [0, 2, 4, 6], [0, 2, 0, 1, 1, 2]),
+    "duplicate": (3, 3, [0, 2, 4, 6], [0, 0, 1, 2, 0, 2], [0, 2, 4, 6], [0, 2, 0, 1, 1, 2]),
+    "range": (3, 3, [0, 2, 4, 6], [0, 1, 1, 3, 0, 2], [0, 2, 4, 6], [0, 2, 0, 1, 1, 2]),
+    "negative": (3, 3, [0, 2, 4, 6], [-1, 1, 1, 2, 0, 2], [0, 2, 4, 6], [0, 2, 0, 1, 1, 2]),
+    "offsets": (3, 3, [0, 2, 4, 5], [0, 1, 1, 2, 0, 2], [0, 2, 4, 6], [0, 2, 0, 1, 1, 2]),
+    "decreasing": (3, 3, [0, 4, 2, 6], [0, 1, 1, 2, 0, 2], [0, 2, 4, 6], [0, 2, 0, 1, 1, 2]),
+    "transpose": (3, 3, [0, 2, 4, 6], [0, 1, 1, 2, 0, 2], [0, 2, 4, 6], [0, 1, 0, 2, 1, 2]),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_BAD_DEVICE))
+def test_device_graph_validation(mbe, case):
+    import torch
+    nu, nv, uo, ua, vo, va = _BAD_DEVICE[case]
+    _say("device validation", case)
+    dg = gg.BiGraph(nu, nv, *[torch.tensor(a, dtype=torch.int32, device="cuda") for a in (uo, ua, vo, va)])
+    if case == "valid":
+        assert mbe.mbe_count(dg)["count"] == mbe.mbe_count(gg.BiGraph(nu, nv, *[np.array(a, np.int32) for a in
+                                                                              (uo, ua, vo, va)]))["count"]
+        return
+    with pytest.raises(mbe.MbeError) as e:
+        mbe.mbe_count(dg)
+    assert e.value.code == -2, case
+
+
 def test_invalid_device_graph(mbe):
     import torch
     _say("invalid device graph")
