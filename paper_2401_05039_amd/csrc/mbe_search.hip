@@ -1818,9 +1818,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         //    bits holds its bit, and of the other single-bit masks only the first per bit is
         //    kept: a Q entry only witnesses that some R (a subset of N(x)) is not maximal, and
         //    the dropped ones witness nothing the kept ones do not.  The count stays nq0 in
-        //    the tallies of diagnostics mode, which keep the method's full Q1.
+        //    the tallies of diagnostics mode, which keep the method's full Q1.  Lists of up
+        //    to 256 are kept whole: there the pass's workgroup barriers cost more than the
+        //    shorter child lists save (measured).
         uint32_t *ids1 = s1;
-        if (!DIAG && nq0 > 1) {
+        if (!DIAG && nq0 > 256) {
             lds_u32 *first1 = lds_at<lds_u32>(lds_raw, sizeof(WGShared));  // BITS words
             for (int b = tid; b < BITS; b += nt) first1[b] = kNone;
             if (tid < W) sh->cov[tid] = 0ull;
