@@ -255,7 +255,7 @@ def main():
     ap.add_argument("--big-max-u", type=int, default=200_000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the search runs on one GPU (sharding across GPUs is a design only); --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
