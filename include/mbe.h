@@ -113,11 +113,12 @@ typedef struct mbe_result {
  *   grid         workgroups of the persistent search kernel (default: 2 per compute unit).
  *   diagnostics  1: also compute nodes / nonmaximal / max_depth / bytes_alg.
  *   no_validate  1: skip the O(|E|) check of the CSR pair (the caller vouches for it).
- *   steal_k      work sharing below a top-level candidate (the k of section III-D): 2: the
- *                candidates of its child list that need a full node are claimed one at a
- *                time by the owning workgroup's waves and by idle workgroups, which rebuild
- *                the same list; 1: by the owning workgroup only; 3 (default): as 2, and in
- *                the classes of degree above 64 the child lists of
+ *   steal_k      work sharing below a top-level candidate (the k of section III-D): 2
+ *                (default): the candidates of its child list that need a full node are
+ *                claimed one at a time by the owning workgroup's waves and, once a workgroup
+ *                of the launch is idle (the rest of the list then moves to a global slot), by
+ *                idle workgroups, which rebuild the same list; 1: by the owning workgroup
+ *                only; 3: as 2, and in the classes of degree above 64 the child lists of
  *                second-level nodes are shared too: a wave publishes the rest of such a list
  *                (in 64-candidate chunks) once a wave or workgroup is idle, and idle waves of
  *                its workgroup and idle workgroups (after every launch's top-level
@@ -191,7 +192,7 @@ int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_
 /*
  * Autotuner of the batched form: runs mbe_count_batch on the given graphs (a representative
  * sample of the batches to come) under each candidate launch setting -- waves per workgroup
- * in {8, 4, 2} times steal_k in {3, 1} -- starting from base (NULL: defaults), checks that
+ * in {8, 4, 2} times steal_k in {2, 3} -- starting from base (NULL: defaults), checks that
  * every setting gives the same per-graph count and hash, and writes the fastest setting
  * (wall time of the whole call) to *best and its time in milliseconds to *best_ms (may be
  * NULL).  Errors as mbe_count_batch; MBE_ERR_DEVICE if two settings disagree.

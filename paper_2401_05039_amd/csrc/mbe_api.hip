@@ -143,14 +143,14 @@ struct Opts {
 };
 
 Opts read_opts(const mbe_options *o) {
-    Opts r{0, 8, 0, 0, 0, 3, 0, -1, nullptr};
+    Opts r{0, 8, 0, 0, 0, 2, 0, -1, nullptr};
     if (!o) return r;
     r.side = o->side;
     r.waves = o->wg_waves > 0 ? o->wg_waves : 8;
     r.grid = o->grid > 0 ? o->grid : 0;
     r.diag = o->diagnostics != 0;
     r.no_validate = o->no_validate != 0;
-    r.steal_k = o->steal_k == 0 ? 3 : o->steal_k;
+    r.steal_k = o->steal_k == 0 ? 2 : o->steal_k;
     r.root_lo = o->root_lo > 0 ? o->root_lo : 0;
     r.root_hi = o->root_hi > 0 ? o->root_hi : -1;
     r.stream = static_cast<hipStream_t>(o->stream);
@@ -1035,7 +1035,7 @@ int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_
     std::vector<mbe_result> ref((size_t)n), outs((size_t)n);
     // candidates: waves per workgroup x work sharing; the first run also warms the workspace
     static const int kWaves[] = {8, 4, 2};
-    static const int kSteal[] = {3, 1};
+    static const int kSteal[] = {2, 3};
     double bt = 0.0;
     bool have = false;
     for (int wi = 0; wi < 3; ++wi) {

@@ -49,7 +49,8 @@ namespace mbe {
 namespace {
 
 constexpr uint64_t kHashK = 0x9E3779B97F4A7C15ull;
-constexpr uint32_t kShared = 0xFFFFFFFFu;  // frame offset meaning "the workgroup's top-level list"
+constexpr uint32_t kShared = 0xFFFFFFFFu;
+constexpr uint32_t kMovedMark = 1u << 30;  // added to the LDS item counter when the list moves  // frame offset meaning "the workgroup's top-level list"
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kQKeep = 256;      // most incomparable Q' masks a compressed child keeps
 // classes that reduce Q' through the presence word when |R'| <= 6 (the widest class runs out
@@ -1132,7 +1133,9 @@ typedef __attribute__((address_space(3))) WaveShare lds_ws;
 struct WGShared {
     unsigned long long task;
     int s0;
-    int claim;
+    uint32_t claim;     // next top-level item (owner, before the list moves to the steal slot)
+    uint32_t moved;     // 0: items claimed in LDS; 2: moving to the steal slot; 1: moved
+    int published;      // the steal slot holds this task's list
     int nonmax;
     int pcount;
     unsigned long long exps;
@@ -1505,7 +1508,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                 }
                 if (found) break;
                 int wait = 0;
-                if (ln == 0 && k3 && __hip_atomic_load(a.busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u) {
+                if (ln == 0 && (k3 || a.steal_on) &&
+                    __hip_atomic_load(a.busy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u) {
                     wait = 1;
                     if (!sh->others_done) {
 #pragma unroll
@@ -1656,7 +1660,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             sh->hvsum = 0;
             sh->rs1 = 0;
             sh->nexp = 0;
-            sh->claim = 0;
+            sh->claim = 0u;
+            sh->moved = 0u;
+            sh->published = 0;
             sh->gclaim = 0;
         }
         __syncthreads();
@@ -1991,8 +1997,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         __syncthreads();
         const int H = uni(sh->s0);
 
-        // -- share the items: with more than one per wave, claims go through the global steal
-        //    slot so that idle workgroups can take some (they rebuild the same list)
+        // -- share the items.  The owner's waves claim them from an LDS counter; once a
+        //    workgroup of the launch is idle, the wave whose claim notices it moves the rest of
+        //    the list to the global steal slot, and from then on everyone (idle workgroups
+        //    rebuild the same list) claims there.  A thief claims there from the start.
         StealSlot *slot = mode == 2 ? &a.steal[sh->victim] : &a.steal[my_slot];
         if (tid == 0) {
             sh->topf = top;
@@ -2000,21 +2008,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
             sh->tk = (int)k;
             sh->busyw = thief3 ? 0u : (uint32_t)nw;
             sh->idlew = 0u;
-            if (mode == 2) {
-                sh->gclaim = 1;
-            } else if (a.steal_on && H > nw) {
-                slot->g = g;
-                slot->k = (int)k;
-                slot->limit = H;
-                __threadfence();
-                __hip_atomic_store(&slot->word, (unsigned long long)sh->epoch << 32, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                atomicAdd(a.steal_live, 1u);
-                sh->gclaim = 1;
-            }
+            if (mode == 2) sh->gclaim = 1;
         }
         __syncthreads();
-        const bool gclaim = uni(sh->gclaim) != 0;
+        bool gclaim = uni(sh->gclaim) != 0;
+        lds_u32 *claim_l = lds_at<lds_u32>(lds_raw, offsetof(WGShared, claim));
+        lds_u32 *moved_l = lds_at<lds_u32>(lds_raw, offsetof(WGShared, moved));
         const unsigned int epoch = uni(sh->epoch);
         if (DIAG) {
             const uint64_t now = clock64();
@@ -2055,9 +2054,46 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                 int i;
                 if (depth == 0) {
                     if (src_top) {
-                        int got = 0;
-                        if (ln == 0) got = gclaim ? claim_chunk(&slot->word, epoch, H, 1u) : atomicAdd(&sh->claim, 1);
+                        int got = 0, mv = 0;
+                        if (ln == 0) {
+                            if (gclaim) {
+                                got = claim_chunk(&slot->word, epoch, H, 1u);
+                            } else {
+                                const uint32_t t = lds_add32(claim_l, 1u);
+                                got = (int)(t & (kMovedMark - 1u));
+                                if (t >= kMovedMark) {
+                                    // the rest of the list went to the steal slot: wait until it
+                                    // is out (the moving wave is a few stores from done), claim there
+                                    while (__hip_atomic_load(moved_l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 1u)
+                                        __builtin_amdgcn_s_sleep(1);
+                                    got = claim_chunk(&slot->word, epoch, H, 1u);
+                                    mv = 1;
+                                } else if (uint32_t none = 0u;
+                                           a.steal_on && got + 2 < H && (got & 7) == 0 &&
+                                           __hip_atomic_load(a.hungry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0u &&
+                                           __hip_atomic_compare_exchange_strong(moved_l, &none, 2u, __ATOMIC_RELAXED,
+                                                                               __ATOMIC_RELAXED,
+                                                                               __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                                    // a workgroup is idle: move items [rest, H) to the steal slot
+                                    // (this claim keeps item got)
+                                    const uint32_t rest = lds_add32(claim_l, kMovedMark) & (kMovedMark - 1u);
+                                    if ((int)rest < H) {
+                                        slot->g = g;
+                                        slot->k = (int)k;
+                                        slot->limit = H;
+                                        __threadfence();
+                                        __hip_atomic_store(&slot->word, ((unsigned long long)epoch << 32) | rest,
+                                                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                                        atomicAdd(a.steal_live, 1u);
+                                        sh->published = 1;
+                                    }
+                                    __hip_atomic_store(moved_l, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                    mv = 1;
+                                }
+                            }
+                        }
                         got = __builtin_amdgcn_readlane(got, 0);
+                        if (__builtin_amdgcn_readlane(mv, 0)) gclaim = true;
                         if (got < 0 || got >= H) break;
                         i = (int)uni(hpos[got]);
                         if (k3) me->item1 = i;
@@ -2183,7 +2219,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         if (DIAG) t_mark = clock64();  // from here to the next task: waiting
         __syncthreads();
         // every chunk is claimed: withdraw the list (thieves still finish the chunks they hold)
-        if (tid == 0 && gclaim && !thief) {
+        if (tid == 0 && sh->published) {
             __hip_atomic_store(&slot->word, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             atomicSub(a.steal_live, 1u);
         }

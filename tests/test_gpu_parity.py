@@ -371,7 +371,7 @@ def test_tuner_picks_a_setting_with_equal_results(mbe):
     _say("tuner", len(gs))
     base = mbe.mbe_count_batch(gs)
     tuned, ms = mbe.mbe_tune_batch(gs)
-    assert tuned.wg_waves in (2, 4, 8) and tuned.steal_k in (1, 3) and ms > 0
+    assert tuned.wg_waves in (2, 4, 8) and tuned.steal_k in (2, 3) and ms > 0
     res = mbe.mbe_count_batch(gs, tuned)
     assert [(r["count"], r["hash"]) for r in res] == [(r["count"], r["hash"]) for r in base]
 
