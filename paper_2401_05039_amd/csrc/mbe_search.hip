@@ -1252,6 +1252,25 @@ __device__ __forceinline__ void block_popcount_prefix(const uint64_t *bitmap, ui
     __syncthreads();
 }
 
+// Moves the unclaimed rest [r, H) of the workgroup's top-level item list to its steal slot
+// and marks the LDS item counter, so later claims go to the slot.  Lane 0 of the one wave that
+// set the move flag from 0 to 2 calls it; the flag becomes 1 once the slot is out.
+__device__ __forceinline__ void move_top_list(const SearchArgs &a, WGShared *sh, StealSlot *slot, lds_u32 *claim_l,
+                                              lds_u32 *moved_l, int g, int k, int H, unsigned int epoch) {
+    const uint32_t rest = lds_add32(claim_l, kMovedMark) & (kMovedMark - 1u);
+    if ((int)rest < H) {
+        slot->g = g;
+        slot->k = k;
+        slot->limit = H;
+        __threadfence();
+        __hip_atomic_store(&slot->word, ((unsigned long long)epoch << 32) | rest, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(a.steal_live, 1u);
+        sh->published = 1;
+    }
+    __hip_atomic_store(moved_l, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // A wave without work looks for a published third-level list with a chunk left -- the one its
 // workgroup took (thief3), else one published by a wave of its workgroup -- and claims a
 // chunk.  On success the claim and the list are left in the wave's share record (the list
@@ -2074,20 +2093,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                                            __hip_atomic_compare_exchange_strong(moved_l, &none, 2u, __ATOMIC_RELAXED,
                                                                                __ATOMIC_RELAXED,
                                                                                __HIP_MEMORY_SCOPE_WORKGROUP)) {
-                                    // a workgroup is idle: move items [rest, H) to the steal slot
-                                    // (this claim keeps item got)
-                                    const uint32_t rest = lds_add32(claim_l, kMovedMark) & (kMovedMark - 1u);
-                                    if ((int)rest < H) {
-                                        slot->g = g;
-                                        slot->k = (int)k;
-                                        slot->limit = H;
-                                        __threadfence();
-                                        __hip_atomic_store(&slot->word, ((unsigned long long)epoch << 32) | rest,
-                                                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                                        atomicAdd(a.steal_live, 1u);
-                                        sh->published = 1;
-                                    }
-                                    __hip_atomic_store(moved_l, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                    // a workgroup is idle: move the rest of the list to the steal
+                                    // slot (this claim keeps item got)
+                                    move_top_list(a, sh, slot, claim_l, moved_l, g, (int)k, H, epoch);
                                     mv = 1;
                                 }
                             }
@@ -2106,8 +2114,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                 } else {
                     if (cur.heavy == 0ull) {
                         int base = cur.chunk + 64;
-                        if (k3 && depth == 1) {
-                            if (uni(me->cdepth) == 1) {
+                        if (kShare3 && a.steal_on && depth == 1) {
+                            if (k3 && uni(me->cdepth) == 1) {
                                 int got = uni(me->pend);
                                 me->pend = -1;
                                 if (got < 0) {
@@ -2131,35 +2139,54 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                                     me->cown = 0;
                                     me->cdepth = -1;
                                 }
-                            } else if (src_top && cur.n - base > 64 && [&] {
-                                           const bool want = uni(hungry_seen) > 0u;
-                                           hungry_seen = __hip_atomic_load(a.hungry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                           return want;
-                                       }()) {
-                                // publish the rest of this list, then claim its chunks like a helper
-                                const int idx = my_slot * a.pubw + wid;
-                                const int lim = (cur.n - base + 63) >> 6;
-                                if (ln == 0) {
-                                    PubSlot *mp = &a.pub[idx];
-                                    const unsigned int e = atomicAdd(a.epoch_ctr, 1u) + 1u;
-                                    mp->g = sh->tg;
-                                    mp->k = sh->tk;
-                                    mp->i1 = me->item1;
-                                    mp->first = base;
-                                    mp->limit = lim;
-                                    __threadfence();
-                                    __hip_atomic_store(&mp->word, (unsigned long long)e << 32, __ATOMIC_RELEASE,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                                    atomicAdd(a.pub_live, 1u);
-                                    lds_add32(npub, 1u);
-                                    me->cepoch = e;
+                            } else if (src_top) {
+                                // idle workgroups of this launch, as read at the previous check
+                                // (the load is issued one check ahead: its latency hides under
+                                // the chunk in between)
+                                const bool want = uni(hungry_seen) > 0u;
+                                hungry_seen = __hip_atomic_load(a.hungry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                if (want) {
+                                    // the top-level list goes out first (its items are the coarser
+                                    // work): the owner's next top-level claim may be far off when
+                                    // second-level subtrees are large
+                                    // (the owning workgroup's list only: a thief's slot is its victim's)
+                                    if (ln == 0 && mode == 1 &&
+                                        __hip_atomic_load(moved_l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u &&
+                                        (int)(__hip_atomic_load(claim_l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) &
+                                              (kMovedMark - 1u)) + 1 < H) {
+                                        uint32_t none = 0u;
+                                        if (__hip_atomic_compare_exchange_strong(moved_l, &none, 2u, __ATOMIC_RELAXED,
+                                                                                 __ATOMIC_RELAXED,
+                                                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+                                            move_top_list(a, sh, slot, claim_l, moved_l, g, (int)k, H, epoch);
+                                    }
+                                    if (k3 && cur.n - base > 64) {
+                                        // publish the rest of this list, then claim its chunks like a helper
+                                        const int idx = my_slot * a.pubw + wid;
+                                        const int lim = (cur.n - base + 63) >> 6;
+                                        if (ln == 0) {
+                                            PubSlot *mp = &a.pub[idx];
+                                            const unsigned int e = atomicAdd(a.epoch_ctr, 1u) + 1u;
+                                            mp->g = sh->tg;
+                                            mp->k = sh->tk;
+                                            mp->i1 = me->item1;
+                                            mp->first = base;
+                                            mp->limit = lim;
+                                            __threadfence();
+                                            __hip_atomic_store(&mp->word, (unsigned long long)e << 32, __ATOMIC_RELEASE,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                                            atomicAdd(a.pub_live, 1u);
+                                            lds_add32(npub, 1u);
+                                            me->cepoch = e;
+                                        }
+                                        me->cidx = idx;
+                                        me->cfirst = base;
+                                        me->climit = lim;
+                                        me->cdepth = 1;
+                                        me->cown = 1;
+                                        continue;
+                                    }
                                 }
-                                me->cidx = idx;
-                                me->cfirst = base;
-                                me->climit = lim;
-                                me->cdepth = 1;
-                                me->cown = 1;
-                                continue;
                             }
                         }
                         if (base >= cur.n) {
