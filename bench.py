@@ -24,8 +24,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # HBM bytes moved by the search launches of one power-law step, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters scaled by a 1 GiB reference copy (profiles/search_kernel_powerlaw_100k_50k.md),
 # taken on the kernel source with this sha256; reported only while the source is unchanged.
-MEASURED_TRAFFIC = {"source_sha256": "a56d6dee266eb6ed15c5e8a579f029bc9c903bc667be444428f3088a43b963ed",
-                    "bytes_per_step": 3.555e10}
+MEASURED_TRAFFIC = {"source_sha256": "7f2790169b8db1afc4001a3f39768bdcf2f20a98b10e1e61c791c4572a570868",
+                    "bytes_per_step": 3.466e10}
 
 
 def log(*a):
