@@ -76,6 +76,10 @@ def _load():
             lib.orc_hash_pair.restype = ctypes.c_uint64
             lib.orc_mix64.argtypes = [ctypes.c_uint64]
             lib.orc_mix64.restype = ctypes.c_uint64
+            lib.orc_hash_u.argtypes = [ctypes.c_int32]
+            lib.orc_hash_u.restype = ctypes.c_uint64
+            lib.orc_hash_v.argtypes = [ctypes.c_int32]
+            lib.orc_hash_v.restype = ctypes.c_uint64
             _lib = lib
     return _lib
 
@@ -91,6 +95,16 @@ def _arrays(g):
 def mix64(z: int) -> int:
     """SplitMix64 output function, as the oracle computes it."""
     return int(_load().orc_mix64(ctypes.c_uint64(z & MASK64)))
+
+
+def hash_u(a: int) -> int:
+    """hu(a), the term of vertex a of U in a biclique's hash."""
+    return int(_load().orc_hash_u(int(a)))
+
+
+def hash_v(b: int) -> int:
+    """hv(b), the term of vertex b of V in a biclique's hash."""
+    return int(_load().orc_hash_v(int(b)))
 
 
 def hash_pair(a: Sequence[int], b: Sequence[int]) -> int:

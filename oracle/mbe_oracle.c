@@ -62,6 +62,11 @@ uint64_t orc_mix64(uint64_t z) { return orc_mix(z); }
 static uint64_t orc_hu(int32_t a) { return orc_mix(ORC_K * (2ULL * (uint64_t)a + 1ULL)); }
 static uint64_t orc_hv(int32_t b) { return orc_mix(ORC_K * (2ULL * (uint64_t)b + 2ULL)); }
 
+/* The per-vertex terms, exported so that tests can pin them against the published SplitMix64
+ * outputs: hu(a) is output 2a+1 and hv(b) output 2b+2 of the generator started from state 0. */
+uint64_t orc_hash_u(int32_t a) { return orc_hu(a); }
+uint64_t orc_hash_v(int32_t b) { return orc_hv(b); }
+
 /* h(A, B) = mix(sum hu(A) + mix(sum hv(B) + K)); A in U, B in V (caller orientation). */
 uint64_t orc_hash_pair(const int32_t *a, int64_t na, const int32_t *b, int64_t nb) {
     uint64_t sa = 0, sb = 0;
