@@ -37,6 +37,7 @@ extern "C" {
 #define MBE_ERR_OUT_OF_MEMORY    -4  /* device allocation failed */
 #define MBE_ERR_DEVICE           -5  /* a HIP runtime call failed */
 #define MBE_ERR_UNSUPPORTED      -6  /* a top-level candidate's degree exceeds MBE_MAX_DEGREE */
+#define MBE_ERR_SCRATCH_LIMIT    -7  /* mbe_count_noalloc: the call does not fit the fixed scratch */
 
 /* Largest degree a top-level candidate may have: its neighbour set is held as a bit mask of
  * at most this many bits. */
@@ -165,6 +166,33 @@ int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out);
  * bytes is NULL.  An empty side or zero edges gives 0.
  */
 int mbe_workspace_size(const mbe_graph *g, const mbe_options *opt, size_t *bytes);
+
+/*
+ * For callers that cannot allocate device memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: mbe_count without any allocation.  The
+ * result is the one mbe_count returns.  Every device buffer of the call (graph copy for host
+ * graphs, ranking arrays and sort temporaries, search arena, sharing slots, accumulators) is
+ * carved from a fixed scratch array of MBE_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device it runs on until the process ends; the call makes no hipMalloc or hipFree and
+ * no allocating library call.  Set-up, once per device at the first such call there (that
+ * device current): the address of the device's scratch copy is looked up, and the library's
+ * per-device timing events are created.
+ *   - The caller passes the graph (host or device arrays, as for mbe_count) and out.
+ *   - The mask-width class launches run one after another on opt->stream, and the search grid
+ *     is cut down to the arena slots that fit in the scratch (results do not depend on it).
+ *   - A call that would need more than the scratch holds (even one arena slot, or the
+ *     ranking arrays) returns MBE_ERR_SCRATCH_LIMIT.  Roughly: the ranking needs
+ *     ~40 bytes per candidate-side vertex, and one arena slot ~ (8 W + 40) bytes per vertex of
+ *     the largest 2-hop neighbourhood plus ~ 8 waves x (16 bytes per such vertex + 64 KiB).
+ *   - The scratch keeps the last call's contents; each call clears what must start at zero.
+ *     Calls on one device are serialised by the library's per-device lock, so two calls never
+ *     use the scratch at once; work the caller enqueues on the stream meanwhile must not
+ *     touch it either.
+ *   - mbe_enumerate, the batched form and the server have no such variant.
+ * Errors as mbe_count, plus MBE_ERR_SCRATCH_LIMIT.
+ */
+#define MBE_NOALLOC_SCRATCH_BYTES (256u << 20)
+int mbe_count_noalloc(const mbe_graph *g, const mbe_options *opt, mbe_result *out);
 
 /*
  * As mbe_count, and also write the bicliques to buf as records

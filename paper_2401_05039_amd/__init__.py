@@ -17,7 +17,7 @@ from typing import Any, Dict, List, Optional, Tuple
 
 import numpy as np
 
-__all__ = ["mbe_count", "mbe_count_batch", "mbe_enumerate", "mbe_strerror", "mbe_version", "MbeError",
+__all__ = ["mbe_count", "mbe_count_noalloc", "mbe_count_batch", "mbe_enumerate", "mbe_strerror", "mbe_version", "MbeError",
            "Options", "Server", "lib_path", "load"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,6 +31,8 @@ MBE_ERR_BUFFER_TOO_SMALL = -3
 MBE_ERR_OUT_OF_MEMORY = -4
 MBE_ERR_DEVICE = -5
 MBE_ERR_UNSUPPORTED = -6
+MBE_ERR_SCRATCH_LIMIT = -7
+MBE_NOALLOC_SCRATCH_BYTES = 256 << 20
 MBE_MAX_DEGREE = 1024
 
 
@@ -97,6 +99,8 @@ def load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.mbe_count.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
     lib.mbe_count.restype = ctypes.c_int
+    lib.mbe_count_noalloc.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
+    lib.mbe_count_noalloc.restype = ctypes.c_int
     lib.mbe_workspace_size.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]
     lib.mbe_workspace_size.restype = ctypes.c_int
     lib.mbe_enumerate.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result),
@@ -188,6 +192,20 @@ def mbe_count(g, opt: Optional[Options] = None) -> Dict[str, Any]:
     co = _marshal_opts(opt, bool(cg.on_device))
     res = _Result()
     rc = lib.mbe_count(ctypes.byref(cg), ctypes.byref(co), ctypes.byref(res))
+    if rc != MBE_OK:
+        raise MbeError(rc, _result_dict(res))
+    return _result_dict(res)
+
+
+def mbe_count_noalloc(g, opt: Optional[Options] = None) -> Dict[str, Any]:
+    """``mbe_count`` without any device allocation: the call's buffers come from the library's
+    fixed per-device scratch (``MBE_NOALLOC_SCRATCH_BYTES``); raises MbeError with
+    ``MBE_ERR_SCRATCH_LIMIT`` when the graph needs more."""
+    lib = load()
+    cg, keep = _marshal_graph(g)
+    co = _marshal_opts(opt, bool(cg.on_device))
+    res = _Result()
+    rc = lib.mbe_count_noalloc(ctypes.byref(cg), ctypes.byref(co), ctypes.byref(res))
     if rc != MBE_OK:
         raise MbeError(rc, _result_dict(res))
     return _result_dict(res)

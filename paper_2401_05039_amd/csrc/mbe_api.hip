@@ -67,6 +67,9 @@ struct DeviceState {
     // later calls start there instead of repeating a launch that runs out
     int64_t scap_floor = 0;
     int32_t depth_floor = 0;
+    // device address of this device's copy of the no-allocation scratch (set up on the first
+    // mbe_count_noalloc call on the device)
+    char *scratch = nullptr;
 };
 
 hipError_t ensure_class_streams(DeviceState *st) {
@@ -101,6 +104,26 @@ DeviceState *state_for(int dev) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Fixed device scratch of mbe_count_noalloc, for callers that cannot allocate.  Each device
+// that runs the library holds its own copy until the process ends.  In host code the name
+// `scratch` is not a device address: the address of a device's copy comes from
+// hipGetSymbolAddress, taken once per device (DeviceState::scratch), and only that address is
+// handed to kernels and copies.
+constexpr size_t kScratchBytes = (size_t)MBE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The device memory of one call handed out in order from a fixed region (the scratch).
+struct FixedRegion {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    void *take(size_t bytes, size_t align = 256) {
+        const size_t at = align_up(used, align);
+        if (at > cap || bytes > cap - at) return nullptr;
+        used = at + bytes;
+        return base + at;
+    }
+};
+
 int map_err(hipError_t e) {
     if (e == hipSuccess) return MBE_OK;
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return MBE_ERR_OUT_OF_MEMORY;
@@ -111,6 +134,12 @@ int map_err(hipError_t e) {
     do {                                               \
         hipError_t _e = (expr);                        \
         if (_e != hipSuccess) return map_err(_e);      \
+    } while (0)
+
+#define MBE_CALL(expr)                                 \
+    do {                                               \
+        const int _r = (expr);                         \
+        if (_r != MBE_OK) return _r;                   \
     } while (0)
 
 // Host-side check of one CSR direction against its transpose (same rules as the device
@@ -160,15 +189,16 @@ Opts read_opts(const mbe_options *o) {
 int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
                bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
-               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts);
+               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx);
 
 size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi, bool diag,
                         bool enumerate, int grid, int waves);
 
 // mbe_count / mbe_enumerate; with ws_out, only the preparation runs and *ws_out receives the
-// device bytes the search of this call would hold
+// device bytes the search of this call would hold; with fixed (mbe_count_noalloc), every
+// device buffer of the call is carved from the device's scratch and nothing is allocated
 int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t *ubuf, uint64_t ucap_ints,
-        int ubuf_on_device, bool enumerate, size_t *ws_out = nullptr) {
+        int ubuf_on_device, bool enumerate, size_t *ws_out = nullptr, bool fixed = false) {
     if (!g || !out) return MBE_ERR_INVALID_ARG;
     std::memset(out, 0, sizeof(*out));
     if (g->n_u < 0 || g->n_v < 0 || g->n_edges < 0) return MBE_ERR_INVALID_ARG;
@@ -199,14 +229,44 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     std::lock_guard<std::mutex> lk(st->mu);
     hipStream_t s = opt.stream;
 
+    FixedRegion fxr, *fx = nullptr;
+    if (fixed) {
+        if (enumerate || ws_out) return MBE_ERR_INVALID_ARG;
+        if (!st->scratch) {
+            // set-up, once per device (this device is current): the address of its copy
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return map_err(e);
+            if (!p) return MBE_ERR_DEVICE;
+            st->scratch = static_cast<char *>(p);
+        }
+        fxr.base = st->scratch;
+        fxr.cap = kScratchBytes;
+        fx = &fxr;
+    }
+    // a buffer of the call: the device's cached buffer b (grown when needed), or a piece of
+    // the scratch
+    auto mem = [&](DevBuf &b, size_t bytes, char **p) -> int {
+        if (fx) {
+            *p = static_cast<char *>(fx->take(bytes));
+            return *p ? MBE_OK : MBE_ERR_SCRATCH_LIMIT;
+        }
+        const hipError_t e = b.ensure(bytes);
+        if (e != hipSuccess) return map_err(e);
+        *p = b.as<char>();
+        return MBE_OK;
+    };
+
     const int32_t nu = g->n_u, nv = g->n_v, ne = g->n_edges;
     const int32_t *u_off = g->u_off, *u_adj = g->u_adj, *v_off = g->v_off, *v_adj = g->v_adj;
     if (!g->on_device) {
         const size_t b_uoff = align_up(((size_t)nu + 1) * 4, 256), b_voff = align_up(((size_t)nv + 1) * 4, 256);
         const size_t b_adj = align_up((size_t)ne * 4, 256);
-        MBE_TRY(st->graph.ensure(b_uoff + b_voff + 2 * b_adj));
-        int32_t *d_uoff = st->graph.as<int32_t>(0), *d_voff = st->graph.as<int32_t>(b_uoff);
-        int32_t *d_uadj = st->graph.as<int32_t>(b_uoff + b_voff), *d_vadj = st->graph.as<int32_t>(b_uoff + b_voff + b_adj);
+        char *gb = nullptr;
+        MBE_CALL(mem(st->graph, b_uoff + b_voff + 2 * b_adj, &gb));
+        int32_t *d_uoff = reinterpret_cast<int32_t *>(gb), *d_voff = reinterpret_cast<int32_t *>(gb + b_uoff);
+        int32_t *d_uadj = reinterpret_cast<int32_t *>(gb + b_uoff + b_voff);
+        int32_t *d_vadj = reinterpret_cast<int32_t *>(gb + b_uoff + b_voff + b_adj);
         MBE_TRY(hipMemcpyAsync(d_uoff, u_off, ((size_t)nu + 1) * 4, hipMemcpyHostToDevice, s));
         MBE_TRY(hipMemcpyAsync(d_voff, v_off, ((size_t)nv + 1) * 4, hipMemcpyHostToDevice, s));
         MBE_TRY(hipMemcpyAsync(d_uadj, u_adj, (size_t)ne * 4, hipMemcpyHostToDevice, s));
@@ -219,13 +279,14 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
 
     // small device block: acc[16] | flags | counters[8] + live steal slots[8] + third-level
     // sharing counters[48] | stats[16]
-    MBE_TRY(st->small.ensure(4096));
-    unsigned long long *acc = st->small.as<unsigned long long>(0);
-    unsigned int *flags = st->small.as<unsigned int>(256);
-    unsigned long long *stats = st->small.as<unsigned long long>(1024);
+    char *small = nullptr;
+    MBE_CALL(mem(st->small, 4096, &small));
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(small);
+    unsigned int *flags = reinterpret_cast<unsigned int *>(small + 256);
+    unsigned long long *stats = reinterpret_cast<unsigned long long *>(small + 1024);
 
     if (!opt.no_validate && g->on_device) {
-        MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
+        MBE_TRY(launch_zero(flags, 4, s));
         MBE_TRY(launch_validate(nu, nv, ne, u_off, u_adj, v_off, v_adj, flags, s));
         unsigned int hf = 0;
         MBE_TRY(hipMemcpyAsync(&hf, flags, 4, hipMemcpyDeviceToHost, s));
@@ -240,20 +301,22 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
 
     // rank the candidates by (degree, id)
     const size_t b_keys = align_up((size_t)nc * 8, 256), b_i32 = align_up((size_t)nc * 4, 256);
-    MBE_TRY(st->prep.ensure(2 * b_keys + 2 * b_i32));
-    unsigned long long *keys = st->prep.as<unsigned long long>(0);
-    unsigned long long *sorted = st->prep.as<unsigned long long>(b_keys);
-    int32_t *order = st->prep.as<int32_t>(2 * b_keys);
-    int32_t *rank = st->prep.as<int32_t>(2 * b_keys + b_i32);
-    MBE_TRY(hipMemsetAsync(stats, 0, 16 * 8, s));
+    char *pb = nullptr;
+    MBE_CALL(mem(st->prep, 2 * b_keys + 2 * b_i32, &pb));
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(pb);
+    unsigned long long *sorted = reinterpret_cast<unsigned long long *>(pb + b_keys);
+    int32_t *order = reinterpret_cast<int32_t *>(pb + 2 * b_keys);
+    int32_t *rank = reinterpret_cast<int32_t *>(pb + 2 * b_keys + b_i32);
+    MBE_TRY(launch_zero(stats, 16 * 8, s));
     MBE_TRY(launch_rank_keys(nc, c_off, c_adj, o_off, keys, stats, s));
     int end_bit = 32;
     while (end_bit < 64 && ((unsigned long long)no >> (end_bit - 32)) != 0ull) ++end_bit;
     size_t tmp_bytes = 0;
     MBE_TRY(radix_sort_u64(nullptr, &tmp_bytes, keys, sorted, nc, end_bit, s));
-    MBE_TRY(st->sort_tmp.ensure(tmp_bytes));
-    tmp_bytes = st->sort_tmp.bytes;
-    MBE_TRY(radix_sort_u64(st->sort_tmp.p, &tmp_bytes, keys, sorted, nc, end_bit, s));
+    char *tb = nullptr;
+    MBE_CALL(mem(st->sort_tmp, tmp_bytes, &tb));
+    if (!fx) tmp_bytes = st->sort_tmp.bytes;
+    MBE_TRY(radix_sort_u64(tb, &tmp_bytes, keys, sorted, nc, end_bit, s));
     unsigned long long hstats[16];
     MBE_TRY(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
     MBE_TRY(hipStreamSynchronize(s));
@@ -319,7 +382,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     gd.c_is_v = c_is_v ? 1 : 0;
     gd.cbase = 0;
     gd.obase = 0;
-    GraphDesc *d_gd = st->small.as<GraphDesc>(2048);
+    GraphDesc *d_gd = reinterpret_cast<GraphDesc *>(small + 2048);
     MBE_TRY(hipMemcpyAsync(d_gd, &gd, sizeof(gd), hipMemcpyHostToDevice, s));
 
     SearchArgs a{};
@@ -350,7 +413,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     {
         int attempts = 0;
         const int rc = run_search(st, a, dims, cls_a, cls_b, opt.diag, enumerate, grid, waves, acc, ACC_SLOTS * 8, hacc,
-                                  &hflags, &ms, s, nullptr, 0, &attempts);
+                                  &hflags, &ms, s, nullptr, 0, &attempts, small, fx);
         out->attempts = (uint32_t)attempts;
         if (rc != MBE_OK) return rc;
     }
@@ -431,47 +494,72 @@ size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo,
 int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
                bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
-               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts) {
+               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx) {
     dims.scap = std::max<int64_t>(dims.scap, st->scap_floor);
     dims.maxdepth = std::max<int32_t>(dims.maxdepth, st->depth_floor);
     unsigned int *flags = a.flags;
-    unsigned int *counters = st->small.as<unsigned int>(512);
+    unsigned int *counters = reinterpret_cast<unsigned int *>(small + 512);
     unsigned int hflags = 0;
-    MBE_TRY(ensure_class_streams(st));
+    // the fixed-memory form runs the classes one after another on the caller's stream (it
+    // creates no streams of its own)
+    if (!fx) MBE_TRY(ensure_class_streams(st));
     // persistent grids: as many workgroups per class as fit on the device at once (unless the
     // caller fixed the grid); the arena has one slot per workgroup that can be resident
     int cls_grid[5], cls_res[5];
-    bool sequential = false;
+    bool sequential = fx != nullptr;
+    const size_t mark = fx ? fx->used : 0;
     for (int attempt = 0;; ++attempt) {
-        const int nslots = search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, sequential, cls_grid, cls_res);
+        int nslots = search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, sequential, cls_grid, cls_res);
         a.dims = dims;
         a.lay = search_layout(dims);
+        // per arena slot: its busy flag, and per class one top-level and `waves` third-level
+        // sharing slots
+        const size_t share_per_slot = sizeof(StealSlot) * 5 + sizeof(PubSlot) * (size_t)waves * 5;
+        char *share = nullptr;
+        if (fx) {
+            // as many arena slots as fit in what the call has left of the scratch
+            fx->used = mark;
+            const size_t start = align_up(mark, 4096), slack = 2 * 4096;
+            const size_t left = fx->cap > start + slack ? fx->cap - start - slack : 0;
+            const size_t per_slot = a.lay.wg_bytes + sizeof(unsigned int) + share_per_slot;
+            const int64_t fit = (int64_t)(left / per_slot);
+            if (fit < 1) return MBE_ERR_SCRATCH_LIMIT;
+            nslots = (int)std::min<int64_t>(nslots, fit);
+            a.arena = static_cast<char *>(fx->take(a.lay.wg_bytes * (size_t)nslots, 4096));
+            a.slot_busy = static_cast<unsigned int *>(fx->take(sizeof(unsigned int) * (size_t)nslots));
+            share = static_cast<char *>(fx->take(share_per_slot * (size_t)nslots));
+            if (!a.arena || !a.slot_busy || !share) return MBE_ERR_SCRATCH_LIMIT;
+            // the scratch holds whatever the last call left there
+            MBE_TRY(launch_zero(a.arena, a.lay.wg_bytes * (size_t)nslots, s));
+        } else {
+            MBE_TRY(st->arena.ensure(a.lay.wg_bytes * (size_t)nslots));
+            a.arena = st->arena.as<char>();
+            // kernels keep their scratch bitmaps zero between uses; new memory starts zero too
+            if (st->arena.fresh) MBE_TRY(launch_zero(st->arena.p, st->arena.bytes, s));
+            MBE_TRY(st->slots.ensure(sizeof(unsigned int) * (size_t)nslots));
+            a.slot_busy = st->slots.as<unsigned int>();
+            MBE_TRY(st->steal.ensure(share_per_slot * (size_t)nslots));
+            share = st->steal.as<char>();
+        }
         a.nslots = nslots;
-        MBE_TRY(st->arena.ensure(a.lay.wg_bytes * (size_t)nslots));
-        a.arena = st->arena.as<char>();
-        // kernels keep their scratch bitmaps zero between uses; new memory starts zero too
-        if (st->arena.fresh) MBE_TRY(hipMemsetAsync(st->arena.p, 0, st->arena.bytes, s));
-        MBE_TRY(st->slots.ensure(sizeof(unsigned int) * (size_t)nslots));
-        a.slot_busy = st->slots.as<unsigned int>();
         // per class: nslots top-level slots, then nslots * waves third-level slots
         const size_t steal_bytes = sizeof(StealSlot) * (size_t)nslots * 5;
         const size_t pub_bytes = sizeof(PubSlot) * (size_t)nslots * (size_t)waves * 5;
-        MBE_TRY(st->steal.ensure(steal_bytes + pub_bytes));
-        MBE_TRY(hipMemset2DAsync(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, 0, (size_t)dims.nwords * 8, (size_t)nslots, s));
-        MBE_TRY(hipMemsetAsync(a.slot_busy, 0, sizeof(unsigned int) * (size_t)nslots, s));
-        MBE_TRY(hipMemsetAsync(st->steal.p, 0, steal_bytes + (a.k3 ? pub_bytes : 0), s));
-        MBE_TRY(hipMemsetAsync(run_acc, 0, run_acc_bytes, s));
-        if (graph_acc && graph_acc != run_acc) MBE_TRY(hipMemsetAsync(graph_acc, 0, graph_acc_bytes, s));
-        MBE_TRY(hipMemsetAsync(flags, 0, 4, s));
-        MBE_TRY(hipMemsetAsync(counters, 0, 64 * 4, s));
+        MBE_TRY(launch_zero_2d(a.arena + a.lay.off_bitmap, a.lay.wg_bytes, (size_t)dims.nwords * 8, (size_t)nslots, s));
+        MBE_TRY(launch_zero(a.slot_busy, sizeof(unsigned int) * (size_t)nslots, s));
+        MBE_TRY(launch_zero(share, steal_bytes + (a.k3 ? pub_bytes : 0), s));
+        MBE_TRY(launch_zero(run_acc, run_acc_bytes, s));
+        if (graph_acc && graph_acc != run_acc) MBE_TRY(launch_zero(graph_acc, graph_acc_bytes, s));
+        MBE_TRY(launch_zero(flags, 4, s));
+        MBE_TRY(launch_zero(counters, 64 * 4, s));
         MBE_TRY(hipEventRecord(st->ev0, s));
         if (!sequential) MBE_TRY(hipEventRecord(st->fork, s));
         for (int c = 4; c >= 0; --c) {
             if (cls_lo[c] >= cls_hi[c]) continue;
             SearchArgs ac = a;
-            ac.steal = st->steal.as<StealSlot>() + (size_t)c * nslots;
+            ac.steal = reinterpret_cast<StealSlot *>(share) + (size_t)c * nslots;
             ac.steal_live = counters + 8 + c;
-            ac.pub = st->steal.as<PubSlot>(steal_bytes) + (size_t)c * nslots * (size_t)waves;
+            ac.pub = reinterpret_cast<PubSlot *>(share + steal_bytes) + (size_t)c * nslots * (size_t)waves;
             ac.pubw = waves;
             ac.pub_live = counters + 16 + c;
             ac.busy = counters + 24 + c;
@@ -485,7 +573,9 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
                 cs = st->cls_stream[c];
                 MBE_TRY(hipStreamWaitEvent(cs, st->fork, 0));
             }
-            MBE_TRY(launch_search(ac, 1 << c, diag, enumerate, cls_lo[c], cls_hi[c], counters + c, cls_grid[c], waves, cs));
+            // (with fixed memory the grid is at most the slots that fit)
+            const int gsz = fx ? std::min(cls_grid[c], nslots) : cls_grid[c];
+            MBE_TRY(launch_search(ac, 1 << c, diag, enumerate, cls_lo[c], cls_hi[c], counters + c, gsz, waves, cs));
             if (!sequential) {
                 MBE_TRY(hipEventRecord(st->join[c], cs));
                 MBE_TRY(hipStreamWaitEvent(s, st->join[c], 0));
@@ -668,8 +758,8 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     unsigned int *flags = st->small.as<unsigned int>(256);
     unsigned long long *stats = st->small.as<unsigned long long>(1024);
     MBE_TRY(hipMemcpyAsync(d_tb, tb.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
-    MBE_TRY(hipMemsetAsync(gstats, 0, (size_t)n * 16, s));
-    MBE_TRY(hipMemsetAsync(stats, 0, 16 * 8, s));
+    MBE_TRY(launch_zero(gstats, (size_t)n * 16, s));
+    MBE_TRY(launch_zero(stats, 16 * 8, s));
     MBE_TRY(launch_batch_keys((int32_t)NC, d_coff, d_cadj, d_ooff, d_gof, d_cb, keys, gstats, stats, s));
     int end_bit = 32;
     while (end_bit < 64 && ((unsigned long long)max_no >> (end_bit - 32)) != 0ull) ++end_bit;
@@ -741,7 +831,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     float ms = 0.f;
     int attempts = 0;
     int rc = run_search(st, a, dims, cls_lo, cls_hi, opt.diag, false, grid, opt.waves, acc, ACC_SLOTS * 8, hacc, &hflags,
-                        &ms, s, gacc, (size_t)n * ACC_SLOTS * 8, &attempts);
+                        &ms, s, gacc, (size_t)n * ACC_SLOTS * 8, &attempts, st->small.as<char>(), nullptr);
     if (rc != MBE_OK) return rc;
     std::vector<unsigned long long> hga((size_t)n * ACC_SLOTS);
     MBE_TRY(hipMemcpyAsync(hga.data(), gacc, hga.size() * 8, hipMemcpyDeviceToHost, s));
@@ -1071,6 +1161,10 @@ int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out) {
     return run(g, opt, out, nullptr, 0, 0, false);
 }
 
+int mbe_count_noalloc(const mbe_graph *g, const mbe_options *opt, mbe_result *out) {
+    return run(g, opt, out, nullptr, 0, 0, false, nullptr, true);
+}
+
 int mbe_workspace_size(const mbe_graph *g, const mbe_options *opt, size_t *bytes) {
     if (!bytes) return MBE_ERR_INVALID_ARG;
     *bytes = 0;
@@ -1092,6 +1186,7 @@ const char *mbe_strerror(int code) {
         case MBE_ERR_OUT_OF_MEMORY: return "out of device memory";
         case MBE_ERR_DEVICE: return "HIP runtime error";
         case MBE_ERR_UNSUPPORTED: return "candidate degree above MBE_MAX_DEGREE";
+        case MBE_ERR_SCRATCH_LIMIT: return "the call needs more device memory than the fixed scratch of mbe_count_noalloc";
         default: return "unknown error";
     }
 }

@@ -181,6 +181,11 @@ hipError_t launch_rank_scatter(int32_t nc, int32_t nzero, const unsigned long lo
 hipError_t radix_sort_u64(void *temp, size_t *temp_bytes, const unsigned long long *in,
                           unsigned long long *out, int32_t n, int end_bit, hipStream_t s);
 
+// Zero fills by kernel (mbe_prep.hip): bytes and width_bytes are multiples of 4, pointers
+// 4-byte aligned; the 2-D form clears rows runs of width_bytes spaced pitch bytes apart.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_zero_2d(void *base, size_t pitch, size_t width_bytes, size_t rows, hipStream_t s);
+
 // Batched preparation (mbe_prep.hip).
 hipError_t launch_batch_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,
                              const int32_t *graph_of, const int32_t *cbase, unsigned long long *keys,

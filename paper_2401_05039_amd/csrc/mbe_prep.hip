@@ -184,6 +184,18 @@ __global__ void batch_scatter_kernel(int32_t nc, const unsigned long long *sorte
     }
 }
 
+// Zero fill of rows runs of words 32-bit words, run r starting at base + r * pitch bytes (a
+// plain fill kernel rather than a runtime memset, so that the clears of a call are ordinary
+// kernel launches on its stream).
+__global__ void zero_2d_kernel(char *base, size_t pitch, int64_t words, int64_t rows) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t total = words * rows;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int64_t r = t / words, w = t - r * words;
+        reinterpret_cast<uint32_t *>(base + (size_t)r * pitch)[w] = 0u;
+    }
+}
+
 int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -234,6 +246,18 @@ hipError_t launch_batch_scatter(int32_t nc, const unsigned long long *sorted, co
     if (nc == 0) return hipSuccess;
     hipLaunchKernelGGL(batch_scatter_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, sorted, graph_of, cbase,
                        gstats, order, rank, task_key, task, tbase);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
+    return launch_zero_2d(p, 0, bytes, 1, s);
+}
+
+hipError_t launch_zero_2d(void *base, size_t pitch, size_t width_bytes, size_t rows, hipStream_t s) {
+    const int64_t words = (int64_t)(width_bytes / 4);
+    if (words == 0 || rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_2d_kernel, dim3(grid_for(words * (int64_t)rows, 256)), dim3(256), 0, s,
+                       static_cast<char *>(base), pitch, words, (int64_t)rows);
     return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_strerror_and_version(lib):
     m, _ = lib
     assert m.mbe_strerror(0) == "ok"
-    for code in range(-6, 0):
+    for code in range(-7, 0):
         assert m.mbe_strerror(code) and m.mbe_strerror(code) != "unknown error"
     assert m.mbe_strerror(-99) == "unknown error"
     assert re.match(r"^\d+\.\d+\.\d+$", m.mbe_version())
