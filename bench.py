@@ -20,12 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-
-# HBM bytes moved by the search launches of one power-law step, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters scaled by a 1 GiB reference copy (profiles/search_kernel_powerlaw_100k_50k.md),
-# taken on the kernel source with this sha256; reported only while the source is unchanged.
-MEASURED_TRAFFIC = {"source_sha256": "7f2790169b8db1afc4001a3f39768bdcf2f20a98b10e1e61c791c4572a570868",
-                    "bytes_per_step": 3.466e10}
+BOX_THREADS = 16       # host threads of one GPU's share of the box
 
 
 def log(*a):
@@ -50,15 +45,77 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def measured_traffic():
-    import hashlib
-    src = os.path.join(ROOT, "paper_2401_05039_amd", "csrc", "mbe_search.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    return MEASURED_TRAFFIC["bytes_per_step"] if sha == MEASURED_TRAFFIC["source_sha256"] else None
+def _counter_rows(out_dir, counter):
+    """(kernel name, value) of every dispatch row of counter in rocprofv3's CSV output."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(out_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r.get("Kernel_Name", ""), float(r.get("Counter_Value", 0.0))))
+    return rows
 
 
-def cpu_baseline(g, rng_range, threads):
+def measure_traffic(args):
+    """HBM bytes of one step's search launches, measured: this script runs twice as a child
+    under rocprofv3 --pmc (FETCH_SIZE, then WRITE_SIZE), each child making one plain 1 GiB
+    device copy and one production step.  Each counter is scaled by what it reads for the
+    copy (1 GiB read and 1 GiB written).  Runs before this process touches the GPU; returns
+    None when the profiler is missing or its output is incomplete."""
+    import shutil
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
+    if not os.path.exists(prof):
+        return None
+    got = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        d = tempfile.mkdtemp(prefix="mbe_pmc_", dir="/tmp")
+        cmd = ["timeout", "-s", "KILL", "150", prof, "--pmc", ctr, "--output-format", "csv", "-d", d, "-o", "run",
+               "--", sys.executable, os.path.abspath(__file__), "--traffic-child", "--copy-mib", "1024",
+               "--workload", args.workload]
+        log("traffic:", ctr)
+        r = subprocess.run(cmd, cwd="/tmp", env=dict(os.environ, TMPDIR="/tmp"), capture_output=True, text=True)
+        rows = _counter_rows(d, ctr)
+        shutil.rmtree(d, ignore_errors=True)
+        copy = sum(v for k, v in rows if "copyBuffer" in k)
+        search = [v for k, v in rows if "search_kernel" in k]
+        if r.returncode not in (0, 139) or copy <= 0 or not search:
+            log(f"traffic: {ctr} not measured (rc {r.returncode}, {len(rows)} rows)")
+            return None
+        # counters are in KiB; the copy moves 1 GiB each way
+        scale = float(1 << 30) / (copy * 1024.0)
+        got[ctr] = {"kib": sum(search), "scale": scale, "bytes": sum(search) * 1024.0 * scale,
+                    "launches": len(search)}
+    return {"bytes": got["FETCH_SIZE"]["bytes"] + got["WRITE_SIZE"]["bytes"], "counters": got}
+
+
+def traffic_child(args):
+    """One plain 1 GiB device copy, then one production step (no diagnostics run)."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_2401_05039_amd as mbe
+    mbe.load()
+    g, desc, rng_range = make_workload(args.workload)
+    dev = torch.device("cuda:0")
+    dg = gg.BiGraph(g.n_u, g.n_v, *[torch.from_numpy(np.asarray(a)).to(dev) for a in
+                                    (g.u_off, g.u_adj, g.v_off, g.v_adj)])
+    n = args.copy_mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    lo, hi = rng_range if rng_range else (0, 0)
+    mbe.mbe_count(dg, mbe.Options(root_lo=lo, root_hi=hi))
+    torch.cuda.synchronize()
+
+
+def cpu_baseline(g, rng_range, threads, frac=0.2, chunks=64):
     """The oracle (serial MBEA, split by top-level rank over host threads) on a bounded
     sample of the same graph: evenly spaced chunks of top-level candidates."""
     import numpy as np
@@ -68,8 +125,8 @@ def cpu_baseline(g, rng_range, threads):
     n = oracle.num_roots(g)
     lo0, hi0 = rng_range if rng_range else (0, n)
     span = hi0 - lo0
-    frac = 0.2 if rng_range is None else 1.0
-    chunks = 64 if rng_range is None else min(16, span)
+    if rng_range is not None:
+        frac, chunks = 1.0, min(16, span)
     per = max(1, int(span * frac / chunks))
     starts = np.linspace(lo0, hi0 - per, chunks).astype(np.int64)
     t0 = time.time()
@@ -253,11 +310,20 @@ def main():
     ap.add_argument("--rate", type=float, default=2.5)
     ap.add_argument("--slots", type=int, default=2)
     ap.add_argument("--big-max-u", type=int, default=200_000)
+    ap.add_argument("--no-traffic", action="store_true",
+                    help="skip the two rocprofv3 counter runs that measure the step's HBM traffic")
+    ap.add_argument("--traffic-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the search runs on one GPU (sharding across GPUs is a design only); --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.traffic_child:
+        return traffic_child(args)
+    traffic = None
+    if args.workload in ("power-law", "skewed-sample", "er-small") and not args.no_traffic:
+        # (before this process initialises the GPU: the profiled children are started from here)
+        traffic = measure_traffic(args)
 
     import numpy as np
     import torch
@@ -288,9 +354,12 @@ def main():
     lo, hi = rng_range if rng_range else (0, 0)
     base = dict(wg_waves=args.waves, grid=args.grid, root_lo=lo, root_hi=hi)
 
-    # one untimed run with diagnostics gives the algorithmic bytes of the (deterministic) tree
-    # and the time split over search phases
-    diag = mbe.mbe_count(dg, mbe.Options(diagnostics=True, **base))
+    # one untimed run with diagnostics gives the method's tree (nodes, algorithmic bytes) and the
+    # time split over search phases; one untimed run of the production search with its
+    # design-byte tally gives the bytes its loads and stores request (deterministic)
+    diag = mbe.mbe_count(dg, mbe.Options(diagnostics=1, **base))
+    tally = mbe.mbe_count(dg, mbe.Options(diagnostics=2, **base))
+    assert (tally["count"], tally["hash"]) == (diag["count"], diag["hash"])
     ph = diag["phase_cycles"]
     ph_tot = max(1, sum(ph.values()))
     phase_share = {k: round(v / ph_tot, 4) for k, v in ph.items()}
@@ -311,7 +380,7 @@ def main():
     ms_step = dt * 1000.0 / args.steps
     value = diag["count"] * args.steps / dt
     kavg = sum(kms) / len(kms)
-    achieved = diag["bytes_alg"] / (kavg / 1000.0) / 1e9
+    achieved = tally["bytes_design"] / (kavg / 1000.0) / 1e9
     out = {
         "metric": "maximal bicliques/s",
         "value": value,
@@ -328,11 +397,15 @@ def main():
         "config": dict(desc, count=diag["count"], hash=hex(diag["hash"]), search_nodes=diag["nodes"]),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.workload == "power-law" else None,
-                     "traffic_gbs": (measured_traffic() / (kavg / 1000.0) / 1e9
-                                     if args.workload == "power-law" and measured_traffic() else None),
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_gbs": traffic["bytes"] / (kavg / 1000.0) / 1e9 if traffic else None,
+                     "traffic_frac": traffic["bytes"] / (kavg / 1000.0) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                     "traffic_counters": traffic["counters"] if traffic else None,
                      "kernel": "search_kernel (all mask-width launches of one step)",
-                     "kernel_ms": kavg, "bytes_alg": diag["bytes_alg"]},
+                     "kernel_ms": kavg, "bytes_design": tally["bytes_design"]},
+        # the paper's reverse-scanning method would move bytes_alg for the same tree; this
+        # design never performs those scans, so the rate is an effective one, not traffic
+        "paper_method_rate": {"bytes_alg": diag["bytes_alg"], "gbs": diag["bytes_alg"] / (kavg / 1000.0) / 1e9},
         "phase_share": phase_share,
     }
     if rng_range is not None:
@@ -341,9 +414,12 @@ def main():
         out["cpu_baseline"] = {"value": None, "unit": "bicliques/s", "cores": 0, "kind": "oracle",
                                "sample": "skipped: a single top-level candidate takes the oracle minutes"}
     elif not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
+        threads = min(BOX_THREADS, os.cpu_count() or 1)
         log("cpu baseline on", threads, "threads")
         out["cpu_baseline"] = cpu_baseline(g, rng_range, threads)
+        # the same oracle on one core, on a smaller sample (about a tenth of the work)
+        log("cpu baseline on 1 thread")
+        out["cpu_baseline_serial"] = cpu_baseline(g, rng_range, 1, frac=0.01, chunks=16)
     print(json.dumps(out), flush=True)
 
 

@@ -340,6 +340,26 @@ def config5_requests(n: int, rate: float, seed: int = _BASE_SEED + 5,
     return out
 
 
+def wide_hubs(n_u: int, n_v: int, hub_degrees: Sequence[int], p: float, seed: int, name: str = "") -> BiGraph:
+    """Top-level candidates of any degree: hubs u_0 .. u_{h-1} of U whose neighbourhoods are
+    random subsets of V of the given sizes, plus an Erdos-Renyi background on the other
+    vertices of U (each pair an edge with probability p).  With |U| < |V| the candidates are
+    U, so a hub's neighbour set is as wide as its degree."""
+    h = len(hub_degrees)
+    us, vs = [], []
+    for j, d in enumerate(hub_degrees):
+        perm = np.argsort(stream_u64(seed, 10 + j, n_v), kind="stable")
+        sel = np.sort(perm[:d])
+        us.append(np.full(d, j, dtype=np.int64))
+        vs.append(sel.astype(np.int64))
+    r = stream_uniform(seed, 9, (n_u - h) * n_v)
+    idx = np.nonzero(r < p)[0]
+    us.append(idx // n_v + h)
+    vs.append(idx % n_v)
+    return from_edges(n_u, n_v, np.concatenate(us), np.concatenate(vs),
+                      name=name or f"hubs{n_u}x{n_v}s{seed}")
+
+
 # ----------------------------------------------------------------------------- closed-form families
 
 def hub_lists(n: int) -> BiGraph:

@@ -36,11 +36,12 @@ extern "C" {
 #define MBE_ERR_BUFFER_TOO_SMALL -3  /* records did not fit; the mbe_result is still complete */
 #define MBE_ERR_OUT_OF_MEMORY    -4  /* device allocation failed */
 #define MBE_ERR_DEVICE           -5  /* a HIP runtime call failed */
-#define MBE_ERR_UNSUPPORTED      -6  /* a top-level candidate's degree exceeds MBE_MAX_DEGREE */
+#define MBE_ERR_UNSUPPORTED      -6  /* (kept for binary compatibility; no longer returned) */
 #define MBE_ERR_SCRATCH_LIMIT    -7  /* mbe_count_noalloc: the call does not fit the fixed scratch */
 
-/* Largest degree a top-level candidate may have: its neighbour set is held as a bit mask of
- * at most this many bits. */
+/* Widest fixed mask class: top-level candidates of degree up to this many are searched with
+ * neighbour sets held in registers as bit masks of 64 * 2^c bits (c = 0..4); candidates of any
+ * larger degree go to the wide search, whose masks have any width (see mbe_count). */
 #define MBE_MAX_DEGREE 1024
 
 /* ------------------------------------------------------------------------- graph */
@@ -87,6 +88,14 @@ typedef struct mbe_graph {
  * attempts   search launches the call needed: a launch whose wave stacks or frame-header
  *            arrays run out is repeated with twice the room (a device remembers the largest
  *            room an earlier call needed and starts there)
+ * status     batched and served results: the graph's own status (0 for every graph the call
+ *            searched; a call that fails reports its error as the return code instead)
+ * bytes_design  with diagnostics = 2: the bytes of device memory that the search's own loads,
+ *            stores and atomics request (the design's traffic model, before any cache): the
+ *            top-level candidates' reverse scans and local universes, every frame's lists,
+ *            per-bit tables and position rows written and read, per node the rows, masks and
+ *            tables it reads; the rebuilds of shared lists by helping workgroups are left out,
+ *            so the tally depends on the graph alone, not on the launch shape or timing
  */
 typedef struct mbe_result {
     uint64_t count;
@@ -101,7 +110,8 @@ typedef struct mbe_result {
     uint64_t phase_cycles[6];
     uint64_t shared_chunks;
     uint32_t attempts;
-    uint32_t reserved;
+    int32_t status;
+    uint64_t bytes_design;
 } mbe_result;
 
 /* ------------------------------------------------------------------------- options */
@@ -112,7 +122,10 @@ typedef struct mbe_result {
  *                B in V).
  *   wg_waves     64-lane waves per workgroup (1..8; default 8).
  *   grid         workgroups of the persistent search kernel (default: 2 per compute unit).
- *   diagnostics  1: also compute nodes / nonmaximal / max_depth / bytes_alg.
+ *   diagnostics  1: also compute nodes / nonmaximal / max_depth / bytes_alg (the search then
+ *                keeps the method's full Q lists, so that the tallies are the method's);
+ *                2: the production search (pruned Q lists, as with 0) that also tallies
+ *                bytes_design.  Other values are invalid.
  *   no_validate  1: skip the O(|E|) check of the CSR pair (the caller vouches for it).
  *   steal_k      work sharing below a top-level candidate (the k of section III-D): 2
  *                (default): the candidates of its child list that need a full node are
@@ -147,8 +160,11 @@ typedef struct mbe_options {
 /*
  * Count the maximal bicliques of g and hash them (algorithm: MBEA, Algorithm 1, with the
  * reverse-scanning count of section III-E).  out receives the mbe_result described above.
+ * Any degree is taken: top-level candidates of degree at most MBE_MAX_DEGREE run in one
+ * persistent kernel per mask-width class, the rest (degree above 1024) in the wide search
+ * after them, with the same candidate order, tree and tallies.
  * Errors: MBE_ERR_INVALID_ARG (g or out NULL, negative sizes, missing arrays),
- * MBE_ERR_INVALID_GRAPH, MBE_ERR_UNSUPPORTED, MBE_ERR_OUT_OF_MEMORY, MBE_ERR_DEVICE.
+ * MBE_ERR_INVALID_GRAPH, MBE_ERR_OUT_OF_MEMORY, MBE_ERR_DEVICE.
  * An empty side or zero edges gives count = hash = 0.
  */
 int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out);
@@ -213,7 +229,9 @@ int mbe_enumerate(const mbe_graph *g, const mbe_options *opt, mbe_result *out,
  * list ordered by mask class and then by decreasing candidate degree.  outs[i] receives
  * graph i's mbe_result, equal to what mbe_count would return for it; kernel_ms is the device
  * time of the whole batch.  Host graphs only (on_device = 0); root_lo / root_hi are ignored.
- * Errors as mbe_count; on MBE_ERR_INVALID_GRAPH no graph is searched.
+ * Errors as mbe_count; on MBE_ERR_INVALID_GRAPH no graph is searched.  Packed totals (candidate-side and other-side
+ * vertices, edges, summed in 64 bits over the graphs with edges) must each stay below 2^31 - 1,
+ * else MBE_ERR_INVALID_ARG before any device work.
  */
 int mbe_count_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt, mbe_result *outs);
 

@@ -49,7 +49,8 @@ class _Result(ctypes.Structure):
                 ("bytes_alg", ctypes.c_uint64), ("max_depth", ctypes.c_uint32),
                 ("side", ctypes.c_uint32), ("kernel_ms", ctypes.c_double),
                 ("phase_cycles", ctypes.c_uint64 * 6), ("shared_chunks", ctypes.c_uint64),
-                ("attempts", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("attempts", ctypes.c_uint32), ("status", ctypes.c_int32),
+                ("bytes_design", ctypes.c_uint64)]
 
 
 class _Options(ctypes.Structure):
@@ -65,7 +66,7 @@ class Options:
     side: int = 0
     wg_waves: int = 0
     grid: int = 0
-    diagnostics: bool = False
+    diagnostics: int = 0  # 1: the method's tree tallies; 2: the production search's design bytes
     no_validate: bool = False
     steal_k: int = 0
     root_lo: int = 0
@@ -172,7 +173,7 @@ def _marshal_opts(opt: Optional[Options], on_device: bool) -> _Options:
     if stream is None and on_device:
         import torch
         stream = torch.cuda.current_stream().cuda_stream
-    return _Options(opt.side, opt.wg_waves, opt.grid, int(bool(opt.diagnostics)), int(bool(opt.no_validate)),
+    return _Options(opt.side, opt.wg_waves, opt.grid, int(opt.diagnostics), int(bool(opt.no_validate)),
                     opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0))
 
 

@@ -56,7 +56,7 @@ struct DevBuf {
 
 struct DeviceState {
     std::mutex mu;
-    DevBuf graph, prep, sort_tmp, arena, small, steal, slots;
+    DevBuf graph, prep, sort_tmp, arena, small, steal, slots, warena, witems;
     DevBuf rec, rec_offs, rec_tmp, rec_lens, canon_tmp, out_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int cus = 0;
@@ -67,6 +67,8 @@ struct DeviceState {
     // later calls start there instead of repeating a launch that runs out
     int64_t scap_floor = 0;
     int32_t depth_floor = 0;
+    int64_t wscap_floor = 0;   // the same for the wide search
+    int32_t wdepth_floor = 0;
     // device address of this device's copy of the no-allocation scratch (set up on the first
     // mbe_count_noalloc call on the device)
     char *scratch = nullptr;
@@ -165,19 +167,32 @@ bool host_valid(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *
     return true;
 }
 
+// Top-level candidates above the widest mask class: rank (or task) range [lo, hi), searched by
+// the wide kernel with Wx words per universe mask.
+struct WideRange {
+    int64_t lo = 0, hi = 0;
+    int Wx = 0;
+};
+
+// Device memory the wide search's workgroup slots may take (their count shrinks to fit).
+constexpr size_t kWideArenaBytes = (size_t)4 << 30;
+
 struct Opts {
     int side, waves, grid, diag, no_validate, steal_k;
+    int tb;  // diagnostics = 2: the production search with its design-byte tally
     int64_t root_lo, root_hi;
     hipStream_t stream;
 };
 
 Opts read_opts(const mbe_options *o) {
-    Opts r{0, 8, 0, 0, 0, 2, 0, -1, nullptr};
+    Opts r{0, 8, 0, 0, 0, 2, 0, 0, -1, nullptr};
     if (!o) return r;
     r.side = o->side;
     r.waves = o->wg_waves > 0 ? o->wg_waves : 8;
     r.grid = o->grid > 0 ? o->grid : 0;
-    r.diag = o->diagnostics != 0;
+    r.diag = o->diagnostics == 1;
+    r.tb = o->diagnostics == 2;
+    if (o->diagnostics < 0 || o->diagnostics > 2) r.side = -1;  // (rejected as an invalid argument)
     r.no_validate = o->no_validate != 0;
     r.steal_k = o->steal_k == 0 ? 2 : o->steal_k;
     r.root_lo = o->root_lo > 0 ? o->root_lo : 0;
@@ -187,12 +202,13 @@ Opts read_opts(const mbe_options *o) {
 }
 
 int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
-               bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
+               bool diag, bool enumerate, bool tb, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
-               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx);
+               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx,
+               const WideRange &wr);
 
 size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi, bool diag,
-                        bool enumerate, int grid, int waves);
+                        bool enumerate, int grid, int waves, const WideRange &wr);
 
 // mbe_count / mbe_enumerate; with ws_out, only the preparation runs and *ws_out receives the
 // device bytes the search of this call would hold; with fixed (mbe_count_noalloc), every
@@ -323,7 +339,6 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     const int32_t nzero = (int32_t)hstats[0];
     const int32_t ncand = nc - nzero;
     if (ncand <= 0) return MBE_OK;
-    if (hstats[8] > (unsigned long long)MBE_MAX_DEGREE) return MBE_ERR_UNSUPPORTED;
     MBE_TRY(launch_rank_scatter(nc, nzero, sorted, order, rank, s));
 
     // rank ranges of the mask-width classes (ranks ascend with degree)
@@ -338,6 +353,11 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     }
     const int64_t lo = std::min<int64_t>(opt.root_lo, ncand);
     const int64_t hi = opt.root_hi < 0 ? ncand : std::min<int64_t>(opt.root_hi, ncand);
+    // candidates of degree above 64 * 16 rank after every class: the wide search takes them
+    WideRange wr;
+    wr.lo = std::max<int64_t>(run_r, lo);
+    wr.hi = std::min<int64_t>(run_r + (int64_t)hstats[6] + (int64_t)hstats[7], hi);
+    wr.Wx = (int)((hstats[8] + 63) / 64);
 
     const int waves = opt.waves;
     const int grid = opt.grid > 0 ? opt.grid : 0;  // 0: occupancy-sized per class
@@ -359,7 +379,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         if (!g->on_device)
             bytes += align_up(((size_t)nu + 1) * 4, 256) + align_up(((size_t)nv + 1) * 4, 256) +
                      2 * align_up((size_t)ne * 4, 256);
-        *ws_out = bytes + search_footprint(st, dims, cls_a, cls_b, opt.diag, enumerate, grid, waves);
+        *ws_out = bytes + search_footprint(st, dims, cls_a, cls_b, opt.diag, enumerate, grid, waves, wr);
         return MBE_OK;
     }
 
@@ -412,8 +432,8 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     }
     {
         int attempts = 0;
-        const int rc = run_search(st, a, dims, cls_a, cls_b, opt.diag, enumerate, grid, waves, acc, ACC_SLOTS * 8, hacc,
-                                  &hflags, &ms, s, nullptr, 0, &attempts, small, fx);
+        const int rc = run_search(st, a, dims, cls_a, cls_b, opt.diag, enumerate, opt.tb, grid, waves, acc, ACC_SLOTS * 8, hacc,
+                                  &hflags, &ms, s, nullptr, 0, &attempts, small, fx, wr);
         out->attempts = (uint32_t)attempts;
         if (rc != MBE_OK) return rc;
     }
@@ -428,6 +448,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     out->kernel_ms = ms;
     for (int q = 0; q < PH_COUNT; ++q) out->phase_cycles[q] = hacc[ACC_PHASE + q];
     out->shared_chunks = hacc[ACC_SHARED];
+    out->bytes_design = hacc[ACC_DBYTES];
 
     if (!enumerate) return MBE_OK;
     if ((hflags & FLAG_RECORD_OVERFLOW) || out->out_ints > ucap_ints) return MBE_ERR_BUFFER_TOO_SMALL;
@@ -478,25 +499,51 @@ int search_slots(DeviceState *st, const int64_t *cls_lo, const int64_t *cls_hi, 
 
 // Device bytes the search of a call holds: the arena slots, the slot flags and the sharing
 // slots (with the capacities the device has already grown to).
+// The wide search's arena layout and grid for a call: workgroups up to twice the compute units
+// (or the caller's grid), at most 16 per top-level candidate, and no more than kWideArenaBytes
+// (or cap, when positive) of slots.
+WideLayout wide_plan(DeviceState *st, const SearchDims &dims, const WideRange &wr, int64_t wscap, int32_t wdepth,
+                     int grid, int waves, size_t cap, int *wgrid) {
+    WideLayout wl = wide_layout(dims, wr.Wx, wscap, wdepth, waves);
+    const int64_t nroots = wr.hi - wr.lo;
+    const int64_t budget = (int64_t)((cap ? cap : kWideArenaBytes) / wl.wg_bytes);
+    int64_t g = std::min<int64_t>(grid > 0 ? grid : 2 * (int64_t)st->cus, nroots * 16);
+    g = std::min<int64_t>(g, budget);
+    *wgrid = (int)g;
+    wl.reps = g > 0 ? (int)((g + nroots - 1) / nroots) : 1;
+    return wl;
+}
+
 size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi, bool diag,
-                        bool enumerate, int grid, int waves) {
+                        bool enumerate, int grid, int waves, const WideRange &wr) {
     dims.scap = std::max<int64_t>(dims.scap, st->scap_floor);
     dims.maxdepth = std::max<int32_t>(dims.maxdepth, st->depth_floor);
     int cls_grid[5], cls_res[5];
     const size_t nslots = (size_t)search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, false, cls_grid, cls_res);
-    return search_layout(dims).wg_bytes * nslots + sizeof(unsigned int) * nslots + sizeof(StealSlot) * nslots * 5 +
-           sizeof(PubSlot) * nslots * (size_t)waves * 5;
+    size_t bytes = search_layout(dims).wg_bytes * nslots + sizeof(unsigned int) * nslots + sizeof(StealSlot) * nslots * 5 +
+                   sizeof(PubSlot) * nslots * (size_t)waves * 5;
+    if (wr.lo < wr.hi) {
+        int wgrid = 0;
+        const WideLayout wl = wide_plan(st, dims, wr, std::max<int64_t>(st->wscap_floor, 8 * (int64_t)dims.ucap + 65536),
+                                        std::max<int32_t>(st->wdepth_floor, 256), grid, waves, 0, &wgrid);
+        bytes += wl.wg_bytes * (size_t)std::max(wgrid, 1) + 4 * (size_t)(wr.hi - wr.lo);
+    }
+    return bytes;
 }
 
 // Search run shared by the single-graph and batched calls: sizes the arena, launches one
 // persistent kernel per mask-width class (widest first) and reruns with larger capacities
 // when a kernel reports an overflow.  hacc / hflags receive the run-wide slots and flags.
 int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi,
-               bool diag, bool enumerate, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
+               bool diag, bool enumerate, bool tb, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
-               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx) {
+               unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx,
+               const WideRange &wr) {
     dims.scap = std::max<int64_t>(dims.scap, st->scap_floor);
     dims.maxdepth = std::max<int32_t>(dims.maxdepth, st->depth_floor);
+    const bool wide = wr.lo < wr.hi;
+    int64_t wscap = std::max<int64_t>(st->wscap_floor, 8 * (int64_t)dims.ucap + 65536);
+    int32_t wdepth = std::max<int32_t>(st->wdepth_floor, 256);
     unsigned int *flags = a.flags;
     unsigned int *counters = reinterpret_cast<unsigned int *>(small + 512);
     unsigned int hflags = 0;
@@ -516,10 +563,35 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         // sharing slots
         const size_t share_per_slot = sizeof(StealSlot) * 5 + sizeof(PubSlot) * (size_t)waves * 5;
         char *share = nullptr;
+        // the wide search's own arena (its slots first: with fixed memory it takes up to half of
+        // what is left, the classes the rest)
+        SearchArgs aw{};
+        int wgrid = 0;
+        if (wide) {
+            if (fx) fx->used = mark;
+            const size_t wcap = fx ? (fx->cap - std::min(fx->cap, align_up(mark, 4096) + 4096)) / 2 : 0;
+            aw.wl = wide_plan(st, dims, wr, wscap, wdepth, grid, waves, wcap, &wgrid);
+            const int64_t nroots = wr.hi - wr.lo;
+            if (wgrid < 1) return fx ? MBE_ERR_SCRATCH_LIMIT : MBE_ERR_OUT_OF_MEMORY;
+            if (fx) {
+                aw.warena = static_cast<char *>(fx->take(aw.wl.wg_bytes * (size_t)wgrid, 4096));
+                aw.wide_items = static_cast<unsigned int *>(fx->take(4 * (size_t)nroots));
+                if (!aw.warena || !aw.wide_items) return MBE_ERR_SCRATCH_LIMIT;
+                MBE_TRY(launch_zero(aw.warena, aw.wl.wg_bytes * (size_t)wgrid, s));
+            } else {
+                MBE_TRY(st->warena.ensure(aw.wl.wg_bytes * (size_t)wgrid));
+                MBE_TRY(st->witems.ensure(4 * (size_t)nroots));
+                aw.warena = st->warena.as<char>();
+                aw.wide_items = st->witems.as<unsigned int>();
+            }
+            MBE_TRY(launch_zero_2d(aw.warena + aw.wl.off_bitmap, aw.wl.wg_bytes, (size_t)dims.nwords * 8, (size_t)wgrid, s));
+            MBE_TRY(launch_zero(aw.wide_items, 4 * (size_t)nroots, s));
+        }
         if (fx) {
             // as many arena slots as fit in what the call has left of the scratch
-            fx->used = mark;
-            const size_t start = align_up(mark, 4096), slack = 2 * 4096;
+            const size_t wmark = fx->used;
+            fx->used = wide ? wmark : mark;
+            const size_t start = align_up(fx->used, 4096), slack = 2 * 4096;
             const size_t left = fx->cap > start + slack ? fx->cap - start - slack : 0;
             const size_t per_slot = a.lay.wg_bytes + sizeof(unsigned int) + share_per_slot;
             const int64_t fit = (int64_t)(left / per_slot);
@@ -575,11 +647,19 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
             }
             // (with fixed memory the grid is at most the slots that fit)
             const int gsz = fx ? std::min(cls_grid[c], nslots) : cls_grid[c];
-            MBE_TRY(launch_search(ac, 1 << c, diag, enumerate, cls_lo[c], cls_hi[c], counters + c, gsz, waves, cs));
+            MBE_TRY(launch_search(ac, 1 << c, diag, enumerate, tb, cls_lo[c], cls_hi[c], counters + c, gsz, waves, cs));
             if (!sequential) {
                 MBE_TRY(hipEventRecord(st->join[c], cs));
                 MBE_TRY(hipStreamWaitEvent(s, st->join[c], 0));
             }
+        }
+        if (wide) {
+            // the wide top-level candidates, after the classes, on the call's stream
+            SearchArgs ac = a;
+            ac.warena = aw.warena;
+            ac.wl = aw.wl;
+            ac.wide_items = aw.wide_items;
+            MBE_TRY(launch_wide(ac, diag, enumerate, tb, wr.lo, wr.hi, counters + 5, wgrid, waves, s));
         }
         MBE_TRY(hipEventRecord(st->ev1, s));
         MBE_TRY(hipMemcpyAsync(hacc, run_acc, ACC_SLOTS * 8, hipMemcpyDeviceToHost, s));
@@ -591,8 +671,14 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         if (!(hflags & FLAG_RERUN)) break;
         if (attempt >= 8) return MBE_ERR_OUT_OF_MEMORY;
         if (hflags & FLAG_NO_SLOT) sequential = true;
-        if (hflags & FLAG_STACK_OVERFLOW) dims.scap = std::min<int64_t>(dims.scap * 2, (int64_t)1 << 31);
-        if (hflags & FLAG_DEPTH_OVERFLOW) dims.maxdepth *= 2;
+        if (hflags & FLAG_STACK_OVERFLOW) {
+            dims.scap = std::min<int64_t>(dims.scap * 2, (int64_t)1 << 31);
+            wscap = std::min<int64_t>(wscap * 2, (int64_t)1 << 31);
+        }
+        if (hflags & FLAG_DEPTH_OVERFLOW) {
+            dims.maxdepth *= 2;
+            wdepth *= 2;
+        }
         if (hflags & FLAG_UNIVERSE_OVERFLOW) {
             dims.ucap = (int32_t)std::max<int64_t>(dims.ucap, (int64_t)hacc[ACC_NEED_UCAP]);
             dims.scap = std::max<int64_t>(dims.scap, 4 * (int64_t)dims.ucap + 16384);
@@ -600,6 +686,10 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
     }
     st->scap_floor = std::max<int64_t>(st->scap_floor, dims.scap);
     st->depth_floor = std::max<int32_t>(st->depth_floor, dims.maxdepth);
+    if (wide) {
+        st->wscap_floor = std::max<int64_t>(st->wscap_floor, wscap);
+        st->wdepth_floor = std::max<int32_t>(st->wdepth_floor, wdepth);
+    }
     *hflags_out = hflags;
     return MBE_OK;
 }
@@ -627,6 +717,26 @@ int check_graphs(const mbe_graph *gs, int32_t n, bool validate) {
     return MBE_OK;
 }
 
+// Packed sizes of a batch, summed in 64 bits before anything is packed: the packed candidate
+// and other-side ids and the edge offsets are int32, so a batch whose totals do not fit is
+// refused (MBE_ERR_INVALID_ARG) before any allocation or device work.
+int batch_totals(const mbe_graph *gs, int32_t n, int side_opt, int64_t *nc_tot, int64_t *no_tot, int64_t *e_tot) {
+    int64_t NC = 0, NO = 0, E = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const mbe_graph &g = gs[i];
+        if (g.n_edges == 0) continue;
+        const int sd = side_opt ? side_opt : (g.n_v < g.n_u ? 2 : 1);
+        NC += sd == 2 ? g.n_v : g.n_u;
+        NO += sd == 2 ? g.n_u : g.n_v;
+        E += g.n_edges;
+        if (NC >= INT32_MAX || NO >= INT32_MAX || E > INT32_MAX) return MBE_ERR_INVALID_ARG;
+    }
+    if (nc_tot) *nc_tot = NC;
+    if (no_tot) *no_tot = NO;
+    if (e_tot) *e_tot = E;
+    return MBE_OK;
+}
+
 // The batched pass on a given workspace and stream (the caller holds the workspace and has
 // run check_graphs).
 int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n, const mbe_options *opt_in,
@@ -641,6 +751,7 @@ int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_res
     for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
     const int rc = check_graphs(gs, n, !opt.no_validate);
     if (rc != MBE_OK) return rc;
+    MBE_CALL(batch_totals(gs, n, opt.side, nullptr, nullptr, nullptr));
     bool any = false;
     for (int32_t i = 0; i < n; ++i) any = any || (gs[i].n_edges > 0);
     if (!any) {
@@ -663,8 +774,11 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         opt.steal_k < 1 || opt.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
     for (int32_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(outs[i]));
-    // host checks and packing (each graph keeps its own candidate side)
-    std::vector<int32_t> side(n), nc(n), no(n), cb(n + 1, 0), ob(n + 1, 0), eb(n + 1, 0);
+    // host checks and packing (each graph keeps its own candidate side); totals are checked in
+    // 64 bits before anything is packed
+    MBE_CALL(batch_totals(gs, n, opt.side, nullptr, nullptr, nullptr));
+    std::vector<int32_t> side(n), nc(n), no(n);
+    std::vector<int64_t> cb(n + 1, 0), ob(n + 1, 0), eb(n + 1, 0);
     int64_t NC = 0, NO = 0, E = 0;
     int max_no = 1;
     for (int32_t i = 0; i < n; ++i) {
@@ -674,16 +788,16 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         nc[i] = side[i] == 2 ? g.n_v : g.n_u;
         no[i] = side[i] == 2 ? g.n_u : g.n_v;
         if (g.n_edges == 0) nc[i] = no[i] = 0;  // nothing to search: keep it out of the pack
+    }
+    for (int32_t i = 0; i < n; ++i) {
         cb[i + 1] = cb[i] + nc[i];
         ob[i + 1] = ob[i] + no[i];
-        eb[i + 1] = eb[i] + (nc[i] ? g.n_edges : 0);
+        eb[i + 1] = eb[i] + (nc[i] ? gs[i].n_edges : 0);
         max_no = std::max(max_no, no[i]);
-        if ((int64_t)cb[i + 1] > INT32_MAX / 2 || (int64_t)ob[i + 1] > INT32_MAX / 2) return MBE_ERR_INVALID_ARG;
     }
     NC = cb[n];
     NO = ob[n];
     E = eb[n];
-    if (E > INT32_MAX) return MBE_ERR_INVALID_ARG;
     if (NC == 0) return MBE_OK;
     std::vector<int32_t> c_off(NC + 1), o_off(NO + 1), c_adj(E), o_adj(E), graph_of(NC);
     int64_t cls_cnt[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -695,7 +809,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         const int32_t *go = cv ? g.v_off : g.u_off, *ga = cv ? g.v_adj : g.u_adj;
         const int32_t *ho = cv ? g.u_off : g.v_off, *ha = cv ? g.u_adj : g.v_adj;
         for (int32_t v = 0; v < nc[i]; ++v) {
-            c_off[cb[i] + v] = eb[i] + go[v];
+            c_off[cb[i] + v] = (int32_t)(eb[i] + go[v]);
             graph_of[cb[i] + v] = i;
             const int64_t d = go[v + 1] - go[v];
             if (d > 0) {
@@ -703,15 +817,14 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
                 ++cls_cnt[degree_class(d)];
             }
         }
-        for (int32_t w = 0; w < no[i]; ++w) o_off[ob[i] + w] = eb[i] + ho[w];
+        for (int32_t w = 0; w < no[i]; ++w) o_off[ob[i] + w] = (int32_t)(eb[i] + ho[w]);
         for (int32_t e = 0; e < g.n_edges; ++e) {
-            c_adj[eb[i] + e] = ga[e] + ob[i];
-            o_adj[eb[i] + e] = ha[e] + cb[i];
+            c_adj[eb[i] + e] = ga[e] + (int32_t)ob[i];
+            o_adj[eb[i] + e] = ha[e] + (int32_t)cb[i];
         }
     }
     c_off[NC] = (int32_t)E;
     o_off[NO] = (int32_t)E;
-    if (cls_cnt[5] || cls_cnt[6]) return MBE_ERR_UNSUPPORTED;
 
     // device copies: graph | prep | per-graph accumulators
     auto al = [](size_t b) { return align_up(b, 256); };
@@ -729,7 +842,8 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     if (E) MBE_TRY(hipMemcpyAsync(d_cadj, c_adj.data(), E * 4, hipMemcpyHostToDevice, s));
     if (E) MBE_TRY(hipMemcpyAsync(d_oadj, o_adj.data(), E * 4, hipMemcpyHostToDevice, s));
     MBE_TRY(hipMemcpyAsync(d_gof, graph_of.data(), NC * 4, hipMemcpyHostToDevice, s));
-    MBE_TRY(hipMemcpyAsync(d_cb, cb.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
+    std::vector<int32_t> cb32(cb.begin(), cb.end());  // (the totals fit int32: checked above)
+    MBE_TRY(hipMemcpyAsync(d_cb, cb32.data(), (n + 1) * 4, hipMemcpyHostToDevice, s));
 
     int64_t NT = 0;
     std::vector<int32_t> tb(n + 1, 0);
@@ -791,8 +905,8 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         d.total_fw = 2ull * (unsigned long long)ncand_h[i] + (unsigned long long)(eb[i + 1] - eb[i]);
         d.nwords = (int32_t)((ncand_h[i] + 63) / 64);
         d.c_is_v = side[i] == 2 ? 1 : 0;
-        d.cbase = cb[i];
-        d.obase = ob[i];
+        d.cbase = (int32_t)cb[i];
+        d.obase = (int32_t)ob[i];
         ucap = std::max<int64_t>(ucap, std::min<int64_t>(ncand_h[i], (int64_t)hg[2 * i + 1]));
         maxc = std::max<int64_t>(maxc, ncand_h[i]);
     }
@@ -830,8 +944,12 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     unsigned int hflags = 0;
     float ms = 0.f;
     int attempts = 0;
-    int rc = run_search(st, a, dims, cls_lo, cls_hi, opt.diag, false, grid, opt.waves, acc, ACC_SLOTS * 8, hacc, &hflags,
-                        &ms, s, gacc, (size_t)n * ACC_SLOTS * 8, &attempts, st->small.as<char>(), nullptr);
+    WideRange wr;
+    wr.lo = run_t;
+    wr.hi = run_t + cls_cnt[5] + cls_cnt[6];
+    wr.Wx = (int)((hstats[8] + 63) / 64);
+    int rc = run_search(st, a, dims, cls_lo, cls_hi, opt.diag, false, opt.tb, grid, opt.waves, acc, ACC_SLOTS * 8, hacc, &hflags,
+                        &ms, s, gacc, (size_t)n * ACC_SLOTS * 8, &attempts, st->small.as<char>(), nullptr, wr);
     if (rc != MBE_OK) return rc;
     std::vector<unsigned long long> hga((size_t)n * ACC_SLOTS);
     MBE_TRY(hipMemcpyAsync(hga.data(), gacc, hga.size() * 8, hipMemcpyDeviceToHost, s));
@@ -849,6 +967,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
         for (int ph = 0; ph < PH_COUNT; ++ph) outs[i].phase_cycles[ph] = q[ACC_PHASE + ph];
         outs[i].shared_chunks = hacc[ACC_SHARED];  // (the whole call's)
         outs[i].attempts = (uint32_t)attempts;
+        outs[i].bytes_design = q[ACC_DBYTES];
     }
     return MBE_OK;
 }
@@ -876,7 +995,8 @@ struct ServerRequest {
 };
 
 void free_state(DeviceState *st) {
-    DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->steal, &st->slots, &st->rec,
+    DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->steal, &st->slots, &st->warena,
+                      &st->witems, &st->rec,
                       &st->rec_offs, &st->rec_tmp, &st->rec_lens, &st->canon_tmp, &st->out_tmp};
     for (DevBuf *b : bufs)
         if (b->p) {
@@ -953,6 +1073,8 @@ struct mbe_server {
                 cv_work.wait(lk, [&] { return stopping || any_eligible(); });
                 if (!any_eligible()) return;  // stopping; other slots finish the rest
                 size_t csr = 0, arena = 0;
+                // the packed batch indexes vertices and edges with int32
+                int64_t ids = 0, edges = 0;
                 for (auto it = pending.begin(); it != pending.end() && (int)batch.size() < max_batch;) {
                     const ServerRequest &r = **it;
                     if (!eligible(r)) {
@@ -961,6 +1083,10 @@ struct mbe_server {
                     }
                     const size_t need = csr + r.csr_bytes + std::max(arena, r.arena_bytes);
                     if (!batch.empty() && need > slot_budget) break;
+                    const int64_t ids2 = ids + (int64_t)r.g.n_u + r.g.n_v, edges2 = edges + r.g.n_edges;
+                    if (!batch.empty() && (ids2 >= INT32_MAX || edges2 > INT32_MAX)) break;
+                    ids = ids2;
+                    edges = edges2;
                     csr += r.csr_bytes;
                     arena = std::max(arena, r.arena_bytes);
                     batch.push_back(*it);
@@ -979,7 +1105,7 @@ struct mbe_server {
                 std::lock_guard<std::mutex> lk(mu);
                 for (size_t i = 0; i < batch.size(); ++i) {
                     batch[i]->result = rs[i];
-                    batch[i]->rc = rc;
+                    batch[i]->rc = rc != MBE_OK ? rc : rs[i].status;
                     batch[i]->finish = now;
                     batch[i]->done = true;
                     // the graph copy is no longer needed
@@ -1185,7 +1311,7 @@ const char *mbe_strerror(int code) {
         case MBE_ERR_BUFFER_TOO_SMALL: return "record buffer too small";
         case MBE_ERR_OUT_OF_MEMORY: return "out of device memory";
         case MBE_ERR_DEVICE: return "HIP runtime error";
-        case MBE_ERR_UNSUPPORTED: return "candidate degree above MBE_MAX_DEGREE";
+        case MBE_ERR_UNSUPPORTED: return "unsupported input";
         case MBE_ERR_SCRATCH_LIMIT: return "the call needs more device memory than the fixed scratch of mbe_count_noalloc";
         default: return "unknown error";
     }

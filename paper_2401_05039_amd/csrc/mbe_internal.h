@@ -22,6 +22,7 @@ enum AccSlot : int {
     ACC_NEED_UCAP = 9,  // largest universe met (max), for resizing after an overflow
     ACC_SHARED = 10,    // third-level chunks searched by a wave other than the list's owner
     ACC_PHASE = 11,     // 6 slots: shader-clock cycles per search phase (diagnostics only)
+    ACC_DBYTES = 17,    // design-byte tally of the production search (tally instances only)
     ACC_SLOTS = 24,
 };
 
@@ -82,6 +83,37 @@ struct ArenaLayout {
     size_t off_w_stack; // u32[scap]            frames (lists, masks, per-bit tables)
     size_t off_w_u;     // u32[ucap]            a maximal node's entries, in list order
     size_t off_w_hdr;   // frame headers[maxdepth]
+};
+
+// Arena of the wide search (top-level candidates of degree above 64 * 16, any width): per
+// workgroup slot, then per wave.  Masks of a universe entry take Wx words.
+struct WideLayout {
+    int32_t Wx;          // words of a universe mask: ceil(largest top-level degree / 64)
+    int32_t reps;        // workgroups that rebuild one top-level candidate and share its chunks
+    int64_t scap;        // per-wave stack capacity (32-bit words)
+    int32_t maxdepth;    // per-wave frame headers
+    int32_t pad;
+    size_t wg_bytes;     // stride between workgroup slots
+    size_t off_bitmap;   // u64[nwords]            membership bitmap over candidate ranks
+    size_t off_bpre;     // u32[nwords+1]          its popcount prefix
+    size_t off_M;        // u64[ucap*Wx]           neighbour masks of the local universe
+    size_t off_gid;      // i32[ucap]              global id of each universe entry
+    size_t off_cnt;      // u32[ucap]              top-level counts
+    size_t off_hv;       // u64[64*Wx]             R-side hash term per position of N(x)
+    size_t off_deg;      // u32[64*Wx]             degree per position of N(x)
+    size_t off_t1v;      // u32[ucap]              sort staging (ids)
+    size_t off_t1c;      // u32[ucap]              sort staging (keys)
+    size_t off_whist;    // u32[64*Wx+1]           top-level sort histogram
+    size_t off_S1;       // the top-level list as a frame
+    size_t off_waves;    // start of the per-wave regions
+    size_t wave_bytes;   // stride between waves
+    size_t off_w_stack;  // u32[scap]              frames
+    size_t off_w_u;      // u32[ucap]              a maximal node's entries, in list order
+    size_t off_w_bl;     // u32[64*Wx]             the bits of a node's R'
+    size_t off_w_hist;   // u32[64*Wx+2]           counting-sort histogram of a child list
+    size_t off_w_mr;     // u64[Wx]                a node's R' words
+    size_t off_w_rr;     // u64[Wx]                R' as positions of N(x) (records)
+    size_t off_w_hdr;    // frame headers[maxdepth]
 };
 
 // One graph of the packed candidate-orientation arrays.  A single call has one; a batch
@@ -150,6 +182,11 @@ struct SearchArgs {
     // outputs
     unsigned long long *acc;    // run-wide slots (overflow sizes, record cursors)
     unsigned int *flags;
+    // wide search (wide_kernel only): its own arena of workgroup slots, one chunk counter per
+    // top-level candidate of the launch (zeroed first)
+    char *warena;
+    WideLayout wl;
+    unsigned int *wide_items;
     // record arena (mbe_enumerate only)
     int32_t *rec;
     unsigned long long rec_cap;
@@ -165,9 +202,17 @@ int search_occupancy(int W, bool diag, bool enumerate, int waves);
 
 // Launch the search over tasks [lo, hi) of the work list (or ranks [lo, hi) of graph 0 when
 // it is NULL), all of whose top-level candidates have degree at most 64*W.  counter must be
-// zero.
-hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, int64_t lo,
+// zero.  tb (diag and enumerate off): the production search that also tallies its design
+// bytes into ACC_DBYTES.
+hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, bool tb, int64_t lo,
                          int64_t hi, unsigned int *counter, int grid, int waves, hipStream_t s);
+
+// Wide search: layout for the given capacities (Wx words per universe mask), and the launch
+// over tasks [lo, hi) of the work list (or ranks [lo, hi) of graph 0), each of whose
+// top-level candidates is shared by wl.reps workgroups; counter must be zero.
+WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdepth, int waves);
+hipError_t launch_wide(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi,
+                       unsigned int *counter, int grid, int waves, hipStream_t s);
 
 // Graph preparation and validation (mbe_prep.hip).
 hipError_t launch_validate(int32_t n_u, int32_t n_v, int32_t n_edges, const int32_t *u_off, const int32_t *u_adj,

@@ -315,6 +315,7 @@ struct Ctx {
 
 struct WaveAcc {  // per-lane partial tallies, summed over the wave at the end
     uint64_t count, hash, out_ints, nodes, nonmax, bytes;
+    uint64_t dbytes;  // design-byte tally (TB instances): global bytes this search's loads and stores request
     uint32_t max_depth;
     uint64_t ph[PH_COUNT];  // cycles per phase (wave-uniform; diagnostics only)
 };
@@ -504,7 +505,7 @@ __device__ __forceinline__ void write_record(const Ctx &c, const uint64_t *Rr, i
 
 // Candidates [base, base+64) of frame F: lanes with |R'| = 1 are settled here; the rest are
 // returned as a lane mask.
-template <int WF, bool DIAG, bool ENUM>
+template <int WF, bool DIAG, bool ENUM, bool TB = false>
 __device__ __forceinline__ uint64_t light_chunk(const Ctx &c, const FrameState &F, const FrameView &v, int base, WaveAcc &acc,
                                 bool settle = true) {
     const int ln = lane_id();
@@ -542,7 +543,10 @@ __device__ __forceinline__ uint64_t light_chunk(const Ctx &c, const FrameState &
             const uint64_t fw = F.fw - (2ull + dx);
             acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + 1ull);
         }
+        // first[b]; for a maximal node H[b], cnt[b], the R-side hash term (and orig[b])
+        if (TB) acc.dbytes += 4ull + (maximal ? 20ull + (F.narrow ? 4ull : 0ull) : 0ull);
     }
+    if (TB && act && settle) acc.dbytes += 8ull * WF;  // the entry's mask
     return __ballot(act && r >= 2);
 }
 
@@ -664,11 +668,14 @@ __device__ __forceinline__ int prune_q(const Ctx &c, const FrameView &v, const u
 // holds, per count, the number of P' entries (filled by the caller).  Masks are restricted
 // to R' and, when NARROW, compressed to |R'| bits; the tables and rows follow.  Sets the
 // layout fields of C; false when the stack is full.
-template <int WF, int W, bool NARROW, bool DIAG>
+template <int WF, int W, bool NARROW, bool DIAG, bool TB = false>
 __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int nu,
-                            int r, int qn, int pn, FrameState &C, int preq) {
+                            int r, int qn, int pn, FrameState &C, int preq, WaveAcc &acc, bool tally) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
+    int nzw = 0;  // words of R' (the mask words an entry's gathers read)
+#pragma unroll
+    for (int w = 0; w < WF; ++w) nzw += m[w] ? 1 : 0;
     // Q': with diagnostics off, a compressed child keeps only its inclusion-maximal masks
     // (the tallies of diagnostics mode count the full Q' of the method).  preq >= 0: the
     // caller already left them in c.qk, and stu[0, pn) packs each P' entry's position (low
@@ -681,6 +688,7 @@ __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, c
     } else if constexpr (NARROW && !DIAG) {
         if (qn > 1) {
             const int nk = prune_q<WF, kSmallRPrune<W>>(c, v, m, qn, r);
+            if (TB && tally && ln == 0) acc.dbytes += (uint64_t)qn * (4ull + 8ull * (uint64_t)nzw);  // stu, masks
             if (nk >= 0) {
                 nq2 = nk;
                 pruned = true;
@@ -800,11 +808,33 @@ __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, c
         }
     }
     wait_mem();
+    if (TB && tally && ln == 0) {
+        const uint64_t nloop = (uint64_t)(nu - (pruned ? qn : 0));
+        uint64_t b = nloop * (4ull + 8ull * (uint64_t)wf2) + 16ull * (uint64_t)pn;  // stu; child masks; hs in and out
+        if (preq < 0) b += nloop * 8ull * (uint64_t)nzw;                           // the entries' masks over R'
+        if (NARROW) {
+            b += 8ull * (uint64_t)(pruned ? nq2 : 0) + 4ull * (uint64_t)r * (F.narrow ? 2ull : 1ull);  // kept Q'; orig
+            b += 16ull * (uint64_t)r + 8ull * (uint64_t)n2 + 8ull * (uint64_t)r * (uint64_t)v2.nw;   // tables; rows
+        } else {
+            // tables cleared, each entry's hash term and mask words read, its bits' table atomics
+            // (tallied per lane below), rows of the words of R'
+            b += 16ull * 64ull * W + (uint64_t)n2 * (8ull + 8ull * (uint64_t)nzw) +
+                 8ull * 64ull * (uint64_t)nzw * (uint64_t)v2.nw;
+        }
+        acc.dbytes += b;
+    }
     if constexpr (NARROW) {
         narrow_table_finish(c, v2, n2, r);
     } else {
         static_assert(WF == W, "wide children come from wide lists");
         build_tables_wide<W>(v2, n2, nq2, m);
+        if (TB && tally)
+            for (int k = ln; k < n2; k += 64) {
+                uint64_t bits = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) bits += (uint64_t)__popcll(masks2[(size_t)k * W + w]);
+                acc.dbytes += 16ull * bits;
+            }
     }
     C.off = off2;
     C.top = top2;
@@ -842,7 +872,7 @@ __device__ __forceinline__ void fold_rows(const Ctx &c, const FrameView &v, int 
 // The candidate at position i of frame F, |R'| = r >= 1, handled by the whole wave.
 // Returns true when a child frame was written (its state in C).  report = false rebuilds the
 // child frame of a node another wave owns: nothing is counted or recorded.
-template <int WF, int W, bool DIAG, bool ENUM>
+template <int WF, int W, bool DIAG, bool ENUM, bool TB = false>
 __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, const FrameView &v, int i, FrameState &C,
                            WaveAcc &acc, bool report) {
     const int ln = lane_id();
@@ -877,12 +907,14 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
         if (((m[w] >> ln) & 1ull) && v.first[64 * w + ln] == (uint32_t)i) first_here = true;
     bool nonmax = false;
     uint64_t tp = DIAG ? clock64() : 0ull;
+    if (TB && report && ln == 0) acc.dbytes += 8ull * WF + 4ull * (uint64_t)r;  // R'; first[] of its bits
     if (!__ballot(first_here)) {
         const int wl = i >> 6;  // the word holding position i
         for (int base = 0; base <= wl; base += 64) {
             const int wd = base + ln;
             uint64_t u, a;
             fold_rows(c, v, r, wd, wd <= wl, u, a);
+            if (TB && report && ln == 0) acc.dbytes += 8ull * (uint64_t)r * (uint64_t)min(64, wl + 1 - base);
             if (wd == wl) a &= (1ull << (i & 63)) - 1ull;
             if (__ballot(a != 0ull)) {
                 nonmax = true;
@@ -1056,6 +1088,18 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
     }
     const int ne = wave_sum_i32(ne_l);
     const int pn = nu - qn;
+    if (TB && report && ln == 0) {
+        // R''s rows over every word of positions, the joiners' hash terms, the listed entries
+        // (written, and for the counts of P' read back with their mask words over R'),
+        // the R-side hash terms (and orig) of R'
+        int nzw = 0;
+#pragma unroll
+        for (int w = 0; w < WF; ++w) nzw += m[w] ? 1 : 0;
+        uint64_t b = 8ull * (uint64_t)r * (uint64_t)v.nw + 8ull * (uint64_t)ne + 4ull * (uint64_t)nu;
+        if (!fastq) b += (uint64_t)pn * (4ull + 8ull * (uint64_t)nzw);
+        b += (uint64_t)r * (8ull + (F.narrow ? 4ull : 0ull));
+        acc.dbytes += b;
+    }
 
     // report (L', R')
     const uint64_t sL = F.sL + v.hs[i] + wave_sum_u64(exps);
@@ -1101,10 +1145,10 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
     // |R'| <= 64, compressed to |R'| bits
     bool ok;
     if constexpr (WF == 1) {
-        ok = build_child<1, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C, preq);
+        ok = build_child<1, W, true, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report);
     } else {
-        ok = r <= 64 ? build_child<WF, W, true, DIAG>(c, F, v, m, nu, r, qn, pn, C, preq)
-                     : build_child<WF, W, false, DIAG>(c, F, v, m, nu, r, qn, pn, C, preq);
+        ok = r <= 64 ? build_child<WF, W, true, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report)
+                     : build_child<WF, W, false, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report);
     }
     if (!ok) return false;
     C.level = F.level + 1;
@@ -1167,10 +1211,10 @@ struct WGShared {
 };
 
 // Add the workgroup's tallies to a graph's accumulators and clear them.  All threads call.
-template <bool DIAG>
+template <bool DIAG, bool TB = false>
 __device__ __forceinline__ void flush_acc(WaveAcc &acc, unsigned long long *gacc, WGShared *sh) {
     const int ln = lane_id();
-    uint64_t v[7];
+    uint64_t v[8];
     v[0] = wave_sum_u64(acc.count);
     v[1] = wave_sum_u64(acc.hash);
     v[2] = wave_sum_u64(acc.out_ints);
@@ -1178,10 +1222,12 @@ __device__ __forceinline__ void flush_acc(WaveAcc &acc, unsigned long long *gacc
     v[4] = DIAG ? wave_sum_u64(acc.nonmax) : 0ull;
     v[5] = DIAG ? wave_sum_u64(acc.bytes) : 0ull;
     v[6] = DIAG ? (uint64_t)wave_max_u32(acc.max_depth) : 0ull;
+    v[7] = TB ? wave_sum_u64(acc.dbytes) : 0ull;
     if (ln == 0) {
         for (int q = 0; q < 6; ++q)
             if (v[q]) lds_add(&sh->red[q], v[q]);
         if (v[6]) lds_max(&sh->red[6], v[6]);
+        if (v[7]) lds_add(&sh->red[7], v[7]);
         if (DIAG)
             for (int q = 0; q < PH_COUNT; ++q)
                 if (acc.ph[q]) lds_add(&sh->red[8 + q], acc.ph[q]);
@@ -1195,6 +1241,8 @@ __device__ __forceinline__ void flush_acc(WaveAcc &acc, unsigned long long *gacc
         }
         if (sh->red[6]) atomicMax(&gacc[ACC_MAX_DEPTH], sh->red[6]);
         sh->red[6] = 0ull;
+        if (sh->red[7]) atomicAdd(&gacc[ACC_DBYTES], sh->red[7]);
+        sh->red[7] = 0ull;
         for (int q = 0; q < PH_COUNT; ++q) {
             if (sh->red[8 + q]) atomicAdd(&gacc[ACC_PHASE + q], sh->red[8 + q]);
             sh->red[8 + q] = 0ull;
@@ -1345,7 +1393,8 @@ __device__ __forceinline__ bool find_shared_list(const SearchArgs &a, WGShared *
 
 // The single-word class (the most top-level candidates, small lists) keeps four waves per
 // SIMD resident: its register budget is capped at 128.
-template <int W, bool DIAG, bool ENUM>
+// TB (with DIAG and ENUM off): the production search, also tallying its design bytes.
+template <int W, bool DIAG, bool ENUM, bool TB = false>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 : 2))) void search_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
     extern __shared__ unsigned char lds_raw[];
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
@@ -1579,7 +1628,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         }
         if (g != sh->graph) {
             // tallies belong to the graph they were found in
-            if (sh->graph >= 0) flush_acc<DIAG>(acc, a.graphs[sh->graph].acc, sh);
+            if (sh->graph >= 0) flush_acc<DIAG, TB>(acc, a.graphs[sh->graph].acc, sh);
             __syncthreads();
             if (tid == 0) sh->graph = g;
             __syncthreads();
@@ -1801,6 +1850,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         __syncthreads();
         const bool root_nonmax = uni(sh->nonmax) != 0;
         const int P1 = uni(sh->pcount);
+        if (TB && tid == 0 && !thief) {
+            // x's row; its neighbours' offsets (walk set-up, hash and degree terms); both reverse
+            // scans (rows, ranks, bitmap and mask atomics, the universe index lookups); the terms
+            // per position of N(x); bitmap prefix, universe ids and bitmap clear; universe masks
+            // cleared, then read with the counts and ids
+            const uint64_t dd = (uint64_t)d, wk = (uint64_t)sh->rs1 - 2ull * dd, su = (uint64_t)s0;
+            acc.dbytes += 4ull * (dd + 2ull) + 16ull * dd + 44ull * wk + 12ull * BITS + 32ull * (uint64_t)nwords +
+                          8ull * su + 16ull * W * su + 8ull * su;
+        }
         if (tid == 0 && !thief) {  // a stolen task's top-level node belongs to its owner
             const uint64_t dx = (uint64_t)d;
             if (DIAG) {
@@ -1996,7 +2054,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         const int nch = thief3 ? 0 : (P1 + 63) >> 6;  // a third-level thief takes no top-level item
         for (int q = wid; q < nch; q += nw) {
             const uint64_t tl = DIAG ? clock64() : 0ull;
-            const uint64_t hm = light_chunk<W, DIAG, ENUM>(c, top, v1, nqk + 64 * q, acc, !thief);
+            const uint64_t hm = light_chunk<W, DIAG, ENUM, TB>(c, top, v1, nqk + 64 * q, acc, !thief);
             if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
             if (ln == 0) hb[q] = hm;
         }
@@ -2015,6 +2073,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
         wait_mem();
         __syncthreads();
         const int H = uni(sh->s0);
+        if (TB && tid == 0 && !thief) {
+            // the top-level list: Q1 (pruned, or copied), P1 staged and sorted, ids / hash terms /
+            // masks (universe masks read), tables, rows (list masks read, rows written), chunk
+            // flags, their prefix and the item list (written, read at the claims), the header
+            const uint64_t n1u = (uint64_t)n1, q0 = (uint64_t)nq0;
+            uint64_t b = (!DIAG && nq0 > 256)
+                             ? q0 * (12ull + 16ull * W) + 12ull * (uint64_t)((nq0 + 63) >> 6) + 4ull * (uint64_t)nqk
+                             : 4ull * q0;
+            b += 4ull * (uint64_t)(s0 - nq0) + 20ull * (uint64_t)P1;
+            b += n1u * (24ull + 16ull * W) + 16ull * BITS;
+            b += 8ull * n1u * (uint64_t)qd + 8ull * (uint64_t)d * (uint64_t)v1.nw;
+            b += 24ull * (uint64_t)nch + 8ull * (uint64_t)H + sizeof(FrameState);
+            acc.dbytes += b;
+        }
 
         // -- share the items.  The owner's waves claim them from an LDS counter; once a
         //    workgroup of the launch is idle, the wave whose claim notices it moves the rest of
@@ -2196,8 +2268,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                         }
                         cur.chunk = base;
                         const uint64_t tl = DIAG ? clock64() : 0ull;
-                        cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM>(c, cur, v, base, acc)
-                                                  : light_chunk<W, DIAG, ENUM>(c, cur, v, base, acc);
+                        cur.heavy = (cur.wf == 1) ? light_chunk<1, DIAG, ENUM, TB>(c, cur, v, base, acc)
+                                                  : light_chunk<W, DIAG, ENUM, TB>(c, cur, v, base, acc);
                         if (DIAG) acc.ph[PH_LIGHT] += clock64() - tl;
                         continue;
                     }
@@ -2207,8 +2279,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                 }
                 FrameState ch;
                 const bool report = src_top || depth > 0;
-                const bool pushed = (cur.wf == 1) ? heavy_node<1, W, DIAG, ENUM>(c, cur, v, i, ch, acc, report)
-                                                  : heavy_node<W, W, DIAG, ENUM>(c, cur, v, i, ch, acc, report);
+                const bool pushed = (cur.wf == 1) ? heavy_node<1, W, DIAG, ENUM, TB>(c, cur, v, i, ch, acc, report)
+                                                  : heavy_node<W, W, DIAG, ENUM, TB>(c, cur, v, i, ch, acc, report);
                 if (pushed) {
                     if (depth >= a.dims.maxdepth) {
                         if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
@@ -2218,6 +2290,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
                     if (depth > 0) {
                         hdr[depth] = cur;  // every lane stores the same header
                         wait_mem();
+                        if (TB && ln == 0) acc.dbytes += 2ull * sizeof(FrameState);  // saved, read back on return
                     }
                     ++depth;
                     cur = ch;
@@ -2253,7 +2326,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
     }
 
     // tallies of the last graph
-    if (sh->graph >= 0) flush_acc<DIAG>(acc, a.graphs[sh->graph].acc, sh);
+    if (sh->graph >= 0) flush_acc<DIAG, TB>(acc, a.graphs[sh->graph].acc, sh);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
@@ -2261,14 +2334,855 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 
     }
 }
 
+// ============================================================================ wide roots
+//
+// Top-level candidates of degree above the widest mask class (64 * 16 bits) are searched by
+// wide_kernel: the same method, candidate order, tree and tallies as search_kernel, in a
+// simpler form whose sets may be of any width.
+//  * Every frame, the top-level list included, maps its mask bits to positions of N(x)
+//    through orig[], and masks below the top level are compressed to |R| bits (ceil(|R|/64)
+//    words per entry), so the width shrinks with depth.
+//  * A node's R' words, the list of its bits and a child's counting-sort histogram live in
+//    per-wave global scratch; Q lists are kept whole.
+//  * Several workgroups (replicas) rebuild the same top-level list (deterministically) and
+//    claim its 64-candidate chunks from a per-candidate counter; replica 0 reports the
+//    top-level node itself.
+
+// ids[n] | hs[n] (u64) | masks[n][wf] (u64) | first[rb] | cnt[rb] | H[rb] (u64) | orig[rb] |
+// rows[rb][nw] (u64), with wf = ceil(rb / 64), nw = ceil(n / 64); 32-bit words.
+__device__ __forceinline__ uint64_t wframe_words(int n, int rb) {
+    const uint64_t wf = ((uint64_t)rb + 63u) >> 6, nw = ((uint64_t)n + 63u) >> 6;
+    uint64_t o = align2((uint32_t)n);
+    o += 2ull * (uint64_t)n;
+    o += 2ull * (uint64_t)n * wf;
+    o += 4ull * (uint64_t)rb;  // first, cnt, H
+    o += (uint64_t)rb;         // orig
+    o = (o + 1ull) & ~1ull;
+    o += 2ull * (uint64_t)rb * nw;
+    return o;
+}
+
+struct WFrameView {
+    const uint32_t *ids;
+    const uint64_t *hs;
+    const uint64_t *masks;
+    uint32_t *first;
+    uint32_t *cnt;
+    uint64_t *H;
+    uint32_t *orig;
+    uint64_t *rows;
+    int nw, wf;
+};
+
+__device__ __forceinline__ WFrameView wframe_view(uint32_t *base, int n, int rb) {
+    WFrameView v;
+    v.wf = (rb + 63) >> 6;
+    v.nw = (n + 63) >> 6;
+    uint64_t o = align2((uint32_t)n);
+    v.ids = base;
+    v.hs = reinterpret_cast<const uint64_t *>(base + o);
+    o += 2ull * (uint64_t)n;
+    v.masks = reinterpret_cast<const uint64_t *>(base + o);
+    o += 2ull * (uint64_t)n * (uint64_t)v.wf;
+    v.first = base + o;
+    o += (uint64_t)rb;
+    v.cnt = base + o;
+    o += (uint64_t)rb;
+    v.H = reinterpret_cast<uint64_t *>(base + o);
+    o += 2ull * (uint64_t)rb;
+    v.orig = base + o;
+    o += (uint64_t)rb;
+    o = (o + 1ull) & ~1ull;
+    v.rows = reinterpret_cast<uint64_t *>(base + o);
+    return v;
+}
+
+// The wave's scratch of the wide search.
+struct WCtx {
+    Ctx c;
+    uint32_t *bl;    // the bits of R' (frame bit indices), ascending
+    uint32_t *hist;  // counting-sort histogram of a child list
+    uint64_t *mR;    // R' words (frame bits)
+    uint64_t *Rr;    // R' as positions of N(x) (records)
+};
+
+// Candidates [base, base + 64) of frame F: lanes with |R'| = 1 are settled (when settle), the
+// lanes with |R'| >= 2 are returned.
+template <bool DIAG, bool ENUM, bool TB>
+__device__ __forceinline__ uint64_t light_wide(const WCtx &w, const FrameState &F, const WFrameView &v, int base,
+                                               WaveAcc &acc) {
+    const Ctx &c = w.c;
+    const int ln = lane_id();
+    const int i = base + ln;
+    const bool act = i < F.n;
+    int r = 0, b = 0;
+    if (act)
+        for (int q = 0; q < v.wf; ++q) {
+            const uint64_t x = v.masks[(size_t)i * v.wf + q];
+            if (x) {
+                r += __popcll(x);
+                b = 64 * q + __ffsll((unsigned long long)x) - 1;
+            }
+        }
+    if (TB && act) acc.dbytes += 8ull * (uint64_t)v.wf;
+    if (ENUM) return __ballot(act);
+    if (act && r == 1) {
+        const bool maximal = v.first[b] == (uint32_t)i;  // no earlier entry holds bit b
+        const uint32_t rp = v.orig[b];
+        if (maximal) {
+            acc.count += 1;
+            acc.hash += pair_hash(c.c_is_v, F.sL + v.H[b], c.hvl[rp]);
+            acc.out_ints += 2ull + (uint64_t)F.nL + (uint64_t)v.cnt[b] + 1ull;
+        }
+        if (DIAG) {
+            acc.nodes += 1;
+            if (!maximal) acc.nonmax += 1;
+            if ((uint32_t)F.level > acc.max_depth) acc.max_depth = (uint32_t)F.level;
+            const uint64_t dx = deg_of(c, v.ids[i]);
+            const uint64_t rs = 2ull + (uint64_t)c.degl[rp];
+            const uint64_t fw = F.fw - (2ull + dx);
+            acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + 1ull);
+        }
+        if (TB) acc.dbytes += 8ull + (maximal ? 24ull : 0ull);
+    }
+    return __ballot(act && r >= 2);
+}
+
+// Add a child entry's compressed mask word q (bits 64q ..) to the child's per-bit tables.
+__device__ __forceinline__ void wide_table_add(const WFrameView &v2, int q, uint64_t x, uint32_t slot, uint64_t h) {
+    while (x) {
+        const int t = 64 * q + __ffsll((unsigned long long)x) - 1;
+        x &= x - 1ull;
+        atomicMin(&v2.first[t], slot);
+        atomicAdd(&v2.cnt[t], 1u);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&v2.H[t]), (unsigned long long)h);
+    }
+}
+
+// The candidate at position i of frame F, |R'| >= 2, handled by the whole wave (maximality
+// check, expansion, report, child list).  Returns true when a child frame was written (its
+// state in C).
+template <bool DIAG, bool ENUM, bool TB>
+__device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, const WFrameView &v, int i, FrameState &C,
+                                           WaveAcc &acc) {
+    const Ctx &c = w.c;
+    const int ln = lane_id();
+    const uint64_t below = lanes_below();
+    const int wf = v.wf;
+    // R' (entry i's mask) into the scratch, and its bits in ascending order
+    int r = 0;
+    for (int q = ln; q < wf; q += 64) {
+        const uint64_t x = v.masks[(size_t)i * wf + q];
+        w.mR[q] = x;
+        r += __popcll(x);
+    }
+    r = wave_sum_i32(r);
+    wait_mem();
+    {
+        int t0 = 0;
+        for (int q = 0; q < wf; ++q) {
+            const uint64_t x = uni(w.mR[q]);
+            if (!x) continue;
+            const bool on = (x >> ln) & 1ull;
+            const uint64_t bb = __ballot(on);
+            if (on) w.bl[t0 + __popcll(bb & below)] = (uint32_t)(64 * q + ln);
+            t0 += __popcll(bb);
+        }
+        wait_mem();
+    }
+    if (TB && ln == 0) acc.dbytes += 16ull * (uint64_t)wf + 8ull * (uint64_t)r;
+
+    // maximality: an earlier entry holding all of R' -- a position below i in the AND of R''s
+    // rows; a bit of R' first held at i rules that out at once
+    bool fh = false;
+    for (int t = ln; t < r; t += 64)
+        if (v.first[w.bl[t]] == (uint32_t)i) fh = true;
+    bool nonmax = false;
+    if (!__ballot(fh)) {
+        const int wl = i >> 6;
+        for (int base = 0; base <= wl && !nonmax; base += 64) {
+            const int wd = base + ln;
+            const bool in = wd <= wl;
+            uint64_t a = in ? ~0ull : 0ull;
+            int t = 0;
+            for (; t < r; ++t) {
+                const uint32_t bt = uni(w.bl[t]);
+                if (in) a &= v.rows[(size_t)bt * v.nw + wd];
+                if ((t & 7) == 7 && !__ballot(a != 0ull)) break;
+            }
+            if (wd == wl) a &= (1ull << (i & 63)) - 1ull;
+            if (__ballot(a != 0ull)) nonmax = true;
+            if (TB && ln == 0) acc.dbytes += 8ull * (uint64_t)(t < r ? t + 1 : r) * (uint64_t)min(64, wl + 1 - base);
+        }
+    }
+    uint64_t dx = 0, rs = 0;
+    if (DIAG) {
+        dx = deg_of(c, v.ids[i]);
+        uint64_t t2 = 0;
+        for (int t = ln; t < r; t += 64) t2 += 2ull + (uint64_t)c.degl[v.orig[w.bl[t]]];
+        rs = wave_sum_u64(t2);
+        if (ln == 0) {
+            acc.nodes += 1;
+            if ((uint32_t)F.level > acc.max_depth) acc.max_depth = (uint32_t)F.level;
+        }
+    }
+    if (nonmax) {
+        if (DIAG && ln == 0) {
+            acc.nonmax += 1;
+            const uint64_t fw = F.fw - (2ull + dx);
+            acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r);
+        }
+        return false;
+    }
+
+    // maximal: per word of positions the OR of R''s rows lists the entries meeting R', the AND
+    // those holding all of it (after i; they join L'); the others, Q' before i and P' after,
+    // go to stu in list order
+    int nu = 0, ne_l = 0, qn_l = 0;
+    uint64_t exps = 0;
+    {
+        const int wi = i >> 6;
+        const uint64_t bi = 1ull << (i & 63);
+        for (int base = 0; base < v.nw; base += 64) {
+            const int wd = base + ln;
+            const bool in = wd < v.nw;
+            uint64_t u = 0ull, a = in ? ~0ull : 0ull;
+            for (int t = 0; t < r; ++t) {
+                const uint32_t bt = uni(w.bl[t]);
+                if (in) {
+                    const uint64_t x = v.rows[(size_t)bt * v.nw + wd];
+                    u |= x;
+                    a &= x;
+                }
+            }
+            if (wd == wi) {
+                u &= ~bi;
+                a &= ~bi;
+            }
+            ne_l += __popcll(a);
+            for (uint64_t f = a; f;) {
+                const int b = __ffsll((unsigned long long)f) - 1;
+                f &= f - 1ull;
+                exps += v.hs[64 * wd + b];
+            }
+            uint64_t qp = u & ~a;
+            qn_l += __popcll(qp & (wd < wi ? ~0ull : (wd == wi ? bi - 1ull : 0ull)));
+            const int pc = __popcll(qp);
+            const int incl = wave_incl_scan(pc);
+            int at = nu + incl - pc;
+            while (qp) {
+                const int b = __ffsll((unsigned long long)qp) - 1;
+                qp &= qp - 1ull;
+                c.stu[at++] = (uint32_t)(64 * wd + b);
+            }
+            nu += last_lane(incl);
+        }
+    }
+    const int qn = wave_sum_i32(qn_l);
+    const int ne = wave_sum_i32(ne_l);
+    const int pn = nu - qn;
+    wait_mem();  // stu is read by other lanes below
+    // histogram of the P' counts |mask n R'|
+    for (int b = ln; b <= r; b += 64) w.hist[b] = 0u;
+    wait_mem();
+    uint64_t fwc = 0;
+    for (int base = 0; base < nu; base += 64) {
+        const int j = base + ln;
+        if (j < nu) {
+            const int k = (int)c.stu[j];
+            if (j >= qn) {
+                int cnt = 0;
+                for (int q = 0; q < wf; ++q) {
+                    const uint64_t mq = w.mR[q];
+                    if (mq) cnt += __popcll(v.masks[(size_t)k * wf + q] & mq);
+                }
+                atomicAdd(&w.hist[cnt], 1u);
+            }
+            if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
+        }
+    }
+    see_atomics();  // the histogram was built with atomics
+    if (TB && ln == 0)
+        acc.dbytes += 8ull * (uint64_t)r * (uint64_t)v.nw + 8ull * (uint64_t)ne + 8ull * (uint64_t)nu +
+                      (uint64_t)pn * 8ull * (uint64_t)wf + 16ull * (uint64_t)r;
+
+    // report (L', R')
+    const uint64_t sL = F.sL + v.hs[i] + wave_sum_u64(exps);
+    uint64_t sr = 0;
+    for (int t = ln; t < r; t += 64) sr += c.hvl[v.orig[w.bl[t]]];
+    sr = wave_sum_u64(sr);
+    const int nL = F.nL + 1 + ne;
+    if (ln == 0) {
+        acc.count += 1;
+        acc.hash += pair_hash(c.c_is_v, sL, sr);
+        acc.out_ints += 2ull + (uint64_t)nL + (uint64_t)r;
+    }
+    if (ENUM) {
+        for (int q = ln; q < c.Wroot; q += 64) w.Rr[q] = 0ull;
+        wait_mem();
+        for (int t = ln; t < r; t += 64) {
+            const uint32_t rp = v.orig[w.bl[t]];
+            atomicOr(reinterpret_cast<unsigned long long *>(&w.Rr[rp >> 6]), 1ull << (rp & 63));
+        }
+        see_atomics();
+        write_record(c, w.Rr, nL, r);
+    }
+    if (DIAG && ln == 0) {
+        const uint64_t fw = F.fw - (2ull + dx);
+        acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + (uint64_t)r + (uint64_t)pn +
+                             (uint64_t)qn);
+    }
+    if (pn == 0) return false;
+
+    // child list: Q' in list order, then P' stably sorted by count; masks compressed to the r
+    // bits of R' (child bit t = frame bit bl[t]), mapped to N(x) through orig
+    const int n2 = nu, wf2 = (r + 63) >> 6;
+    const uint32_t off2 = F.top;
+    const uint64_t top2 = ((uint64_t)off2 + wframe_words(n2, r) + 1ull) & ~1ull;
+    if ((int64_t)top2 > c.scap) {
+        if (ln == 0) atomicOr(c.flags, (unsigned int)FLAG_STACK_OVERFLOW);
+        return false;
+    }
+    uint32_t *cb = c.stk + off2;
+    const WFrameView v2 = wframe_view(cb, n2, r);
+    uint32_t *ids2 = cb;
+    uint64_t *hs2 = const_cast<uint64_t *>(v2.hs);
+    uint64_t *masks2 = const_cast<uint64_t *>(v2.masks);
+    int carry = qn;
+    for (int base = 0; base <= r; base += 64) {
+        const int b = base + ln;
+        const int h = b <= r ? (int)w.hist[b] : 0;
+        const int incl = wave_incl_scan(h);
+        if (b <= r) w.hist[b] = (uint32_t)(carry + incl - h);
+        carry += last_lane(incl);
+    }
+    for (int t = ln; t < r; t += 64) {
+        v2.orig[t] = v.orig[w.bl[t]];
+        v2.first[t] = kNone;
+        v2.cnt[t] = 0u;
+        v2.H[t] = 0ull;
+    }
+    wait_mem();
+    const int nbits = r <= 1 ? 1 : 32 - __clz(r - 1);
+    for (int base = 0; base < nu; base += 64) {
+        const int j = base + ln;
+        const bool act = j < nu;
+        const int k = act ? (int)c.stu[j] : 0;
+        const bool inp = act && j >= qn;
+        int cnt = 0;
+        if (inp)
+            for (int q = 0; q < wf; ++q) {
+                const uint64_t mq = w.mR[q];
+                if (mq) cnt += __popcll(v.masks[(size_t)k * wf + q] & mq);
+            }
+        uint32_t slot = (uint32_t)j;  // Q' entries keep their list order
+        if (__ballot(inp)) {
+            // stable placement among equal counts: lanes with the same count, in lane order
+            uint64_t same = __ballot(inp);
+            for (int bit = 0; bit < nbits; ++bit) {
+                const bool on = (cnt >> bit) & 1;
+                const uint64_t bb = __ballot(inp && on);
+                same &= on ? bb : ~bb;
+            }
+            uint32_t start = 0;
+            if (inp) start = w.hist[cnt];
+            if (inp) {
+                slot = start + (uint32_t)__popcll(same & below);
+                if ((same >> ln) == 1ull) w.hist[cnt] = start + (uint32_t)__popcll(same);
+            }
+            see_atomics();  // (the next round reads the updated histogram entries)
+        }
+        if (act) {
+            ids2[slot] = v.ids[k];
+            const uint64_t h = v.hs[k];
+            hs2[slot] = h;
+            uint64_t ow = 0;
+            int t = 0;
+            for (int q = 0; q < wf; ++q) {
+                uint64_t mq = w.mR[q];
+                if (!mq) continue;
+                const uint64_t x = v.masks[(size_t)k * wf + q];
+                while (mq) {
+                    const int p = __ffsll((unsigned long long)mq) - 1;
+                    mq &= mq - 1ull;
+                    ow |= ((x >> p) & 1ull) << (t & 63);
+                    ++t;
+                    if ((t & 63) == 0) {
+                        masks2[(size_t)slot * wf2 + ((t >> 6) - 1)] = ow;
+                        wide_table_add(v2, (t >> 6) - 1, ow, slot, h);
+                        ow = 0ull;
+                    }
+                }
+            }
+            if (t & 63) {
+                masks2[(size_t)slot * wf2 + (t >> 6)] = ow;
+                wide_table_add(v2, t >> 6, ow, slot, h);
+            }
+        }
+    }
+    see_atomics();
+    // position rows: one 64-entry block of one mask word per transpose
+    for (int q = 0; q < wf2; ++q)
+        for (int blk = 0; blk < v2.nw; ++blk) {
+            const int e = 64 * blk + ln;
+            const uint64_t t = wave_transpose64(e < n2 ? masks2[(size_t)e * wf2 + q] : 0ull);
+            if (64 * q + ln < r) v2.rows[(size_t)(64 * q + ln) * v2.nw + blk] = t;
+        }
+    wait_mem();
+    if (TB && ln == 0)
+        acc.dbytes += (uint64_t)n2 * (4ull + 16ull + 8ull * (uint64_t)wf2 + 8ull * (uint64_t)wf) + 32ull * (uint64_t)r +
+                      16ull * (uint64_t)r * (uint64_t)n2 / 64ull + 8ull * (uint64_t)r * (uint64_t)v2.nw;
+    C.off = off2;
+    C.top = (uint32_t)top2;
+    C.n = n2;
+    C.nq = qn;
+    C.level = F.level + 1;
+    C.nL = nL;
+    C.wf = wf2;
+    C.narrow = 1;
+    C.chunk = qn - 64;
+    C.rbits = r;
+    C.heavy = 0ull;
+    C.sL = sL;
+    C.fw = DIAG ? wave_sum_u64(fwc) : 0ull;
+    return true;
+}
+
+// Stable counting sort by key, as wave_sort_by_key, with the histogram in global memory.
+template <typename Put>
+__device__ __forceinline__ void wave_sort_by_key_g(const uint32_t *src, const uint32_t *key_of, int n, int nbins,
+                                                   uint32_t *hist, Put put) {
+    const int ln = lane_id();
+    const uint64_t below = lanes_below();
+    for (int b = ln; b < nbins; b += 64) hist[b] = 0u;
+    wait_mem();
+    for (int base = 0; base < n; base += 64) {
+        const int j = base + ln;
+        if (j < n) atomicAdd(&hist[key_of[j]], 1u);
+    }
+    see_atomics();
+    int carry = 0;
+    for (int base = 0; base < nbins; base += 64) {
+        const int b = base + ln;
+        const int h = b < nbins ? (int)hist[b] : 0;
+        const int incl = wave_incl_scan(h);
+        if (b < nbins) hist[b] = (uint32_t)(carry + incl - h);
+        carry += last_lane(incl);
+    }
+    wait_mem();
+    const int nbits = nbins <= 1 ? 1 : 32 - __clz(nbins - 1);
+    for (int base = 0; base < n; base += 64) {
+        const int j = base + ln;
+        const bool act = j < n;
+        const uint32_t key = act ? key_of[j] : 0u;
+        const uint32_t p = act ? src[j] : 0u;
+        uint64_t same = __ballot(act);
+        for (int bit = 0; bit < nbits; ++bit) {
+            const bool on = (key >> bit) & 1u;
+            const uint64_t bb = __ballot(act && on);
+            same &= on ? bb : ~bb;
+        }
+        uint32_t start = 0;
+        if (act) start = hist[key];
+        if (act) {
+            put(start + (uint32_t)__popcll(same & below), p);
+            if ((same >> ln) == 1ull) hist[key] = start + (uint32_t)__popcll(same);
+        }
+        see_atomics();  // (the next round reads the updated histogram entries)
+    }
+}
+
+template <bool DIAG, bool ENUM, bool TB>
+__global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
+    extern __shared__ unsigned char lds_raw[];
+    WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
+    const int tid = threadIdx.x, nt = blockDim.x, wid = uni(tid >> 6), nw = nt >> 6, ln = lane_id();
+    const WideLayout &L = a.wl;
+    const int Wx = L.Wx;
+    char *wg = a.warena + (size_t)blockIdx.x * L.wg_bytes;
+    uint64_t *bitmap = reinterpret_cast<uint64_t *>(wg + L.off_bitmap);
+    uint32_t *bpre = reinterpret_cast<uint32_t *>(wg + L.off_bpre);
+    uint64_t *M = reinterpret_cast<uint64_t *>(wg + L.off_M);
+    int32_t *gid = reinterpret_cast<int32_t *>(wg + L.off_gid);
+    uint32_t *cnt1 = reinterpret_cast<uint32_t *>(wg + L.off_cnt);
+    uint64_t *hvl = reinterpret_cast<uint64_t *>(wg + L.off_hv);
+    uint32_t *degl = reinterpret_cast<uint32_t *>(wg + L.off_deg);
+    uint32_t *t1v = reinterpret_cast<uint32_t *>(wg + L.off_t1v);
+    uint32_t *t1c = reinterpret_cast<uint32_t *>(wg + L.off_t1c);
+    uint32_t *whist = reinterpret_cast<uint32_t *>(wg + L.off_whist);
+    uint32_t *s1 = reinterpret_cast<uint32_t *>(wg + L.off_S1);
+    char *wv = wg + L.off_waves + (size_t)wid * L.wave_bytes;
+    FrameState *hdr = reinterpret_cast<FrameState *>(wv + L.off_w_hdr);
+
+    WCtx w;
+    Ctx &c = w.c;
+    c.gid = gid;
+    c.M = M;
+    c.hvl = hvl;
+    c.degl = degl;
+    c.c_off = a.c_off;
+    c.s1 = s1;
+    c.stk = reinterpret_cast<uint32_t *>(wv + L.off_w_stack);
+    c.stu = reinterpret_cast<uint32_t *>(wv + L.off_w_u);
+    c.scap = L.scap;
+    c.c_is_v = 0;
+    c.cbase = 0;
+    c.obase = 0;
+    c.Wroot = Wx;
+    c.rec = a.rec;
+    c.rec_cap = a.rec_cap;
+    c.rec_offs = a.rec_offs;
+    c.rec_offs_cap = a.rec_offs_cap;
+    c.acc = a.acc;
+    c.flags = a.flags;
+    w.bl = reinterpret_cast<uint32_t *>(wv + L.off_w_bl);
+    w.hist = reinterpret_cast<uint32_t *>(wv + L.off_w_hist);
+    w.mR = reinterpret_cast<uint64_t *>(wv + L.off_w_mr);
+    w.Rr = reinterpret_cast<uint64_t *>(wv + L.off_w_rr);
+
+    WaveAcc acc{};
+    const int ucap = a.dims.ucap;
+    const int64_t nroots = hi - lo;
+    const int64_t ntasks = nroots * (int64_t)L.reps;
+    if (tid < 16) sh->red[tid] = 0ull;
+    if (tid == 0) sh->graph = -1;
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) {
+            const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh->task = (f & FLAG_RERUN) ? ~0ull : (unsigned long long)atomicAdd(counter, 1u);
+        }
+        __syncthreads();
+        const unsigned long long tt = sh->task;
+        if (tt == ~0ull || (int64_t)tt >= ntasks) break;
+        const int64_t ri = (int64_t)tt % nroots;   // top-level candidates of largest degree first
+        const bool owner = (int64_t)tt < nroots;   // replica 0 reports the top-level node
+        int g = 0;
+        int64_t k;
+        if (a.tasks) {
+            const unsigned long long tk = a.tasks[lo + ri];
+            g = (int)(tk >> 32);
+            k = (int64_t)(tk & 0xFFFFFFFFull);
+        } else {
+            k = hi - 1 - ri;
+        }
+        if (g != sh->graph) {
+            if (sh->graph >= 0) flush_acc<DIAG, TB>(acc, a.graphs[sh->graph].acc, sh);
+            __syncthreads();
+            if (tid == 0) sh->graph = g;
+            __syncthreads();
+        }
+        const GraphDesc gd = a.graphs[g];
+        c.c_is_v = gd.c_is_v;
+        c.cbase = gd.cbase;
+        c.obase = gd.obase;
+        const int nwords = gd.nwords;
+        const int32_t x = gd.order[k];
+        const int32_t rbx = a.c_off[x];
+        const int32_t d = a.c_off[x + 1] - rbx;
+        const int32_t *row = a.c_adj + rbx;
+        c.row = row;
+        c.x_root = x;
+        const int wd = (d + 63) >> 6;
+
+        // -- reverse scan 1: mark the ranks of all 2-hop neighbours of x
+        for (int j = wid; j < d; j += nw) {
+            const int32_t wv2 = row[j];
+            const int32_t e0 = a.o_off[wv2], e1 = a.o_off[wv2 + 1];
+            for (int p = e0 + ln; p < e1; p += 64) {
+                const int32_t v = a.o_adj[p];
+                if (v != x) {
+                    const int32_t rk = a.rank[v];
+                    atomicOr(reinterpret_cast<unsigned long long *>(&bitmap[rk >> 6]), 1ull << (rk & 63));
+                }
+            }
+        }
+        uint64_t hv_local = 0, rs_local = 0;
+        for (int j = tid; j < d; j += nt) {
+            const int32_t wv2 = row[j];
+            const uint64_t h = hr(c, wv2);
+            hvl[j] = h;
+            hv_local += h;
+            const uint32_t dw = (uint32_t)(a.o_off[wv2 + 1] - a.o_off[wv2]);
+            degl[j] = dw;
+            rs_local += 2ull + dw;
+        }
+        if (tid == 0) {
+            sh->nonmax = 0;
+            sh->pcount = 0;
+            sh->exps = 0;
+            sh->fw1 = 0;
+            sh->hvsum = 0;
+            sh->rs1 = 0;
+            sh->nexp = 0;
+        }
+        __syncthreads();
+        see_atomics();
+        hv_local = wave_sum_u64(hv_local);
+        rs_local = wave_sum_u64(rs_local);
+        if (ln == 0) {
+            lds_add(&sh->hvsum, hv_local);
+            lds_add(&sh->rs1, rs_local);
+        }
+        block_popcount_prefix(bitmap, bpre, nwords, sh);
+        const int s0 = uni(sh->s0);
+        if (s0 > ucap) {
+            for (int q = tid; q < nwords; q += nt) bitmap[q] = 0ull;
+            if (tid == 0) {
+                atomicOr(a.flags, (unsigned int)FLAG_UNIVERSE_OVERFLOW);
+                atomicMax(&a.acc[ACC_NEED_UCAP], (unsigned long long)s0);
+            }
+            __syncthreads();
+            continue;
+        }
+        const int nq0 = (int)bpre[k >> 6] + __popcll(bitmap[k >> 6] & ((1ull << (k & 63)) - 1ull));
+        c.s0 = s0;
+        for (int q = tid; q < nwords; q += nt) {
+            uint64_t bits = bitmap[q];
+            uint32_t pos = bpre[q];
+            while (bits) {
+                const int b = __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1ull;
+                gid[pos++] = gd.order[q * 64 + b];
+            }
+        }
+        for (size_t q = tid; q < (size_t)s0 * Wx; q += nt) M[q] = 0ull;
+        wait_mem();
+        __syncthreads();
+        // -- reverse scan 2: M[v] gets bit j for every w_j in N(x) adjacent to v
+        for (int j = wid; j < d; j += nw) {
+            const int32_t wv2 = row[j];
+            const int32_t e0 = a.o_off[wv2], e1 = a.o_off[wv2 + 1];
+            for (int p = e0 + ln; p < e1; p += 64) {
+                const int32_t v = a.o_adj[p];
+                if (v != x) {
+                    const int32_t rk = a.rank[v];
+                    const uint32_t li =
+                        bpre[rk >> 6] + (uint32_t)__popcll(bitmap[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
+                    atomicOr(reinterpret_cast<unsigned long long *>(&M[(size_t)li * Wx + (j >> 6)]), 1ull << (j & 63));
+                }
+            }
+        }
+        __syncthreads();
+        see_atomics();
+        for (int q = tid; q < nwords; q += nt) bitmap[q] = 0ull;
+        // -- the top-level node for x: counts, maximality against earlier ranks, expansion
+        {
+            bool nm = false;
+            int pc = 0, nexp = 0;
+            uint64_t ex = 0, fw = 0;
+            for (int li = tid; li < s0; li += nt) {
+                int cc = 0;
+                for (int q = 0; q < wd; ++q) cc += __popcll(M[(size_t)li * Wx + q]);
+                cnt1[li] = (uint32_t)cc;
+                const int32_t gv = gid[li];
+                const uint64_t dg = DIAG ? 2ull + (uint64_t)(a.c_off[gv + 1] - a.c_off[gv]) : 0ull;
+                if (li < nq0) {
+                    if (cc == d) nm = true;
+                    else fw += dg;
+                } else if (cc == d) {
+                    ex += hl(c, gv);
+                    ++nexp;
+                } else {
+                    ++pc;
+                    fw += dg;
+                }
+            }
+            if (__ballot(nm) && ln == 0) atomicOr(&sh->nonmax, 1);
+            ex = wave_sum_u64(ex);
+            fw = wave_sum_u64(fw);
+            pc = wave_sum_i32(pc);
+            nexp = wave_sum_i32(nexp);
+            if (ln == 0) {
+                atomicAdd(&sh->pcount, pc);
+                atomicAdd(&sh->nexp, nexp);
+                lds_add(&sh->exps, ex);
+                lds_add(&sh->fw1, fw);
+            }
+        }
+        wait_mem();
+        __syncthreads();
+        const bool root_nonmax = uni(sh->nonmax) != 0;
+        const int P1 = uni(sh->pcount);
+        if (tid == 0 && owner) {
+            const uint64_t dx = (uint64_t)d;
+            if (DIAG) {
+                acc.nodes += 1;
+                if (acc.max_depth < 1) acc.max_depth = 1;
+                const uint64_t fwtop = gd.total_fw - (2ull + dx);
+                const uint64_t rs = sh->rs1;
+                uint64_t b = (2ull + dx) + (rs < fwtop ? rs : fwtop) + (uint64_t)(gd.ncand - 1) + dx;
+                if (root_nonmax) acc.nonmax += 1;
+                else b += (uint64_t)P1 + (uint64_t)nq0;
+                acc.bytes += 4ull * b;
+            }
+            if (TB) {
+                const uint64_t wk = (uint64_t)sh->rs1 - 2ull * dx, su = (uint64_t)s0;
+                acc.dbytes += 4ull * (dx + 2ull) + 16ull * dx + 44ull * wk + 12ull * dx + 32ull * (uint64_t)nwords +
+                              8ull * su + 16ull * (uint64_t)wd * su + 8ull * su;
+            }
+            if (!root_nonmax) {
+                acc.count += 1;
+                acc.hash += pair_hash(c.c_is_v, hl(c, x) + sh->exps, sh->hvsum);
+                acc.out_ints += 2ull + (uint64_t)(1 + sh->nexp) + (uint64_t)d;
+            }
+        }
+        if (ENUM && !root_nonmax && owner && wid == 0) {
+            for (int q = ln; q < Wx; q += 64) {
+                const int bits = d - 64 * q;
+                w.Rr[q] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : ((1ull << bits) - 1ull));
+            }
+            wait_mem();
+            write_record(c, w.Rr, 1 + sh->nexp, d);
+        }
+        if (root_nonmax || P1 == 0) {
+            __syncthreads();
+            continue;
+        }
+        // -- the top-level list as a frame: Q1 (earlier ranks) ++ P1 stably sorted by count,
+        //    masks over the positions of N(x), per-bit tables, rows
+        const int n1 = nq0 + P1;
+        const WFrameView v1 = wframe_view(s1, n1, d);
+        uint32_t *ids1 = s1;
+        for (int li = tid; li < nq0; li += nt) ids1[li] = (uint32_t)li;
+        if (wid == 0) {
+            int pn = 0;
+            for (int base = nq0; base < s0; base += 64) {
+                const int li = base + ln;
+                const bool act2 = li < s0;
+                const uint32_t cc = act2 ? cnt1[li] : 0u;
+                const bool pk = act2 && (int)cc < d;
+                const uint64_t pb = __ballot(pk);
+                if (pk) {
+                    const int p = pn + __popcll(pb & lanes_below());
+                    t1v[p] = (uint32_t)li;
+                    t1c[p] = cc;
+                }
+                pn += __popcll(pb);
+            }
+            wait_mem();
+            wave_sort_by_key_g(t1v, t1c, pn, d, whist, [&](uint32_t slot, uint32_t li) { ids1[nq0 + slot] = li; });
+        }
+        for (int b = tid; b < d; b += nt) {
+            v1.first[b] = kNone;
+            v1.cnt[b] = 0u;
+            v1.H[b] = 0ull;
+            v1.orig[b] = (uint32_t)b;
+        }
+        wait_mem();
+        __syncthreads();
+        uint64_t *masks1 = const_cast<uint64_t *>(v1.masks);
+        uint64_t *hs1 = const_cast<uint64_t *>(v1.hs);
+        for (int j = tid; j < n1; j += nt) {
+            const uint32_t li = ids1[j];
+            const uint64_t h = hl(c, gid[li]);
+            hs1[j] = h;
+            for (int q = 0; q < wd; ++q) {
+                uint64_t mm = M[(size_t)li * Wx + q];
+                masks1[(size_t)j * wd + q] = mm;
+                while (mm) {
+                    const int b = 64 * q + __ffsll((unsigned long long)mm) - 1;
+                    mm &= mm - 1ull;
+                    atomicMin(&v1.first[b], (uint32_t)j);
+                    atomicAdd(&v1.cnt[b], 1u);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&v1.H[b]), (unsigned long long)h);
+                }
+            }
+        }
+        __syncthreads();
+        see_atomics();
+        for (int job = wid; job < v1.nw * wd; job += nw) {
+            const int blk = job / wd, q = job - blk * wd;
+            const int e = 64 * blk + ln;
+            const uint64_t t = wave_transpose64(e < n1 ? masks1[(size_t)e * wd + q] : 0ull);
+            if (64 * q + ln < d) v1.rows[(size_t)(64 * q + ln) * v1.nw + blk] = t;
+        }
+        wait_mem();
+        __syncthreads();
+        if (TB && tid == 0 && owner)
+            acc.dbytes += 4ull * (uint64_t)nq0 + 4ull * (uint64_t)(s0 - nq0) + 20ull * (uint64_t)P1 +
+                          (uint64_t)n1 * (24ull + 16ull * (uint64_t)wd) + 32ull * (uint64_t)d +
+                          8ull * (uint64_t)n1 * (uint64_t)wd + 8ull * (uint64_t)d * (uint64_t)v1.nw;
+
+        FrameState top;
+        top.off = kShared;
+        top.top = 0;
+        top.n = n1;
+        top.nq = nq0;
+        top.level = 2;
+        top.nL = 1 + uni(sh->nexp);
+        top.wf = wd;
+        top.narrow = 1;
+        top.chunk = 0;
+        top.rbits = d;
+        top.heavy = 0ull;
+        top.sL = hl(c, x) + uni((uint64_t)sh->exps);
+        top.fw = uni((uint64_t)sh->fw1);
+        const int nch = (P1 + 63) >> 6;
+
+        // -- chunks of the top-level list, claimed by every wave of every replica; each wave
+        //    searches depth-first below the candidates of its chunk
+        bool aborted = false;
+        for (;;) {
+            int q = 0;
+            if (ln == 0) q = (int)atomicAdd(&a.wide_items[ri], 1u);
+            q = __builtin_amdgcn_readlane(q, 0);
+            if (q >= nch) break;
+            if (uni(__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & FLAG_RERUN) break;
+            FrameState cur = top;
+            cur.chunk = nq0 + 64 * q;
+            cur.heavy = light_wide<DIAG, ENUM, TB>(w, cur, v1, cur.chunk, acc);
+            int depth = 0;
+            while (!aborted) {
+                const WFrameView v = wframe_view(frame_base(c, cur.off), cur.n, cur.rbits);
+                if (cur.heavy == 0ull) {
+                    if (depth == 0) break;  // the chunk is done
+                    const int base = cur.chunk + 64;
+                    if (base >= cur.n) {
+                        --depth;
+                        cur = uni_frame(hdr[depth]);
+                        continue;
+                    }
+                    cur.chunk = base;
+                    cur.heavy = light_wide<DIAG, ENUM, TB>(w, cur, v, base, acc);
+                    continue;
+                }
+                const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
+                cur.heavy &= cur.heavy - 1ull;
+                FrameState ch;
+                if (heavy_wide<DIAG, ENUM, TB>(w, cur, v, cur.chunk + lane, ch, acc)) {
+                    if (depth + 1 >= L.maxdepth) {
+                        if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
+                        aborted = true;
+                        break;
+                    }
+                    hdr[depth] = cur;  // every lane stores the same header
+                    wait_mem();
+                    if (TB && ln == 0) acc.dbytes += 2ull * sizeof(FrameState);
+                    ++depth;
+                    cur = ch;
+                } else if (__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_STACK_OVERFLOW) {
+                    aborted = true;
+                }
+            }
+            if (aborted) break;
+        }
+        __syncthreads();
+    }
+    if (sh->graph >= 0) flush_acc<DIAG, TB>(acc, a.graphs[sh->graph].acc, sh);
+}
+
 size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + hist_region_bytes(64 * W, waves) + (size_t)waves * kWaveLds; }
 
 template <int W>
-hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, int64_t lo, int64_t hi, unsigned int *counter,
+hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi, unsigned int *counter,
                     int grid, int waves, hipStream_t s) {
     dim3 g(grid), b(64 * waves);
     const size_t lds = lds_bytes(W, waves);
-    if (diag && enumerate)
+    if (tb && !diag && !enumerate)
+        hipLaunchKernelGGL((search_kernel<W, false, false, true>), g, b, lds, s, a, lo, hi, counter);
+    else if (diag && enumerate)
         hipLaunchKernelGGL((search_kernel<W, true, true>), g, b, lds, s, a, lo, hi, counter);
     else if (diag)
         hipLaunchKernelGGL((search_kernel<W, true, false>), g, b, lds, s, a, lo, hi, counter);
@@ -2310,6 +3224,67 @@ int search_occupancy(int W, bool diag, bool enumerate, int waves) {
     }
 }
 
+WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdepth, int waves) {
+    WideLayout L{};
+    L.Wx = Wx;
+    L.scap = scap;
+    L.maxdepth = maxdepth;
+    const size_t ucap = (size_t)d.ucap, W = (size_t)Wx, bits = 64 * W;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    L.off_bitmap = take((size_t)d.nwords * 8);
+    L.off_bpre = take(((size_t)d.nwords + 1) * 4);
+    L.off_M = take(ucap * W * 8);
+    L.off_gid = take(ucap * 4);
+    L.off_cnt = take(ucap * 4);
+    L.off_hv = take(bits * 8);
+    L.off_deg = take(bits * 4);
+    L.off_t1v = take(ucap * 4);
+    L.off_t1c = take(ucap * 4);
+    L.off_whist = take((bits + 1) * 4);
+    // the top-level list: ids | hs | masks | first, cnt | H | orig | rows (see wframe_view)
+    const size_t s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 4 * bits + bits + 2 + 2 * bits * ((ucap + 63) / 64);
+    L.off_S1 = take(s1_words * 4);
+    L.off_waves = o;
+    size_t w = 0;
+    auto wtake = [&](size_t bytes) {
+        const size_t at = w;
+        w = align_up(w + bytes, 256);
+        return at;
+    };
+    L.off_w_stack = wtake((size_t)scap * 4);
+    L.off_w_u = wtake(ucap * 4);
+    L.off_w_bl = wtake(bits * 4);
+    L.off_w_hist = wtake((bits + 2) * 4);
+    L.off_w_mr = wtake(W * 8);
+    L.off_w_rr = wtake(W * 8);
+    L.off_w_hdr = wtake((size_t)maxdepth * sizeof(FrameState));
+    L.wave_bytes = w;
+    L.wg_bytes = align_up(o + (size_t)waves * w, 4096);
+    return L;
+}
+
+hipError_t launch_wide(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi,
+                       unsigned int *counter, int grid, int waves, hipStream_t s) {
+    dim3 g(grid), b(64 * waves);
+    const size_t lds = sizeof(WGShared);
+    if (tb && !diag && !enumerate)
+        hipLaunchKernelGGL((wide_kernel<false, false, true>), g, b, lds, s, a, lo, hi, counter);
+    else if (diag && enumerate)
+        hipLaunchKernelGGL((wide_kernel<true, true, false>), g, b, lds, s, a, lo, hi, counter);
+    else if (diag)
+        hipLaunchKernelGGL((wide_kernel<true, false, false>), g, b, lds, s, a, lo, hi, counter);
+    else if (enumerate)
+        hipLaunchKernelGGL((wide_kernel<false, true, false>), g, b, lds, s, a, lo, hi, counter);
+    else
+        hipLaunchKernelGGL((wide_kernel<false, false, false>), g, b, lds, s, a, lo, hi, counter);
+    return hipGetLastError();
+}
+
 ArenaLayout search_layout(const SearchDims &d) {
     ArenaLayout L{};
     const size_t ucap = (size_t)d.ucap, W = (size_t)d.Wmax, bits = 64 * W;
@@ -2349,14 +3324,14 @@ ArenaLayout search_layout(const SearchDims &d) {
     return L;
 }
 
-hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, int64_t lo, int64_t hi,
+hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi,
                          unsigned int *counter, int grid, int waves, hipStream_t s) {
     switch (W) {
-        case 1: return launch_w<1>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
-        case 2: return launch_w<2>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
-        case 4: return launch_w<4>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
-        case 8: return launch_w<8>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
-        case 16: return launch_w<16>(a, diag, enumerate, lo, hi, counter, grid, waves, s);
+        case 1: return launch_w<1>(a, diag, enumerate, tb, lo, hi, counter, grid, waves, s);
+        case 2: return launch_w<2>(a, diag, enumerate, tb, lo, hi, counter, grid, waves, s);
+        case 4: return launch_w<4>(a, diag, enumerate, tb, lo, hi, counter, grid, waves, s);
+        case 8: return launch_w<8>(a, diag, enumerate, tb, lo, hi, counter, grid, waves, s);
+        case 16: return launch_w<16>(a, diag, enumerate, tb, lo, hi, counter, grid, waves, s);
         default: return hipErrorInvalidValue;
     }
 }

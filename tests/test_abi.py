@@ -133,3 +133,19 @@ def test_server_rejects_bad_options():
     with pytest.raises(m.MbeError) as e:
         m.Server(slots=99)
     assert e.value.code == -1
+
+
+def test_batch_totals_past_int32_refused_before_device_work():
+    # the same host arrays repeated until the packed edge count passes 2^31 - 1: refused with
+    # MBE_ERR_INVALID_ARG by the 64-bit size check, before any packing or device work
+    import paper_2401_05039_amd as m
+    g = gg.erdos_renyi_m(1000, 1000, 1_000_000, 5)
+    n = (2**31) // g.n_edges + 1
+    with pytest.raises(m.MbeError) as e:
+        m.mbe_count_batch([g] * n, m.Options(no_validate=True))
+    assert e.value.code == -1
+    # ids past int32 too: many copies of a wide, sparse graph
+    h = gg.from_edges(2_000_000, 1_000_000, [0], [0])
+    with pytest.raises(m.MbeError) as e:
+        m.mbe_count_batch([h] * 2200, m.Options(no_validate=True))
+    assert e.value.code == -1

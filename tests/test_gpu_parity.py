@@ -125,13 +125,69 @@ def test_mask_width_classes(mbe, orc, deg):
     _check(mbe, orc, g, f"width{deg}")
 
 
-def test_degree_above_mask_width_is_refused(mbe):
-    g = gg.complete(2, 1025)
-    _say("degree 1025")
-    with pytest.raises(mbe.MbeError) as e:
-        mbe.mbe_count(g)
-    assert e.value.code == -6
-    assert mbe.mbe_count(gg.complete(2, 1024))["count"] == 1
+# ----------------------------------------------------------------------------- wide top-level candidates
+
+def _wide(i):
+    # hubs of degree 1025 .. 4500 (above the widest fixed mask class) with random
+    # neighbourhoods: deep subtrees whose frames are wider than 1024 bits at the top
+    specs = [(200, 5000, np.linspace(1100, 4500, 12), 0.002, 4),
+             (150, 4000, np.linspace(1030, 3900, 16), 0.003, 5),
+             (120, 3000, np.linspace(1025, 2900, 10), 0.02, 6)]
+    nu, nv, degs, p, seed = specs[i]
+    return gg.wide_hubs(nu, nv, [int(d) for d in degs], p, seed)
+
+
+def test_wide_degree_boundary(mbe, orc):
+    # 1024 is the widest fixed class, 1025 the first wide candidate; the chain puts the last
+    # 76 of its candidates in the wide search, each expanding every later one
+    for g in (gg.complete(2, 1024), gg.complete(2, 1025), gg.complete(3, 5000), gg.complete_minus_edge(3, 2000),
+              gg.chain(1100), gg.transpose(gg.chain(1100))):
+        _check(mbe, orc, g, g.name)
+
+
+@pytest.mark.parametrize("i", range(3))
+def test_wide_top_level_candidates(mbe, orc, i):
+    g = _wide(i)
+    base = _check(mbe, orc, g, f"wide{i}")
+    # grid 1: one workgroup takes every wide candidate in turn; small grids share a candidate's
+    # chunks among few replicas
+    for waves, grid, sk in ((8, 1, 2), (4, 3, 3), (2, 0, 1), (8, 0, 3)):
+        r = mbe.mbe_count(g, mbe.Options(wg_waves=waves, grid=grid, steal_k=sk, diagnostics=True))
+        for k in DIAG_KEYS:
+            assert r[k] == base[k], (i, waves, grid, sk, k)
+    # the top-level ranges of the wide candidates add up
+    n = orc.num_roots(g)
+    parts = [mbe.mbe_count(g, mbe.Options(root_lo=lo, root_hi=hi)) for lo, hi in ((0, n - 5), (n - 5, n - 2), (n - 2, n))]
+    assert sum(p["count"] for p in parts) == base["count"]
+    assert sum(p["hash"] for p in parts) % (1 << 64) == base["hash"]
+
+
+def test_wide_records(mbe, orc):
+    g = _wide(0)
+    _say("wide records", g.n_edges)
+    want = orc.mbea(g, want_list=True)
+    res, flat = mbe.mbe_enumerate(g, mbe.Options(diagnostics=True))
+    assert res["count"] == want["count"] and res["hash"] == want["hash"]
+    assert mbe.decode_records(flat) == want["list"]
+
+
+def test_wide_in_batch_and_server(mbe, orc):
+    gs = [_wide(0), gg.config1(), gg.chain(1100), gg.random_small(30, 40, 0.3, 77), _wide(2), gg.crown(8)]
+    _say("wide batch", len(gs))
+    want = [orc.mbea(g) for g in gs]
+    res = mbe.mbe_count_batch(gs, mbe.Options(diagnostics=True))
+    for i, (r, w) in enumerate(zip(res, want)):
+        for k in DIAG_KEYS:
+            assert r[k] == w[k], (i, gs[i].name, k, r[k], w[k])
+        assert r["status"] == 0
+    for sk in (1, 3):
+        fast = mbe.mbe_count_batch(gs, mbe.Options(steal_k=sk))
+        assert [(r["count"], r["hash"]) for r in fast] == [(w["count"], w["hash"]) for w in want]
+    with mbe.Server(slots=2, small_edges=3000) as sv:
+        tks = [sv.submit(g) for g in gs]
+        for tk, w, g in zip(tks, want, gs):
+            r, _ = sv.wait(tk)
+            assert (r["count"], r["hash"]) == (w["count"], w["hash"]), g.name
 
 
 @pytest.mark.parametrize("seed", range(3))

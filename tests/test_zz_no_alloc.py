@@ -61,3 +61,14 @@ def test_noalloc_scratch_limit_then_recovers(mbe):
     small = gg.config1()
     _same(mbe.mbe_count_noalloc(small, mbe.Options(diagnostics=True)),
           mbe.mbe_count(small, mbe.Options(diagnostics=True)))
+
+
+def test_noalloc_wide_top_level_candidates(mbe):
+    # candidates of degree above 1024 go to the wide search, whose arena also comes from the
+    # scratch
+    g = gg.wide_hubs(200, 5000, [1100 + 300 * k for k in range(12)], 0.002, 4)
+    for opt in (mbe.Options(diagnostics=True), mbe.Options(steal_k=3)):
+        _same(mbe.mbe_count_noalloc(g, opt), mbe.mbe_count(g, opt))
+    small = gg.crown(7)
+    _same(mbe.mbe_count_noalloc(small, mbe.Options(diagnostics=True)),
+          mbe.mbe_count(small, mbe.Options(diagnostics=True)))
