@@ -417,9 +417,9 @@ def main():
         threads = min(BOX_THREADS, os.cpu_count() or 1)
         log("cpu baseline on", threads, "threads")
         out["cpu_baseline"] = cpu_baseline(g, rng_range, threads)
-        # the same oracle on one core, on a smaller sample (about a tenth of the work)
+        # the same oracle on one core, on a smaller sample (about half the parallel leg's work)
         log("cpu baseline on 1 thread")
-        out["cpu_baseline_serial"] = cpu_baseline(g, rng_range, 1, frac=0.01, chunks=16)
+        out["cpu_baseline_serial"] = cpu_baseline(g, rng_range, 1, frac=0.1, chunks=32)
     print(json.dumps(out), flush=True)
 
 
