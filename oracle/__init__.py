@@ -67,6 +67,8 @@ def _load():
                                      ctypes.c_int64, ctypes.c_int64, p32, ctypes.c_int64,
                                      ctypes.POINTER(OrcResult)]
             lib.orc_mbea.restype = ctypes.c_int
+            lib.orc_imbea.argtypes = lib.orc_mbea.argtypes
+            lib.orc_imbea.restype = ctypes.c_int
             lib.orc_brute.argtypes = [ctypes.c_int32, ctypes.c_int32, p32, p32, p32, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
             lib.orc_brute.restype = ctypes.c_int64
@@ -162,6 +164,26 @@ def mbea(g, side: int = 0, rank_lo: int = 0, rank_hi: int = -1, want_list: bool 
                       rank_lo, rank_hi, _p32(buf) if want_list else None, buf.size, ctypes.byref(res))
     if rc != 0:
         raise RuntimeError("oracle mbea failed")
+    out = {k: getattr(res, k) for k, _ in OrcResult._fields_}
+    if want_list:
+        if res.written < 0:
+            raise RuntimeError("oracle record buffer too small")
+        out["list"] = canonical(split_records(buf, res.written))
+    return out
+
+
+def imbea(g, side: int = 0, rank_lo: int = 0, rank_hi: int = -1, want_list: bool = False,
+          list_cap: int = 1 << 26) -> Dict:
+    """MBEA with iMBEA's candidate pruning (the C set of section II-C): the same answer as
+    mbea, its own tree tallies.  Fields as mbea's."""
+    lib = _load()
+    u_off, u_adj, v_off, v_adj = _arrays(g)
+    res = OrcResult()
+    buf = np.zeros(list_cap if want_list else 1, dtype=np.int32)
+    rc = lib.orc_imbea(g.n_u, g.n_v, _p32(u_off), _p32(u_adj), _p32(v_off), _p32(v_adj), side,
+                       rank_lo, rank_hi, _p32(buf) if want_list else None, buf.size, ctypes.byref(res))
+    if rc != 0:
+        raise RuntimeError("oracle imbea failed")
     out = {k: getattr(res, k) for k, _ in OrcResult._fields_}
     if want_list:
         if res.written < 0:

@@ -259,6 +259,116 @@ static void mbea(orc_ctx *g, const int32_t *L, int32_t nL, const int32_t *R, int
     free(Lp); free(Rp); free(Pp); free(Qp);
 }
 
+/* |R n N(v)| for ascending R and N(v) (a count-only merge). */
+static int32_t meet_count(const int32_t *r, int32_t nr, const int32_t *nv, int32_t nn) {
+    int32_t i = 0, j = 0, k = 0;
+    while (i < nr && j < nn) {
+        if (r[i] < nv[j]) i++;
+        else if (r[i] > nv[j]) j++;
+        else { k++; i++; j++; }
+    }
+    return k;
+}
+
+/*
+ * Algorithm 1 with iMBEA's candidate pruning (the embedded pruning of section II-C, after
+ * Zhang et al.): when x's node is maximal, every other candidate v of P that joins L' (it is
+ * adjacent to all of R') and has no neighbour in R outside R' -- so its neighbourhood within
+ * R is exactly x's -- leaves P and joins Q together with x.  Such a v could only head nodes
+ * whose bicliques x's subtree already holds, so the answer is the same with fewer nodes.
+ * When x is not maximal nothing else moves (the maximal-expansion scan is where the test is
+ * made).  A candidate that has left P is never taken; for the nodes after x it is in Q.
+ *
+ * silent_before: candidates at positions below it are only run for their effect on P and Q
+ * (maximality, and the set that leaves P with them), with nothing counted or reported and no
+ * recursion -- the top-level prefix of a rank range, so that a range sees the moves the whole
+ * run makes.  stop_before: positions from here on are not taken.
+ */
+static void imbea(orc_ctx *g, const int32_t *L, int32_t nL, const int32_t *R, int32_t nR,
+                  const orc_cand *P, int32_t nP, int32_t *Q, int32_t nQ, uint32_t depth,
+                  int32_t silent_before, int32_t stop_before) {
+    int32_t *Lp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nL + nP + 1));
+    int32_t *Rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nR + 1));
+    orc_cand *Pp = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(nP + 1));
+    int32_t *Qp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nQ + nP + 1));
+    int32_t *Cs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nP + 1));   /* positions leaving P */
+    unsigned char *gone = (unsigned char *)calloc((size_t)nP + 1, 1);
+
+    for (int32_t ip = 0; ip < nP && ip < stop_before; ip++) {
+        if (gone[ip]) continue;                          /* left P with an earlier x */
+        const int silent = ip < silent_before;
+        int32_t x = P[ip].v;
+        if (!silent) {
+            g->res->nodes += 1;
+            if (depth > g->res->max_depth) g->res->max_depth = depth;
+        }
+        int32_t nLp = 0;
+        for (int32_t i = 0; i < nL; i++) Lp[nLp++] = L[i];
+        Lp[nLp++] = x;
+        const int32_t *nx = g->c_adj + g->c_off[x];
+        int32_t nRp = intersect(R, nR, nx, (int32_t)deg_c(g, x), Rp);
+        for (int32_t i = 0; i < nRp; i++) {
+            int32_t w = Rp[i];
+            for (int32_t e = g->o_off[w]; e < g->o_off[w + 1]; e++) g->cnt[g->o_adj[e]] += 1;
+        }
+        /* the same byte tally as the plain search, over the P and Q of this moment */
+        uint64_t rs = 0, fw = 0, nPrest = 0;
+        for (int32_t i = 0; i < nRp; i++) rs += 2 + (uint64_t)deg_o(g, Rp[i]);
+        for (int32_t i = ip + 1; i < nP; i++)
+            if (!gone[i]) { fw += 2 + (uint64_t)deg_c(g, P[i].v); nPrest++; }
+        for (int32_t i = 0; i < nQ; i++) fw += 2 + (uint64_t)deg_c(g, Q[i]);
+
+        int maximal = 1;
+        int32_t nQp = 0;
+        for (int32_t i = 0; i < nQ; i++) {
+            int32_t c = g->cnt[Q[i]];
+            if (c == nRp) { maximal = 0; break; }
+            else if (c > 0) Qp[nQp++] = Q[i];
+        }
+        int32_t nPp = 0, nC = 0;
+        if (maximal) {
+            for (int32_t i = ip + 1; i < nP; i++) {
+                if (gone[i]) continue;
+                int32_t v = P[i].v, c = g->cnt[v];
+                if (c == nRp) {
+                    Lp[nLp++] = v;
+                    /* v joins L'; with no neighbour in R outside R' it also leaves P */
+                    if (meet_count(R, nR, g->c_adj + g->c_off[v], (int32_t)deg_c(g, v)) == nRp) Cs[nC++] = i;
+                } else if (c > 0) { Pp[nPp].key = c; Pp[nPp].v = v; Pp[nPp].seq = nPp; nPp++; }
+            }
+        } else {
+            if (!silent) g->res->nonmaximal += 1;
+            nQp = 0;
+        }
+        for (int32_t i = 0; i < nRp; i++) {
+            int32_t w = Rp[i];
+            for (int32_t e = g->o_off[w]; e < g->o_off[w + 1]; e++) g->cnt[g->o_adj[e]] = 0;
+        }
+        if (!silent) {
+            uint64_t state = nPrest + (uint64_t)nQ + (uint64_t)nRp + (uint64_t)nPp + (uint64_t)nQp;
+            uint64_t base = 2 + (uint64_t)deg_c(g, x) + state;
+            g->res->bytes_alg += 4 * (base + (rs < fw ? rs : fw));
+            g->res->bytes_rs += 4 * (base + rs);
+        }
+        if (maximal && !silent) {
+            report(g, Lp, nLp, Rp, nRp);
+            if (nPp > 0) {
+                qsort(Pp, (size_t)nPp, sizeof(orc_cand), cmp_cand);
+                int32_t *Qchild = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nQp + nPp + 1));
+                memcpy(Qchild, Qp, sizeof(int32_t) * (size_t)nQp);
+                imbea(g, Lp, nLp, Rp, nRp, Pp, nPp, Qchild, nQp, depth + 1, 0, nPp);
+                free(Qchild);
+            }
+        }
+        Q[nQ++] = x;                                     /* Q = Q u C, C = {x} u the moved */
+        for (int32_t k = 0; k < nC; k++) {
+            gone[Cs[k]] = 1;
+            Q[nQ++] = P[Cs[k]].v;
+        }
+    }
+    free(Lp); free(Rp); free(Pp); free(Qp); free(Cs); free(gone);
+}
+
 /* Candidate side: 1 = U, 2 = V, 0 = the smaller side, U on a tie (reading r4). */
 static int pick_side(int32_t n_u, int32_t n_v, int side) {
     if (side == 1 || side == 2) return side;
@@ -315,6 +425,50 @@ int orc_mbea(int32_t n_u, int32_t n_v, const int32_t *u_off, const int32_t *u_ad
     if (rank_lo < rank_hi)
         mbea(&g, NULL, 0, R, g.no, P + rank_lo, (int32_t)(nP - rank_lo), Q, nQ, 1,
              (int32_t)(rank_hi - rank_lo));
+    free(P); free(R); free(Q); free(g.cnt);
+    return 0;
+}
+
+/*
+ * As orc_mbea, with iMBEA's candidate pruning (see imbea above).  The top-level candidates
+ * ranked before rank_lo are run silently, so that a rank range makes the moves the whole run
+ * makes: count, hash and the tree tallies of disjoint ranges add up to the whole run's.
+ */
+int orc_imbea(int32_t n_u, int32_t n_v, const int32_t *u_off, const int32_t *u_adj,
+              const int32_t *v_off, const int32_t *v_adj, int side, int64_t rank_lo,
+              int64_t rank_hi, int32_t *buf, int64_t buf_cap, orc_result *res) {
+    if (!res || n_u < 0 || n_v < 0) return -1;
+    memset(res, 0, sizeof(*res));
+    side = pick_side(n_u, n_v, side);
+    res->side = (uint32_t)side;
+    orc_ctx g;
+    memset(&g, 0, sizeof(g));
+    g.c_is_v = (side == 2);
+    g.nc = g.c_is_v ? n_v : n_u;
+    g.no = g.c_is_v ? n_u : n_v;
+    g.c_off = g.c_is_v ? v_off : u_off;
+    g.c_adj = g.c_is_v ? v_adj : u_adj;
+    g.o_off = g.c_is_v ? u_off : v_off;
+    g.o_adj = g.c_is_v ? u_adj : v_adj;
+    g.buf = buf;
+    g.buf_cap = buf_cap;
+    g.res = res;
+    if (g.nc == 0 || g.no == 0) return 0;
+    orc_cand *P = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)g.nc);
+    int32_t nP = 0;
+    for (int32_t v = 0; v < g.nc; v++) {
+        int64_t d = deg_c(&g, v);
+        if (d > 0) { P[nP].key = (int32_t)d; P[nP].v = v; P[nP].seq = v; nP++; }
+    }
+    qsort(P, (size_t)nP, sizeof(orc_cand), cmp_cand);
+    if (rank_lo < 0) rank_lo = 0;
+    if (rank_hi < 0 || rank_hi > nP) rank_hi = nP;
+    int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (size_t)g.no);
+    for (int32_t w = 0; w < g.no; w++) R[w] = w;
+    int32_t *Q = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nP + 1));
+    g.cnt = (int32_t *)calloc((size_t)g.nc, sizeof(int32_t));
+    if (!P || !R || !Q || !g.cnt) { free(P); free(R); free(Q); free(g.cnt); return -1; }
+    if (rank_lo < rank_hi) imbea(&g, NULL, 0, R, g.no, P, nP, Q, 0, 1, (int32_t)rank_lo, (int32_t)rank_hi);
     free(P); free(R); free(Q); free(g.cnt);
     return 0;
 }

@@ -1391,11 +1391,15 @@ __device__ __forceinline__ bool find_shared_list(const SearchArgs &a, WGShared *
     return got_one;
 }
 
-// The single-word class (the most top-level candidates, small lists) keeps four waves per
-// SIMD resident: its register budget is capped at 128.
+// The classes of up to eight mask words keep four waves per SIMD resident (two 8-wave
+// workgroups per compute unit): their register budget is capped at 128.  For two to eight
+// words that spills some state to scratch (about 300 bytes per lane), and still measured
+// faster than 203-234 registers at two waves per SIMD: power-law step 47.8 -> 39.1 ms,
+// skewed sample 1.76 -> 1.27 s.  The search waits on memory latency, and more resident waves
+// hide it.
 // TB (with DIAG and ENUM off): the production search, also tallying its design bytes.
 template <int W, bool DIAG, bool ENUM, bool TB = false>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W == 1 ? 4 : 2))) void search_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 : 2))) void search_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
     extern __shared__ unsigned char lds_raw[];
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
     const int tid = threadIdx.x, nt = blockDim.x, wid = uni(tid >> 6), nw = nt >> 6, ln = lane_id();

@@ -457,3 +457,106 @@ def test_server_results_equal_alone(mbe, slots, small_edges):
             r, lat = sv.wait(tk)
             assert (r["count"], r["hash"]) == (alone[i]["count"], alone[i]["hash"]), gs[i].name
             assert lat >= 0.0
+
+
+# ----------------------------------------------------------------------------- the configs' own inputs
+
+def _gold(key):
+    return json.load(open(os.path.join(GOLDEN, "workloads.json")))[key]
+
+
+def test_workload3_every_class(mbe):
+    # ranks of the skewed graph in each of its mask classes (W = 4, 8, 16), and the whole
+    # W = 16 class as one range
+    gold = _gold("config3_classes")
+    g = gg.config3()
+    assert any(s["rank_lo"] >= 4968 and s["nodes"] > 1000 for s in gold["samples"])
+    for s in gold["samples"]:
+        _say("workload3 ranks", s["rank_lo"], s["rank_hi"], s["nodes"])
+        r = mbe.mbe_count(g, mbe.Options(diagnostics=True, root_lo=s["rank_lo"], root_hi=s["rank_hi"]))
+        for k in DIAG_KEYS:
+            assert r[k] == s[k], (s["rank_lo"], k, r[k], s[k])
+        fast = mbe.mbe_count(g, mbe.Options(root_lo=s["rank_lo"], root_hi=s["rank_hi"], steal_k=3))
+        for k in ("count", "hash", "out_ints"):
+            assert fast[k] == s[k], (s["rank_lo"], "fast", k)
+
+
+def test_workload4_subset_in_one_batch(mbe):
+    # a fixed subset of the batch covering mask classes W = 1, 2 and 4, in one batched call
+    gold = _gold("config4_subset")
+    assert sorted(gold["classes"]) == ["1", "2", "4"]
+    gs = [gg.config4_graph(e["index"]) for e in gold["graphs"]]
+    _say("workload4 subset", len(gs), sum(g.n_edges for g in gs))
+    res = mbe.mbe_count_batch(gs, mbe.Options(diagnostics=True))
+    for e, r in zip(gold["graphs"], res):
+        for k in DIAG_KEYS:
+            assert r[k] == e[k], (e["index"], k, r[k], e[k])
+    for sk in (2, 3):
+        fast = mbe.mbe_count_batch(gs, mbe.Options(steal_k=sk))
+        for e, r in zip(gold["graphs"], fast):
+            assert (r["count"], r["hash"], r["out_ints"]) == (e["count"], e["hash"], e["out_ints"]), e["index"]
+
+
+def test_workload5_large_request_in_server_mix(mbe, orc):
+    # the smallest Chung-Lu request of the serving stream (23k x 11.5k, 575k edges, 5.6M
+    # bicliques) submitted among small batch-style requests; every result against the oracle
+    gold = _gold("config5_request")
+    reqs = gg.config5_requests(200, 2.5)
+    big = reqs[gold["request"]][1]
+    assert big.n_edges == gold["edges"]
+    small = [g for _, g in reqs[:60] if g.n_u < 20000 and g.n_edges <= 6000][:24]
+    want_small = [orc.mbea(g) for g in small]
+    _say("workload5 mix", len(small), big.name)
+    r = mbe.mbe_count(big, mbe.Options(diagnostics=True))
+    for k in DIAG_KEYS:
+        assert r[k] == gold[k], (k, r[k], gold[k])
+    with mbe.Server(slots=2, small_edges=10000) as sv:
+        order = small[:12] + [big] + small[12:]
+        tks = [sv.submit(g) for g in order]
+        got = [sv.wait(t)[0] for t in tks]
+    gb = got[12]
+    assert (gb["count"], gb["hash"], gb["out_ints"]) == (gold["count"], gold["hash"], gold["out_ints"])
+    for g, w, x in zip(small, want_small, got[:12] + got[13:]):
+        assert (x["count"], x["hash"], x["out_ints"]) == (w["count"], w["hash"], w["out_ints"]), g.name
+
+
+def _mix_np(z):
+    z = z.copy()
+    z ^= z >> np.uint64(30)
+    z *= np.uint64(0xBF58476D1CE4E5B9)
+    z ^= z >> np.uint64(27)
+    z *= np.uint64(0x94D049BB133111EB)
+    z ^= z >> np.uint64(31)
+    return z
+
+
+def test_enumerate_crown20_closed_form(mbe):
+    # crown(20) = K_{20,20} minus a perfect matching: its 2^20 - 2 maximal bicliques are
+    # (A, V minus the partners of A) for every proper non-empty index set; all records come
+    # back in canonical order (A ascending lexicographically), and the hash equals the sum
+    # of the contract's h over that closed-form list
+    import torch
+    from hash_contract import hu, hv, K
+    n = 20
+    g = gg.crown(n)
+    _say("crown20 records")
+    out = torch.empty((2 ** n - 2) * (2 + n), dtype=torch.int32, device="cuda")
+    res, buf = mbe.mbe_enumerate(g, out=out)
+    assert res["count"] == 2 ** n - 2 and res["out_ints"] == (2 ** n - 2) * (2 + n)
+    arr = buf.cpu().numpy().reshape(-1, 2 + n).astype(np.int64)
+    na, nb, vals = arr[:, 0], arr[:, 1], arr[:, 2:]
+    assert ((na + nb) == n).all() and (na >= 1).all() and (nb >= 1).all()
+    assert (np.sort(vals, axis=1) == np.arange(n)[None, :]).all()  # A and B complementary
+    is_a = np.arange(n)[None, :] < na[:, None]
+    bits = (is_a * (np.int64(1) << vals)).sum(axis=1)
+    assert (np.sort(bits) == np.arange(1, 2 ** n - 1)).all()  # every proper subset once
+    la = [tuple(r[2:2 + k]) for r, k in zip(arr.tolist(), na.tolist())]
+    assert all(la[i] < la[i + 1] for i in range(len(la) - 1))
+    with np.errstate(over="ignore"):
+        hu_t = np.array([hu(i) for i in range(n)], dtype=np.uint64)
+        hv_t = np.array([hv(i) for i in range(n)], dtype=np.uint64)
+        sa = np.where(is_a, hu_t[vals], np.uint64(0)).sum(axis=1, dtype=np.uint64)
+        sb = np.where(~is_a, hv_t[vals], np.uint64(0)).sum(axis=1, dtype=np.uint64)
+        h = _mix_np(sa + _mix_np(sb + np.uint64(K)))
+        total = int(h.sum(dtype=np.uint64))
+    assert res["hash"] == total

@@ -8,7 +8,9 @@ oracle's C source (on the CPU), builds it, and runs the pins on the copy alone:
   is pinned to the published SplitMix64 outputs);
 * the tree: node, non-maximal, depth and byte tallies of the hand-derived closed forms.
 
-A mutant must fail at least one of them."""
+A mutant must fail at least one of them.  The plain search's mutants are planted outside the
+iMBEA variant's code, and the variant's mutants inside it; the variant's pins are its
+definition list (brute force) and its hand-derived trees (tests/test_oracle_imbea.py)."""
 import ctypes
 import os
 import subprocess
@@ -42,6 +44,48 @@ MUTANTS = {
 }
 
 
+IMBEA_MUTANTS = {
+    "imbea_moved_ones_still_taken": ("if (gone[ip]) continue;", "(void)gone;"),
+    "imbea_every_joiner_moved": ("if (meet_count(R, nR, g->c_adj + g->c_off[v], (int32_t)deg_c(g, v)) == nRp) Cs[nC++] = i;",
+                                 "Cs[nC++] = i;"),
+    "imbea_tested_against_r_prime": ("if (meet_count(R, nR, g->c_adj", "if (meet_count(Rp, nRp, g->c_adj"),
+    "imbea_moved_not_put_in_q": ("Q[nQ++] = P[Cs[k]].v;", "(void)0;"),
+    "imbea_silent_prefix_counted": ("if (!silent) {\n            g->res->nodes += 1;", "{\n            g->res->nodes += 1;"),
+}
+
+# the iMBEA variant's code: from its count-only merge to the plain entry's side rule, and its
+# entry point
+_IMBEA_SPANS = [("/* |R n N(v)| for ascending R and N(v)", "/* Candidate side: 1 = U, 2 = V"),
+                ("/*\n * As orc_mbea, with iMBEA's candidate pruning", "/* Number of top-level candidates")]
+
+
+def _split(src):
+    """(text outside the iMBEA code with placeholders, the iMBEA pieces)."""
+    pieces = []
+    for a, b in _IMBEA_SPANS:
+        i, j = src.index(a), src.index(b)
+        pieces.append(src[i:j])
+        src = src[:i] + f"@@IMBEA{len(pieces) - 1}@@" + src[j:]
+    return src, pieces
+
+
+def _join(outside, pieces):
+    for k, p in enumerate(pieces):
+        outside = outside.replace(f"@@IMBEA{k}@@", p)
+    return outside
+
+
+def _plant(src, old, new, inside):
+    outside, pieces = _split(src)
+    if inside:
+        assert sum(p.count(old) for p in pieces) == 1, old
+        pieces = [p.replace(old, new) for p in pieces]
+    else:
+        assert outside.count(old) == 1, old
+        outside = outside.replace(old, new)
+    return _join(outside, pieces)
+
+
 def _build(src_text):
     d = tempfile.mkdtemp(prefix="orc_mut_")
     c = os.path.join(d, "m.c")
@@ -60,16 +104,17 @@ class _Copy:
         p32 = ctypes.POINTER(ctypes.c_int32)
         lib.orc_mbea.argtypes = [ctypes.c_int32, ctypes.c_int32, p32, p32, p32, p32, ctypes.c_int, ctypes.c_int64,
                                  ctypes.c_int64, p32, ctypes.c_int64, ctypes.POINTER(orc.OrcResult)]
+        lib.orc_imbea.argtypes = lib.orc_mbea.argtypes
         lib.orc_hash_pair.argtypes = [p32, ctypes.c_int64, p32, ctypes.c_int64]
         lib.orc_hash_pair.restype = ctypes.c_uint64
         self.lib, self.p32 = lib, p32
 
-    def mbea(self, g):
+    def mbea(self, g, fn="orc_mbea", lo=0, hi=-1):
         arrs = [np.ascontiguousarray(x, dtype=np.int32) for x in (g.u_off, g.u_adj, g.v_off, g.v_adj)]
         buf = np.zeros(1 << 16, dtype=np.int32)
         res = self.orc.OrcResult()
-        self.lib.orc_mbea(g.n_u, g.n_v, *[a.ctypes.data_as(self.p32) for a in arrs], 0, 0, -1,
-                          buf.ctypes.data_as(self.p32), buf.size, ctypes.byref(res))
+        getattr(self.lib, fn)(g.n_u, g.n_v, *[a.ctypes.data_as(self.p32) for a in arrs], 0, lo, hi,
+                              buf.ctypes.data_as(self.p32), buf.size, ctypes.byref(res))
         lst = self.orc.canonical(self.orc.split_records(buf, res.written)) if res.written >= 0 else None
         return res, lst
 
@@ -120,14 +165,48 @@ def _pins_fail(orc, cp):
     return None
 
 
+def _imbea_pins_fail(orc, cp):
+    """Name of the first iMBEA pin the copy fails, or None (tests/test_oracle_imbea.py)."""
+    hand = gg.from_edges(3, 3, [0, 0, 1, 1, 2, 2], [0, 1, 0, 1, 1, 2])
+    res, _ = cp.mbea(hand, "orc_imbea")
+    if (res.nodes, res.nonmaximal, res.count, res.bytes_alg, res.max_depth) != (3, 0, 3, 160, 2):
+        return "hand-worked tree"
+    for m, n in ((4, 9), (3, 3)):
+        res, _ = cp.mbea(gg.complete(m, n), "orc_imbea")
+        if (res.nodes, res.nonmaximal, res.count) != (1, 0, 1):
+            return "complete"
+    blocks = gg.disjoint_union(gg.disjoint_union(gg.complete(2, 3), gg.complete(4, 1)), gg.complete(3, 3))
+    res, _ = cp.mbea(blocks, "orc_imbea")
+    if (res.nodes, res.nonmaximal, res.count) != (3, 0, 3):
+        return "complete blocks"
+    # ranges: the prefix before rank_lo runs silently
+    res, _ = cp.mbea(gg.complete(4, 9), "orc_imbea", 1, -1)
+    if (res.nodes, res.count) != (0, 0):
+        return "silent prefix"
+    graphs = [gg.chain(7), gg.complete_minus_edge(4, 5)] + [gg.random_small(10, 12, 0.4, s) for s in range(30)]
+    for g in graphs:
+        b = orc.brute(g)
+        res, lst = cp.mbea(g, "orc_imbea")
+        if res.count != len(b["list"]) or lst != b["list"] or res.hash != hc.total(b["list"]):
+            return "definition " + g.name
+    return None
+
+
 def test_unmodified_source_passes_every_pin(orc):
-    assert _pins_fail(orc, _Copy(orc, _build(open(SRC).read()))) is None
+    cp = _Copy(orc, _build(open(SRC).read()))
+    assert _pins_fail(orc, cp) is None
+    assert _imbea_pins_fail(orc, cp) is None
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(orc, name):
-    src = open(SRC).read()
     old, new = MUTANTS[name]
-    assert src.count(old) == 1, name
-    cp = _Copy(orc, _build(src.replace(old, new)))
+    cp = _Copy(orc, _build(_plant(open(SRC).read(), old, new, inside=False)))
     assert _pins_fail(orc, cp) is not None, f"mutant {name} passed every pin"
+
+
+@pytest.mark.parametrize("name", sorted(IMBEA_MUTANTS))
+def test_imbea_pins_catch_mutant(orc, name):
+    old, new = IMBEA_MUTANTS[name]
+    cp = _Copy(orc, _build(_plant(open(SRC).read(), old, new, inside=True)))
+    assert _imbea_pins_fail(orc, cp) is not None, f"mutant {name} passed every pin"
