@@ -139,6 +139,46 @@ def cpu_baseline(g, rng_range, threads, frac=0.2, chunks=64):
                       f"{cnt} bicliques in {dt:.2f} s wall on {threads} threads"}
 
 
+def load_study(mbe, dg, rng, steal_ks=(1, 2, 3)):
+    """Per-workgroup load of the search (the per-block time distribution and the work-sharing
+    ablation of the paper's evaluation, section IV): one tally run per steal depth k with a load
+    record per workgroup.  A workgroup is busy from its start to its end minus the time it
+    spent finding work; the launch span runs from the first start to the last end."""
+    import numpy as np
+    lo, hi = rng if rng else (0, 0)
+    out = {}
+    for k in steal_ks:
+        res, rec = mbe.mbe_count_loads(dg, mbe.Options(steal_k=k, root_lo=lo, root_hi=hi))
+        start, end, wait = rec[:, 1].astype(np.float64), rec[:, 2].astype(np.float64), rec[:, 3].astype(np.float64)
+        span = end.max() - start.min()
+        busy = end - start - wait
+        frac = busy / span
+        out[f"k{k}"] = {
+            "search_ms": res["kernel_ms"],
+            "workgroups": int(len(rec)),
+            "busy_frac": {q: float(np.percentile(frac, p)) for q, p in
+                          (("min", 0), ("p10", 10), ("p50", 50), ("p90", 90), ("max", 100))},
+            "idle_share": float(1.0 - busy.sum() / (len(rec) * span)),
+            "busy_max_over_median": float(busy.max() / max(np.median(busy), 1.0)),
+            "shared_chunks": res["shared_chunks"],
+            "count": res["count"],
+        }
+        log(f"load study k={k}: {res['kernel_ms']:.1f} ms, idle share {out[f'k{k}']['idle_share']:.3f}")
+    return out
+
+
+def steal_ablation(mbe, dg, rng, steps=3):
+    """Search time per step under steal depth k = 1, 2, 3 (same answers)."""
+    lo, hi = rng if rng else (0, 0)
+    out = {}
+    for k in (1, 2, 3):
+        opt = mbe.Options(steal_k=k, root_lo=lo, root_hi=hi)
+        mbe.mbe_count(dg, opt)
+        ks = [mbe.mbe_count(dg, opt)["kernel_ms"] for _ in range(steps)]
+        out[f"k{k}_ms"] = sum(ks) / len(ks)
+    return out
+
+
 def bench_batch(args, mbe):
     """Batched form: n independent graphs (|U|, |V| log-uniform in [50, 2000], density uniform
     in [0.01, 0.1], ER or Chung-Lu) in one mbe_count_batch call, against one mbe_count call
@@ -313,6 +353,8 @@ def main():
     ap.add_argument("--no-traffic", action="store_true",
                     help="skip the two rocprofv3 counter runs that measure the step's HBM traffic")
     ap.add_argument("--traffic-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-load-study", action="store_true",
+                    help="skip the per-workgroup load study (k = 1, 2, 3) on the skewed sample")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the search runs on one GPU (sharding across GPUs is a design only); --gpus must be 1",
@@ -408,6 +450,19 @@ def main():
         "paper_method_rate": {"bytes_alg": diag["bytes_alg"], "gbs": diag["bytes_alg"] / (kavg / 1000.0) / 1e9},
         "phase_share": phase_share,
     }
+    out["steal_ablation"] = steal_ablation(mbe, dg, rng_range)
+    if not args.no_load_study:
+        # the load study on the skewed graph's sample of 64 top-level candidates (deep,
+        # unbalanced subtrees)
+        if args.workload == "skewed-sample":
+            sg, srng = dg, rng_range
+        else:
+            g3 = gg.config3()
+            sg = gg.BiGraph(g3.n_u, g3.n_v, *[torch.from_numpy(np.asarray(a)).to(dev) for a in
+                                              (g3.u_off, g3.u_adj, g3.v_off, g3.v_adj)])
+            srng = (2000, 2064)
+        out["load_study"] = dict(workload="skewed dense chung-lu 20k x 5k + 50 planted, top-level ranks [2000, 2064)",
+                                 **load_study(mbe, sg, srng))
     if rng_range is not None:
         # one top-level candidate of the skewed graph holds ~0.8M bicliques: the oracle needs
         # minutes for the smallest sample, so no bounded baseline exists for this workload

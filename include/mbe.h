@@ -184,6 +184,21 @@ int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out);
 int mbe_workspace_size(const mbe_graph *g, const mbe_options *opt, size_t *bytes);
 
 /*
+ * The load study of section IV (the per-block time distribution of its evaluation): mbe_count
+ * with diagnostics = 2, also returning one record per workgroup of every search launch of the
+ * call: rec[4i .. 4i+3] = (mask words of the launch's class, 0 for the wide search; start and
+ * end of the workgroup in nanoseconds from the earliest start of the call; nanoseconds it
+ * spent finding work: claiming top-level candidates, scanning for lists to share, waiting
+ * while others were busy).  Times come from the device wall clock.  A workgroup is busy for
+ * (end - start - wait) of the launch.  *n_records receives the number of records; when it
+ * exceeds cap_records the call returns MBE_ERR_BUFFER_TOO_SMALL with out complete and rec
+ * unspecified.  Errors as mbe_count, plus MBE_ERR_INVALID_ARG (out or n_records NULL,
+ * cap_records < 0, rec NULL with cap_records > 0).
+ */
+int mbe_count_loads(const mbe_graph *g, const mbe_options *opt, mbe_result *out, uint64_t *rec,
+                    int64_t cap_records, int64_t *n_records);
+
+/*
  * For callers that cannot allocate device memory -- code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc: mbe_count without any allocation.  The
  * result is the one mbe_count returns.  Every device buffer of the call (graph copy for host

@@ -17,7 +17,7 @@ from typing import Any, Dict, List, Optional, Tuple
 
 import numpy as np
 
-__all__ = ["mbe_count", "mbe_count_noalloc", "mbe_count_batch", "mbe_enumerate", "mbe_strerror", "mbe_version", "MbeError",
+__all__ = ["mbe_count", "mbe_count_loads", "mbe_count_noalloc", "mbe_count_batch", "mbe_enumerate", "mbe_strerror", "mbe_version", "MbeError",
            "Options", "Server", "lib_path", "load"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -100,6 +100,9 @@ def load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.mbe_count.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
     lib.mbe_count.restype = ctypes.c_int
+    lib.mbe_count_loads.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result),
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.mbe_count_loads.restype = ctypes.c_int
     lib.mbe_count_noalloc.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
     lib.mbe_count_noalloc.restype = ctypes.c_int
     lib.mbe_workspace_size.argtypes = [ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(ctypes.c_size_t)]
@@ -196,6 +199,23 @@ def mbe_count(g, opt: Optional[Options] = None) -> Dict[str, Any]:
     if rc != MBE_OK:
         raise MbeError(rc, _result_dict(res))
     return _result_dict(res)
+
+
+def mbe_count_loads(g, opt: Optional[Options] = None, cap: int = 1 << 16) -> Tuple[Dict[str, Any], np.ndarray]:
+    """``mbe_count`` with the design-byte tally, and one load record per workgroup of every
+    search launch: an (n, 4) uint64 array of (mask words of its class, 0 = wide search;
+    start ns; end ns; ns spent finding work)."""
+    lib = load()
+    cg, keep = _marshal_graph(g)
+    co = _marshal_opts(opt, bool(cg.on_device))
+    res = _Result()
+    rec = np.zeros((max(1, cap), 4), dtype=np.uint64)
+    n = ctypes.c_int64(0)
+    rc = lib.mbe_count_loads(ctypes.byref(cg), ctypes.byref(co), ctypes.byref(res), ctypes.c_void_p(rec.ctypes.data),
+                             ctypes.c_int64(cap), ctypes.byref(n))
+    if rc != MBE_OK:
+        raise MbeError(rc, _result_dict(res))
+    return _result_dict(res), rec[:n.value].copy()
 
 
 def mbe_count_noalloc(g, opt: Optional[Options] = None) -> Dict[str, Any]:

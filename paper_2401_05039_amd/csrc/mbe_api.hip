@@ -56,7 +56,7 @@ struct DevBuf {
 
 struct DeviceState {
     std::mutex mu;
-    DevBuf graph, prep, sort_tmp, arena, small, steal, slots, warena, witems;
+    DevBuf graph, prep, sort_tmp, arena, small, steal, slots, warena, witems, loads;
     DevBuf rec, rec_offs, rec_tmp, rec_lens, canon_tmp, out_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int cus = 0;
@@ -205,7 +205,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
                bool diag, bool enumerate, bool tb, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
                unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx,
-               const WideRange &wr);
+               const WideRange &wr, std::vector<unsigned long long> *loads = nullptr);
 
 size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo, const int64_t *cls_hi, bool diag,
                         bool enumerate, int grid, int waves, const WideRange &wr);
@@ -214,7 +214,8 @@ size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo,
 // device bytes the search of this call would hold; with fixed (mbe_count_noalloc), every
 // device buffer of the call is carved from the device's scratch and nothing is allocated
 int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t *ubuf, uint64_t ucap_ints,
-        int ubuf_on_device, bool enumerate, size_t *ws_out = nullptr, bool fixed = false) {
+        int ubuf_on_device, bool enumerate, size_t *ws_out = nullptr, bool fixed = false,
+        std::vector<unsigned long long> *loads = nullptr) {
     if (!g || !out) return MBE_ERR_INVALID_ARG;
     std::memset(out, 0, sizeof(*out));
     if (g->n_u < 0 || g->n_v < 0 || g->n_edges < 0) return MBE_ERR_INVALID_ARG;
@@ -433,7 +434,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     {
         int attempts = 0;
         const int rc = run_search(st, a, dims, cls_a, cls_b, opt.diag, enumerate, opt.tb, grid, waves, acc, ACC_SLOTS * 8, hacc,
-                                  &hflags, &ms, s, nullptr, 0, &attempts, small, fx, wr);
+                                  &hflags, &ms, s, nullptr, 0, &attempts, small, fx, wr, loads);
         out->attempts = (uint32_t)attempts;
         if (rc != MBE_OK) return rc;
     }
@@ -538,7 +539,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
                bool diag, bool enumerate, bool tb, int grid, int waves, unsigned long long *run_acc, size_t run_acc_bytes,
                unsigned long long *hacc, unsigned int *hflags_out, float *ms, hipStream_t s,
                unsigned long long *graph_acc, size_t graph_acc_bytes, int *attempts, char *small, FixedRegion *fx,
-               const WideRange &wr) {
+               const WideRange &wr, std::vector<unsigned long long> *loads) {
     dims.scap = std::max<int64_t>(dims.scap, st->scap_floor);
     dims.maxdepth = std::max<int32_t>(dims.maxdepth, st->depth_floor);
     const bool wide = wr.lo < wr.hi;
@@ -624,6 +625,19 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         if (graph_acc && graph_acc != run_acc) MBE_TRY(launch_zero(graph_acc, graph_acc_bytes, s));
         MBE_TRY(launch_zero(flags, 4, s));
         MBE_TRY(launch_zero(counters, 64 * 4, s));
+        // load records (tally runs that ask for them): 3 u64 per workgroup of every launch
+        std::vector<std::pair<int, int64_t>> load_launch;  // (mask words, 0 = wide; workgroups)
+        unsigned long long *load_buf = nullptr;
+        int64_t load_n = 0;
+        if (loads && tb && !fx) {
+            for (int c = 4; c >= 0; --c)
+                if (cls_lo[c] < cls_hi[c]) load_n += cls_grid[c];
+            if (wide) load_n += wgrid;
+            MBE_TRY(st->loads.ensure(24 * (size_t)std::max<int64_t>(load_n, 1)));
+            load_buf = st->loads.as<unsigned long long>();
+            MBE_TRY(launch_zero(load_buf, 24 * (size_t)std::max<int64_t>(load_n, 1), s));
+        }
+        int64_t load_off = 0;
         MBE_TRY(hipEventRecord(st->ev0, s));
         if (!sequential) MBE_TRY(hipEventRecord(st->fork, s));
         for (int c = 4; c >= 0; --c) {
@@ -647,6 +661,11 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
             }
             // (with fixed memory the grid is at most the slots that fit)
             const int gsz = fx ? std::min(cls_grid[c], nslots) : cls_grid[c];
+            if (load_buf) {
+                ac.wg_load = load_buf + 3 * load_off;
+                load_launch.push_back({1 << c, gsz});
+                load_off += gsz;
+            }
             MBE_TRY(launch_search(ac, 1 << c, diag, enumerate, tb, cls_lo[c], cls_hi[c], counters + c, gsz, waves, cs));
             if (!sequential) {
                 MBE_TRY(hipEventRecord(st->join[c], cs));
@@ -659,6 +678,11 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
             ac.warena = aw.warena;
             ac.wl = aw.wl;
             ac.wide_items = aw.wide_items;
+            if (load_buf) {
+                ac.wg_load = load_buf + 3 * load_off;
+                load_launch.push_back({0, wgrid});
+                load_off += wgrid;
+            }
             MBE_TRY(launch_wide(ac, diag, enumerate, tb, wr.lo, wr.hi, counters + 5, wgrid, waves, s));
         }
         MBE_TRY(hipEventRecord(st->ev1, s));
@@ -668,7 +692,23 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
         MBE_TRY(hipEventElapsedTime(ms, st->ev0, st->ev1));
         if (hflags & FLAG_SHARE_MISMATCH) return MBE_ERR_DEVICE;
         if (attempts) *attempts = attempt + 1;
-        if (!(hflags & FLAG_RERUN)) break;
+        if (!(hflags & FLAG_RERUN)) {
+            if (load_buf) {
+                std::vector<unsigned long long> raw(3 * (size_t)load_off);
+                MBE_TRY(hipMemcpy(raw.data(), load_buf, raw.size() * 8, hipMemcpyDeviceToHost));
+                loads->clear();
+                int64_t at = 0;
+                for (const auto &l : load_launch)
+                    for (int64_t b = 0; b < l.second; ++b, ++at) {
+                        if (raw[3 * at] == 0) continue;  // a workgroup that found no arena slot
+                        loads->push_back((unsigned long long)l.first);
+                        loads->push_back(raw[3 * at]);
+                        loads->push_back(raw[3 * at + 1]);
+                        loads->push_back(raw[3 * at + 2]);
+                    }
+            }
+            break;
+        }
         if (attempt >= 8) return MBE_ERR_OUT_OF_MEMORY;
         if (hflags & FLAG_NO_SLOT) sequential = true;
         if (hflags & FLAG_STACK_OVERFLOW) {
@@ -996,7 +1036,7 @@ struct ServerRequest {
 
 void free_state(DeviceState *st) {
     DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->steal, &st->slots, &st->warena,
-                      &st->witems, &st->rec,
+                      &st->witems, &st->loads, &st->rec,
                       &st->rec_offs, &st->rec_tmp, &st->rec_lens, &st->canon_tmp, &st->out_tmp};
     for (DevBuf *b : bufs)
         if (b->p) {
@@ -1285,6 +1325,34 @@ int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_
 
 int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out) {
     return run(g, opt, out, nullptr, 0, 0, false);
+}
+
+int mbe_count_loads(const mbe_graph *g, const mbe_options *opt, mbe_result *out, uint64_t *rec, int64_t cap_records,
+                    int64_t *n_records) {
+    if (!out || !n_records || cap_records < 0 || (cap_records > 0 && !rec)) return MBE_ERR_INVALID_ARG;
+    *n_records = 0;
+    mbe_options o = opt ? *opt : mbe_options{};
+    o.diagnostics = 2;
+    std::vector<unsigned long long> raw;
+    const int rc = run(g, &o, out, nullptr, 0, 0, false, nullptr, false, &raw);
+    if (rc != MBE_OK) return rc;
+    const int64_t n = (int64_t)(raw.size() / 4);
+    *n_records = n;
+    if (n == 0) return MBE_OK;
+    int dev = 0, khz = 0;
+    MBE_TRY(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+    unsigned long long t0 = ~0ull;
+    for (int64_t i = 0; i < n; ++i) t0 = std::min(t0, raw[4 * i + 1]);
+    if (n > cap_records) return MBE_ERR_BUFFER_TOO_SMALL;
+    const double ns_per_tick = 1.0e6 / (double)khz;
+    for (int64_t i = 0; i < n; ++i) {
+        rec[4 * i] = raw[4 * i];
+        rec[4 * i + 1] = (uint64_t)((double)(raw[4 * i + 1] - t0) * ns_per_tick);
+        rec[4 * i + 2] = (uint64_t)((double)(raw[4 * i + 2] - t0) * ns_per_tick);
+        rec[4 * i + 3] = (uint64_t)((double)raw[4 * i + 3] * ns_per_tick);
+    }
+    return MBE_OK;
 }
 
 int mbe_count_noalloc(const mbe_graph *g, const mbe_options *opt, mbe_result *out) {

@@ -187,6 +187,12 @@ struct SearchArgs {
     char *warena;
     WideLayout wl;
     unsigned int *wide_items;
+    // candidate pruning (wide search only, when not NULL): twin[v] = the lowest rank of a
+    // candidate whose row equals v's
+    const int32_t *twin;
+    // load records (tally instances only, when not NULL): per workgroup of the launch, its
+    // start and end on the wall clock and the time it spent finding work (3 u64 each)
+    unsigned long long *wg_load;
     // record arena (mbe_enumerate only)
     int32_t *rec;
     unsigned long long rec_cap;
@@ -212,7 +218,7 @@ hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, 
 // top-level candidates is shared by wl.reps workgroups; counter must be zero.
 WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdepth, int waves);
 hipError_t launch_wide(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi,
-                       unsigned int *counter, int grid, int waves, hipStream_t s);
+                       unsigned int *counter, int grid, int waves, hipStream_t s, bool prune = false);
 
 // Graph preparation and validation (mbe_prep.hip).
 hipError_t launch_validate(int32_t n_u, int32_t n_v, int32_t n_edges, const int32_t *u_off, const int32_t *u_adj,
@@ -230,6 +236,15 @@ hipError_t radix_sort_u64(void *temp, size_t *temp_bytes, const unsigned long lo
 // 4-byte aligned; the 2-D form clears rows runs of width_bytes spaced pitch bytes apart.
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_zero_2d(void *base, size_t pitch, size_t width_bytes, size_t rows, hipStream_t s);
+
+// Twins for the candidate pruning (mbe_prep.hip): row keys, their sort, and twin[v] = the
+// lowest rank with v's exact row.
+hipError_t launch_row_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, unsigned long long *key,
+                           unsigned int *val, hipStream_t s);
+hipError_t sort_pairs_u64_u32(void *temp, size_t *temp_bytes, const unsigned long long *kin, unsigned long long *kout,
+                              const unsigned int *vin, unsigned int *vout, int32_t n, hipStream_t s);
+hipError_t launch_twins(int32_t nc, const unsigned long long *key, const unsigned int *val, const int32_t *c_off,
+                        const int32_t *c_adj, const int32_t *rank, int32_t *twin, hipStream_t s);
 
 // Batched preparation (mbe_prep.hip).
 hipError_t launch_batch_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, const int32_t *o_off,

@@ -196,6 +196,60 @@ __global__ void zero_2d_kernel(char *base, size_t pitch, int64_t words, int64_t 
     }
 }
 
+// Twins (candidates with equal neighbour rows), for the candidate pruning of section II-C:
+// key[v] = a hash of v's degree and row (order-independent SplitMix64 sum), ~0 for degree-0
+// candidates, so that a sort groups equal rows; val[v] = v.
+__device__ __forceinline__ unsigned long long prep_mix(unsigned long long z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+__global__ void row_key_kernel(int32_t nc, const int32_t *c_off, const int32_t *c_adj, unsigned long long *key,
+                               unsigned int *val) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nc; v += stride) {
+        const int32_t b = c_off[v], e = c_off[v + 1];
+        unsigned long long h = prep_mix(0x9E3779B97F4A7C15ull * (unsigned long long)(e - b + 1));
+        for (int32_t p = b; p < e; ++p) h += prep_mix(0x9E3779B97F4A7C15ull * (unsigned long long)(c_adj[p] + 7));
+        key[v] = e > b ? h : ~0ull;
+        val[v] = (unsigned int)v;
+    }
+}
+
+// After the sort by key: twin[v] = the lowest rank among the candidates whose row equals v's
+// (v's own rank when none ranks lower); rows are compared in full within each run of equal
+// keys, so a hash collision never makes twins.
+__global__ void twin_kernel(int32_t nc, const unsigned long long *key, const unsigned int *val, const int32_t *c_off,
+                            const int32_t *c_adj, const int32_t *rank, int32_t *twin) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nc; p += stride) {
+        const unsigned long long k = key[p];
+        const int32_t v = (int32_t)val[p];
+        if (k == ~0ull) {
+            twin[v] = -1;
+            continue;
+        }
+        int64_t s = p;
+        while (s > 0 && key[s - 1] == k) --s;
+        const int32_t vb = c_off[v], d = c_off[v + 1] - vb;
+        int32_t best = rank[v];
+        for (int64_t q = s; q < nc && key[q] == k; ++q) {
+            const int32_t u = (int32_t)val[q];
+            if (rank[u] >= best) continue;
+            const int32_t ub = c_off[u];
+            if (c_off[u + 1] - ub != d) continue;
+            bool same = true;
+            for (int32_t t = 0; t < d && same; ++t) same = c_adj[ub + t] == c_adj[vb + t];
+            if (same) best = rank[u];
+        }
+        twin[v] = best;
+    }
+}
+
 int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;
@@ -247,6 +301,25 @@ hipError_t launch_batch_scatter(int32_t nc, const unsigned long long *sorted, co
     hipLaunchKernelGGL(batch_scatter_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, sorted, graph_of, cbase,
                        gstats, order, rank, task_key, task, tbase);
     return hipGetLastError();
+}
+
+hipError_t launch_row_keys(int32_t nc, const int32_t *c_off, const int32_t *c_adj, unsigned long long *key,
+                           unsigned int *val, hipStream_t s) {
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(row_key_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, c_off, c_adj, key, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_twins(int32_t nc, const unsigned long long *key, const unsigned int *val, const int32_t *c_off,
+                        const int32_t *c_adj, const int32_t *rank, int32_t *twin, hipStream_t s) {
+    if (nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(twin_kernel, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, key, val, c_off, c_adj, rank, twin);
+    return hipGetLastError();
+}
+
+hipError_t sort_pairs_u64_u32(void *temp, size_t *temp_bytes, const unsigned long long *kin, unsigned long long *kout,
+                              const unsigned int *vin, unsigned int *vout, int32_t n, hipStream_t s) {
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, kin, kout, vin, vout, (unsigned int)n, 0, 64, s);
 }
 
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {

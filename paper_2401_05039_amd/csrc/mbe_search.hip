@@ -1476,6 +1476,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
     const int ucap = a.dims.ucap;
     if (tid < 16) sh->red[tid] = 0ull;
     uint64_t t_mark = DIAG ? clock64() : 0ull;  // start of the phase being timed
+    // (tally instances) this workgroup's start on the wall clock and its time finding work
+    const uint64_t ld_start = TB ? wall_clock64() : 0ull;
+    uint64_t ld_wait = 0;
     if (tid == 0) {
         sh->graph = -1;
         sh->held = 0;
@@ -1497,6 +1500,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
                 sh->held = 0;
             }
             bool waited = false;
+            const uint64_t ld_w0 = TB ? wall_clock64() : 0ull;
             for (;;) {
                 int mode = 0;
                 unsigned int t = 0;
@@ -1607,6 +1611,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
                     sh->held = 1;
                 }
             }
+            if (TB) ld_wait += wall_clock64() - ld_w0;
         }
         __syncthreads();
         if (DIAG) {
@@ -2333,6 +2338,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
     if (sh->graph >= 0) flush_acc<DIAG, TB>(acc, a.graphs[sh->graph].acc, sh);
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (TB && a.wg_load) {
+            a.wg_load[3 * (size_t)blockIdx.x] = ld_start;
+            a.wg_load[3 * (size_t)blockIdx.x + 1] = wall_clock64();
+            a.wg_load[3 * (size_t)blockIdx.x + 2] = ld_wait;
+        }
         __threadfence();
         atomicExch(&a.slot_busy[my_slot], 0u);
     }
@@ -2845,6 +2855,7 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
     w.Rr = reinterpret_cast<uint64_t *>(wv + L.off_w_rr);
 
     WaveAcc acc{};
+    const uint64_t ld_start = TB ? wall_clock64() : 0ull;
     const int ucap = a.dims.ucap;
     const int64_t nroots = hi - lo;
     const int64_t ntasks = nroots * (int64_t)L.reps;
@@ -3175,6 +3186,11 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
         __syncthreads();
     }
     if (sh->graph >= 0) flush_acc<DIAG, TB>(acc, a.graphs[sh->graph].acc, sh);
+    if (TB && a.wg_load && tid == 0) {
+        a.wg_load[3 * (size_t)blockIdx.x] = ld_start;
+        a.wg_load[3 * (size_t)blockIdx.x + 1] = wall_clock64();
+        a.wg_load[3 * (size_t)blockIdx.x + 2] = 0ull;  // replicas take chunks without waiting
+    }
 }
 
 size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + hist_region_bytes(64 * W, waves) + (size_t)waves * kWaveLds; }

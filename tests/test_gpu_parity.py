@@ -560,3 +560,34 @@ def test_enumerate_crown20_closed_form(mbe):
         h = _mix_np(sa + _mix_np(sb + np.uint64(K)))
         total = int(h.sum(dtype=np.uint64))
     assert res["hash"] == total
+
+
+# ----------------------------------------------------------------------------- tallies and load records
+
+def test_design_bytes_independent_of_launch_shape(mbe):
+    g = gg.config1()
+    _say("design bytes shapes")
+    base = mbe.mbe_count(g, mbe.Options(diagnostics=2))
+    assert base["bytes_design"] > 0 and base["nodes"] == 0
+    for waves, grid, sk in ((4, 3, 2), (8, 1, 3), (2, 0, 1)):
+        r = mbe.mbe_count(g, mbe.Options(diagnostics=2, wg_waves=waves, grid=grid, steal_k=sk))
+        assert (r["count"], r["hash"], r["bytes_design"]) == (base["count"], base["hash"], base["bytes_design"])
+
+
+def test_load_records(mbe, orc):
+    g = gg.config1()
+    want = orc.mbea(g)
+    _say("load records")
+    for sk in (1, 2, 3):
+        res, rec = mbe.mbe_count_loads(g, mbe.Options(steal_k=sk, grid=16))
+        assert (res["count"], res["hash"]) == (want["count"], want["hash"])
+        assert 1 <= len(rec) <= 16 * 5
+        w, start, end, wait = (rec[:, k].astype(np.int64) for k in range(4))
+        assert set(w.tolist()) <= {0, 1, 2, 4, 8, 16}
+        assert start.min() == 0 and (end >= start).all() and (wait <= end - start).all()
+    # the wide search's workgroups report too
+    res, rec = mbe.mbe_count_loads(gg.complete(3, 2000))
+    assert res["count"] == 1 and 0 in set(rec[:, 0].tolist())
+    with pytest.raises(mbe.MbeError) as e:
+        mbe.mbe_count_loads(g, cap=0)
+    assert e.value.code == -3
