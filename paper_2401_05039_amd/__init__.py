@@ -57,7 +57,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("side", ctypes.c_int32), ("wg_waves", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("diagnostics", ctypes.c_int32), ("no_validate", ctypes.c_int32),
                 ("steal_k", ctypes.c_int32), ("root_lo", ctypes.c_int64),
-                ("root_hi", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+                ("root_hi", ctypes.c_int64), ("stream", ctypes.c_void_p), ("prune", ctypes.c_int32)]
 
 
 @dataclasses.dataclass
@@ -72,6 +72,7 @@ class Options:
     root_lo: int = 0
     root_hi: int = 0
     stream: Optional[int] = None  # hipStream_t as an integer; None = torch's current stream
+    prune: bool = False  # iMBEA's candidate pruning (the same answer, the pruned tree's tallies)
 
 
 class _ServerOptions(ctypes.Structure):
@@ -177,7 +178,7 @@ def _marshal_opts(opt: Optional[Options], on_device: bool) -> _Options:
         import torch
         stream = torch.cuda.current_stream().cuda_stream
     return _Options(opt.side, opt.wg_waves, opt.grid, int(opt.diagnostics), int(bool(opt.no_validate)),
-                    opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0))
+                    opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0), int(bool(opt.prune)))
 
 
 PHASES = ("root", "light", "check", "expand", "child", "wait")

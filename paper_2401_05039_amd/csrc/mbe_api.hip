@@ -56,7 +56,7 @@ struct DevBuf {
 
 struct DeviceState {
     std::mutex mu;
-    DevBuf graph, prep, sort_tmp, arena, small, steal, slots, warena, witems, loads;
+    DevBuf graph, prep, sort_tmp, arena, small, steal, slots, warena, witems, loads, twin;
     DevBuf rec, rec_offs, rec_tmp, rec_lens, canon_tmp, out_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int cus = 0;
@@ -179,19 +179,22 @@ constexpr size_t kWideArenaBytes = (size_t)4 << 30;
 
 struct Opts {
     int side, waves, grid, diag, no_validate, steal_k;
-    int tb;  // diagnostics = 2: the production search with its design-byte tally
+    int tb;     // diagnostics = 2: the production search with its design-byte tally
+    int prune;  // the candidate pruning of section II-C
     int64_t root_lo, root_hi;
     hipStream_t stream;
 };
 
 Opts read_opts(const mbe_options *o) {
-    Opts r{0, 8, 0, 0, 0, 2, 0, 0, -1, nullptr};
+    Opts r{0, 8, 0, 0, 0, 2, 0, 0, 0, -1, nullptr};
     if (!o) return r;
     r.side = o->side;
     r.waves = o->wg_waves > 0 ? o->wg_waves : 8;
     r.grid = o->grid > 0 ? o->grid : 0;
     r.diag = o->diagnostics == 1;
     r.tb = o->diagnostics == 2;
+    r.prune = o->prune != 0;
+    if (r.prune && r.tb) r.side = -1;  // (no tally instance with pruning: rejected)
     if (o->diagnostics < 0 || o->diagnostics > 2) r.side = -1;  // (rejected as an invalid argument)
     r.no_validate = o->no_validate != 0;
     r.steal_k = o->steal_k == 0 ? 2 : o->steal_k;
@@ -355,10 +358,41 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     const int64_t lo = std::min<int64_t>(opt.root_lo, ncand);
     const int64_t hi = opt.root_hi < 0 ? ncand : std::min<int64_t>(opt.root_hi, ncand);
     // candidates of degree above 64 * 16 rank after every class: the wide search takes them
+    // (with the candidate pruning, it takes every top-level candidate)
     WideRange wr;
     wr.lo = std::max<int64_t>(run_r, lo);
     wr.hi = std::min<int64_t>(run_r + (int64_t)hstats[6] + (int64_t)hstats[7], hi);
     wr.Wx = (int)((hstats[8] + 63) / 64);
+    int32_t *twin = nullptr;
+    if (opt.prune) {
+        wr.lo = lo;
+        wr.hi = hi;
+        for (int c = 0; c < 5; ++c) cls_lo[c] = cls_hi[c] = 0;
+        // twins: candidates with equal rows, found by a sort of row keys; twin[v] = the lowest
+        // rank with v's row
+        const size_t b_k = align_up((size_t)nc * 8, 256), b_v = align_up((size_t)nc * 4, 256);
+        char *tw = nullptr;
+        MBE_CALL(mem(st->twin, 2 * b_k + 3 * b_v, &tw));
+        unsigned long long *tkey = reinterpret_cast<unsigned long long *>(tw);
+        unsigned long long *tkey2 = reinterpret_cast<unsigned long long *>(tw + b_k);
+        unsigned int *tval = reinterpret_cast<unsigned int *>(tw + 2 * b_k);
+        unsigned int *tval2 = reinterpret_cast<unsigned int *>(tw + 2 * b_k + b_v);
+        twin = reinterpret_cast<int32_t *>(tw + 2 * b_k + 2 * b_v);
+        MBE_TRY(launch_row_keys(nc, c_off, c_adj, tkey, tval, s));
+        size_t tb_bytes = 0;
+        MBE_TRY(sort_pairs_u64_u32(nullptr, &tb_bytes, tkey, tkey2, tval, tval2, nc, s));
+        char *ttmp = nullptr;
+        if (fx) {
+            MBE_CALL(mem(st->sort_tmp, tb_bytes, &ttmp));
+        } else {
+            // (the ranking's sort temporaries are done with)
+            MBE_TRY(st->sort_tmp.ensure(tb_bytes));
+            ttmp = st->sort_tmp.as<char>();
+            tb_bytes = st->sort_tmp.bytes;
+        }
+        MBE_TRY(sort_pairs_u64_u32(ttmp, &tb_bytes, tkey, tkey2, tval, tval2, nc, s));
+        MBE_TRY(launch_twins(nc, tkey2, tval2, c_off, c_adj, rank, twin, s));
+    }
 
     const int waves = opt.waves;
     const int grid = opt.grid > 0 ? opt.grid : 0;  // 0: occupancy-sized per class
@@ -407,6 +441,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     MBE_TRY(hipMemcpyAsync(d_gd, &gd, sizeof(gd), hipMemcpyHostToDevice, s));
 
     SearchArgs a{};
+    a.twin = twin;
     a.steal_on = opt.steal_k >= 2 ? 1 : 0;
     a.k3 = opt.steal_k >= 3 ? 1 : 0;
     a.c_off = c_off;
@@ -683,7 +718,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
                 load_launch.push_back({0, wgrid});
                 load_off += wgrid;
             }
-            MBE_TRY(launch_wide(ac, diag, enumerate, tb, wr.lo, wr.hi, counters + 5, wgrid, waves, s));
+            MBE_TRY(launch_wide(ac, diag, enumerate, tb, wr.lo, wr.hi, counters + 5, wgrid, waves, s, a.twin != nullptr));
         }
         MBE_TRY(hipEventRecord(st->ev1, s));
         MBE_TRY(hipMemcpyAsync(hacc, run_acc, ACC_SLOTS * 8, hipMemcpyDeviceToHost, s));
@@ -785,6 +820,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
 int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_result *outs) {
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
     const Opts opt = read_opts(opt_in);
+    if (opt.prune) return MBE_ERR_INVALID_ARG;
     if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
         opt.steal_k < 1 || opt.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
@@ -1036,7 +1072,7 @@ struct ServerRequest {
 
 void free_state(DeviceState *st) {
     DevBuf *bufs[] = {&st->graph, &st->prep, &st->sort_tmp, &st->arena, &st->small, &st->steal, &st->slots, &st->warena,
-                      &st->witems, &st->loads, &st->rec,
+                      &st->witems, &st->loads, &st->twin, &st->rec,
                       &st->rec_offs, &st->rec_tmp, &st->rec_lens, &st->canon_tmp, &st->out_tmp};
     for (DevBuf *b : bufs)
         if (b->p) {
@@ -1332,6 +1368,7 @@ int mbe_count_loads(const mbe_graph *g, const mbe_options *opt, mbe_result *out,
     if (!out || !n_records || cap_records < 0 || (cap_records > 0 && !rec)) return MBE_ERR_INVALID_ARG;
     *n_records = 0;
     mbe_options o = opt ? *opt : mbe_options{};
+    if (o.prune) return MBE_ERR_INVALID_ARG;
     o.diagnostics = 2;
     std::vector<unsigned long long> raw;
     const int rc = run(g, &o, out, nullptr, 0, 0, false, nullptr, false, &raw);

@@ -109,6 +109,7 @@ struct WideLayout {
     size_t wave_bytes;   // stride between waves
     size_t off_w_stack;  // u32[scap]              frames
     size_t off_w_u;      // u32[ucap]              a maximal node's entries, in list order
+    size_t off_w_u2;     // u32[ucap]              (candidate pruning) the same, regrouped
     size_t off_w_bl;     // u32[64*Wx]             the bits of a node's R'
     size_t off_w_hist;   // u32[64*Wx+2]           counting-sort histogram of a child list
     size_t off_w_mr;     // u64[Wx]                a node's R' words

@@ -2414,6 +2414,7 @@ __device__ __forceinline__ WFrameView wframe_view(uint32_t *base, int n, int rb)
 // The wave's scratch of the wide search.
 struct WCtx {
     Ctx c;
+    uint32_t *stu2;  // (candidate pruning) a child list's entries while they are regrouped
     uint32_t *bl;    // the bits of R' (frame bit indices), ascending
     uint32_t *hist;  // counting-sort histogram of a child list
     uint64_t *mR;    // R' words (frame bits)
@@ -2422,7 +2423,10 @@ struct WCtx {
 
 // Candidates [base, base + 64) of frame F: lanes with |R'| = 1 are settled (when settle), the
 // lanes with |R'| >= 2 are returned.
-template <bool DIAG, bool ENUM, bool TB>
+// IMB: the candidate pruning of section II-C (see heavy_wide); a single-bit candidate whose
+// bit is first held by an earlier candidate of the list (a twin, maximal as the first holder)
+// left the list with it and is not a node.
+template <bool DIAG, bool ENUM, bool TB, bool IMB = false>
 __device__ __forceinline__ uint64_t light_wide(const WCtx &w, const FrameState &F, const WFrameView &v, int base,
                                                WaveAcc &acc) {
     const Ctx &c = w.c;
@@ -2442,13 +2446,14 @@ __device__ __forceinline__ uint64_t light_wide(const WCtx &w, const FrameState &
     if (ENUM) return __ballot(act);
     if (act && r == 1) {
         const bool maximal = v.first[b] == (uint32_t)i;  // no earlier entry holds bit b
+        const bool gone = IMB && v.first[b] >= (uint32_t)F.nq && v.first[b] < (uint32_t)i;
         const uint32_t rp = v.orig[b];
         if (maximal) {
             acc.count += 1;
             acc.hash += pair_hash(c.c_is_v, F.sL + v.H[b], c.hvl[rp]);
             acc.out_ints += 2ull + (uint64_t)F.nL + (uint64_t)v.cnt[b] + 1ull;
         }
-        if (DIAG) {
+        if (DIAG && !gone) {
             acc.nodes += 1;
             if (!maximal) acc.nonmax += 1;
             if ((uint32_t)F.level > acc.max_depth) acc.max_depth = (uint32_t)F.level;
@@ -2476,7 +2481,13 @@ __device__ __forceinline__ void wide_table_add(const WFrameView &v2, int q, uint
 // The candidate at position i of frame F, |R'| >= 2, handled by the whole wave (maximality
 // check, expansion, report, child list).  Returns true when a child frame was written (its
 // state in C).
-template <bool DIAG, bool ENUM, bool TB>
+// IMB: the candidate pruning of section II-C.  Candidates of a list are sorted by count, so an
+// earlier candidate holding all of a candidate's mask has the same mask (a twin).  When x is
+// maximal, its later twins leave the list and join Q with x: a twin whose first twin (the
+// earliest) is maximal is never a node, and for the nodes between the two it is a Q entry --
+// their child lists take it into Q' instead of P'.  The first twin is maximal exactly when no
+// Q entry of the list holds the mask.
+template <bool DIAG, bool ENUM, bool TB, bool IMB = false>
 __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, const WFrameView &v, int i, FrameState &C,
                                            WaveAcc &acc) {
     const Ctx &c = w.c;
@@ -2511,10 +2522,11 @@ __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, c
     bool fh = false;
     for (int t = ln; t < r; t += 64)
         if (v.first[w.bl[t]] == (uint32_t)i) fh = true;
-    bool nonmax = false;
+    bool nonmax = false, gone = false;
     if (!__ballot(fh)) {
         const int wl = i >> 6;
-        for (int base = 0; base <= wl && !nonmax; base += 64) {
+        bool inq = false, inp = false;  // (IMB) holders of R' among the Q entries, among earlier candidates
+        for (int base = 0; base <= wl && (IMB || !nonmax); base += 64) {
             const int wd = base + ln;
             const bool in = wd <= wl;
             uint64_t a = in ? ~0ull : 0ull;
@@ -2526,9 +2538,17 @@ __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, c
             }
             if (wd == wl) a &= (1ull << (i & 63)) - 1ull;
             if (__ballot(a != 0ull)) nonmax = true;
+            if (IMB) {
+                const int q0 = F.nq - 64 * wd;  // positions of word wd below nq
+                const uint64_t qm = q0 >= 64 ? ~0ull : (q0 <= 0 ? 0ull : ((1ull << q0) - 1ull));
+                inq = inq || (a & qm) != 0ull;
+                inp = inp || (a & ~qm) != 0ull;
+            }
             if (TB && ln == 0) acc.dbytes += 8ull * (uint64_t)(t < r ? t + 1 : r) * (uint64_t)min(64, wl + 1 - base);
         }
+        if (IMB) gone = !__ballot(inq) && __ballot(inp);
     }
+    if (gone) return false;  // left the list with its first twin: not a node
     uint64_t dx = 0, rs = 0;
     if (DIAG) {
         dx = deg_of(c, v.ids[i]);
@@ -2592,10 +2612,72 @@ __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, c
             nu += last_lane(incl);
         }
     }
-    const int qn = wave_sum_i32(qn_l);
+    int qn = wave_sum_i32(qn_l);
     const int ne = wave_sum_i32(ne_l);
-    const int pn = nu - qn;
     wait_mem();  // stu is read by other lanes below
+    if (IMB) {
+        // entries after i that left the list with an earlier twin (of the same count as i, a
+        // twin before i, none of the Q entries holding their mask) are Q entries for i: they go
+        // to Q' (stu becomes Q' | the moved ones | the rest of P', each in list order)
+        const int wl = i >> 6;
+        int nmv = 0;
+        for (int base = qn; base < nu; base += 64) {
+            const int j = base + ln;
+            bool mv = false;
+            uint32_t k = 0;
+            if (j < nu) {
+                k = c.stu[j];
+                int cnt = 0;
+                for (int q = 0; q < wf; ++q) cnt += __popcll(v.masks[(size_t)k * wf + q]);
+                if (cnt == r) {
+                    bool inq = false, inp = false;
+                    for (int wd = 0; wd <= wl; ++wd) {
+                        uint64_t a = ~0ull;
+                        for (int q = 0; q < wf && a; ++q) {
+                            uint64_t x = v.masks[(size_t)k * wf + q];
+                            while (x && a) {
+                                const int bt = 64 * q + __ffsll((unsigned long long)x) - 1;
+                                x &= x - 1ull;
+                                a &= v.rows[(size_t)bt * v.nw + wd];
+                            }
+                        }
+                        if (wd == wl) a &= (1ull << (i & 63)) - 1ull;
+                        const int q0 = F.nq - 64 * wd;
+                        const uint64_t qm = q0 >= 64 ? ~0ull : (q0 <= 0 ? 0ull : ((1ull << q0) - 1ull));
+                        inq = inq || (a & qm) != 0ull;
+                        inp = inp || (a & ~qm) != 0ull;
+                    }
+                    mv = inp && !inq;
+                }
+                c.stu[j] = k | (mv ? 0x80000000u : 0u);  // (positions are below 2^31)
+            }
+            nmv += __popcll(__ballot(mv));
+        }
+        if (nmv > 0) {
+            wait_mem();
+            // stable partition of stu[qn, nu) into the moved entries, then the others
+            int am = qn, ak = qn + nmv;
+            for (int base = qn; base < nu; base += 64) {
+                const int j = base + ln;
+                const uint32_t e = j < nu ? c.stu[j] : 0u;
+                const bool act = j < nu;
+                const bool mv = act && (e & 0x80000000u);
+                const uint64_t bm = __ballot(mv), bk = __ballot(act && !mv);
+                if (mv) w.stu2[am - qn + __popcll(bm & below)] = e & 0x7FFFFFFFu;
+                if (act && !mv) w.stu2[ak - qn + __popcll(bk & below)] = e;
+                am += __popcll(bm);
+                ak += __popcll(bk);
+            }
+            wait_mem();
+            for (int j = qn + ln; j < nu; j += 64) c.stu[j] = w.stu2[j - qn];
+            wait_mem();
+            qn += nmv;
+        } else {
+            for (int j = qn + ln; j < nu; j += 64) c.stu[j] &= 0x7FFFFFFFu;
+            wait_mem();
+        }
+    }
+    const int pn = nu - qn;
     // histogram of the P' counts |mask n R'|
     for (int b = ln; b <= r; b += 64) w.hist[b] = 0u;
     wait_mem();
@@ -2806,7 +2888,11 @@ __device__ __forceinline__ void wave_sort_by_key_g(const uint32_t *src, const ui
     }
 }
 
-template <bool DIAG, bool ENUM, bool TB>
+// IMB: with the candidate pruning of section II-C (every top-level candidate is searched here
+// then): see heavy_wide; at the top level a candidate's twins are the candidates with its exact
+// row (a.twin), every first twin is maximal (no earlier candidate can hold its row), and the
+// later twins are never nodes.
+template <bool DIAG, bool ENUM, bool TB, bool IMB = false>
 __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
     extern __shared__ unsigned char lds_raw[];
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
@@ -2849,6 +2935,7 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
     c.rec_offs_cap = a.rec_offs_cap;
     c.acc = a.acc;
     c.flags = a.flags;
+    w.stu2 = reinterpret_cast<uint32_t *>(wv + L.off_w_u2);
     w.bl = reinterpret_cast<uint32_t *>(wv + L.off_w_bl);
     w.hist = reinterpret_cast<uint32_t *>(wv + L.off_w_hist);
     w.mR = reinterpret_cast<uint64_t *>(wv + L.off_w_mr);
@@ -3022,7 +3109,9 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
         const int P1 = uni(sh->pcount);
         if (tid == 0 && owner) {
             const uint64_t dx = (uint64_t)d;
-            if (DIAG) {
+            // (IMB: a top-level candidate with an earlier twin is exactly a non-maximal one,
+            // and it left the list with its first twin: not a node)
+            if (DIAG && !(IMB && root_nonmax)) {
                 acc.nodes += 1;
                 if (acc.max_depth < 1) acc.max_depth = 1;
                 const uint64_t fwtop = gd.total_fw - (2ull + dx);
@@ -3062,22 +3151,30 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
         uint32_t *ids1 = s1;
         for (int li = tid; li < nq0; li += nt) ids1[li] = (uint32_t)li;
         if (wid == 0) {
-            int pn = 0;
+            // (IMB) candidates ranked after x with a twin ranked before x left the list with it:
+            // they join Q1, after the earlier ranks, in rank order
+            int pn = 0, nmv = 0;
             for (int base = nq0; base < s0; base += 64) {
                 const int li = base + ln;
                 const bool act2 = li < s0;
                 const uint32_t cc = act2 ? cnt1[li] : 0u;
-                const bool pk = act2 && (int)cc < d;
-                const uint64_t pb = __ballot(pk);
+                const bool cand = act2 && (int)cc < d;
+                const bool mv = IMB && cand && a.twin[gid[li]] < (int32_t)k;
+                const bool pk = cand && !mv;
+                const uint64_t pb = __ballot(pk), mb = __ballot(mv);
                 if (pk) {
                     const int p = pn + __popcll(pb & lanes_below());
                     t1v[p] = (uint32_t)li;
                     t1c[p] = cc;
                 }
+                if (mv) ids1[nq0 + nmv + __popcll(mb & lanes_below())] = (uint32_t)li;
                 pn += __popcll(pb);
+                nmv += __popcll(mb);
             }
+            if (ln == 0) sh->pcount = pn;  // the candidates left in the list
             wait_mem();
-            wave_sort_by_key_g(t1v, t1c, pn, d, whist, [&](uint32_t slot, uint32_t li) { ids1[nq0 + slot] = li; });
+            const int q1 = nq0 + nmv;
+            wave_sort_by_key_g(t1v, t1c, pn, d, whist, [&](uint32_t slot, uint32_t li) { ids1[q1 + slot] = li; });
         }
         for (int b = tid; b < d; b += nt) {
             v1.first[b] = kNone;
@@ -3120,11 +3217,12 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
                           (uint64_t)n1 * (24ull + 16ull * (uint64_t)wd) + 32ull * (uint64_t)d +
                           8ull * (uint64_t)n1 * (uint64_t)wd + 8ull * (uint64_t)d * (uint64_t)v1.nw;
 
+        const int P1c = IMB ? uni(sh->pcount) : P1;  // candidates of the list
         FrameState top;
         top.off = kShared;
         top.top = 0;
         top.n = n1;
-        top.nq = nq0;
+        top.nq = n1 - P1c;
         top.level = 2;
         top.nL = 1 + uni(sh->nexp);
         top.wf = wd;
@@ -3134,7 +3232,7 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
         top.heavy = 0ull;
         top.sL = hl(c, x) + uni((uint64_t)sh->exps);
         top.fw = uni((uint64_t)sh->fw1);
-        const int nch = (P1 + 63) >> 6;
+        const int nch = (P1c + 63) >> 6;
 
         // -- chunks of the top-level list, claimed by every wave of every replica; each wave
         //    searches depth-first below the candidates of its chunk
@@ -3146,8 +3244,8 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
             if (q >= nch) break;
             if (uni(__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & FLAG_RERUN) break;
             FrameState cur = top;
-            cur.chunk = nq0 + 64 * q;
-            cur.heavy = light_wide<DIAG, ENUM, TB>(w, cur, v1, cur.chunk, acc);
+            cur.chunk = top.nq + 64 * q;
+            cur.heavy = light_wide<DIAG, ENUM, TB, IMB>(w, cur, v1, cur.chunk, acc);
             int depth = 0;
             while (!aborted) {
                 const WFrameView v = wframe_view(frame_base(c, cur.off), cur.n, cur.rbits);
@@ -3160,13 +3258,13 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
                         continue;
                     }
                     cur.chunk = base;
-                    cur.heavy = light_wide<DIAG, ENUM, TB>(w, cur, v, base, acc);
+                    cur.heavy = light_wide<DIAG, ENUM, TB, IMB>(w, cur, v, base, acc);
                     continue;
                 }
                 const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
                 cur.heavy &= cur.heavy - 1ull;
                 FrameState ch;
-                if (heavy_wide<DIAG, ENUM, TB>(w, cur, v, cur.chunk + lane, ch, acc)) {
+                if (heavy_wide<DIAG, ENUM, TB, IMB>(w, cur, v, cur.chunk + lane, ch, acc)) {
                     if (depth + 1 >= L.maxdepth) {
                         if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
                         aborted = true;
@@ -3278,6 +3376,7 @@ WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdep
     };
     L.off_w_stack = wtake((size_t)scap * 4);
     L.off_w_u = wtake(ucap * 4);
+    L.off_w_u2 = wtake(ucap * 4);
     L.off_w_bl = wtake(bits * 4);
     L.off_w_hist = wtake((bits + 2) * 4);
     L.off_w_mr = wtake(W * 8);
@@ -3289,9 +3388,18 @@ WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdep
 }
 
 hipError_t launch_wide(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi,
-                       unsigned int *counter, int grid, int waves, hipStream_t s) {
+                       unsigned int *counter, int grid, int waves, hipStream_t s, bool prune) {
     dim3 g(grid), b(64 * waves);
     const size_t lds = sizeof(WGShared);
+    if (prune) {
+        if (enumerate)
+            hipLaunchKernelGGL((wide_kernel<false, true, false, true>), g, b, lds, s, a, lo, hi, counter);
+        else if (diag)
+            hipLaunchKernelGGL((wide_kernel<true, false, false, true>), g, b, lds, s, a, lo, hi, counter);
+        else
+            hipLaunchKernelGGL((wide_kernel<false, false, false, true>), g, b, lds, s, a, lo, hi, counter);
+        return hipGetLastError();
+    }
     if (tb && !diag && !enumerate)
         hipLaunchKernelGGL((wide_kernel<false, false, true>), g, b, lds, s, a, lo, hi, counter);
     else if (diag && enumerate)

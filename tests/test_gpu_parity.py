@@ -591,3 +591,92 @@ def test_load_records(mbe, orc):
     with pytest.raises(mbe.MbeError) as e:
         mbe.mbe_count_loads(g, cap=0)
     assert e.value.code == -3
+
+
+# ----------------------------------------------------------------------------- candidate pruning (iMBEA)
+
+def _with_twins(g, k, seed):
+    """g plus copies of k of its candidate-side rows (twins across the whole graph)."""
+    us, vs = g.edges()
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(g.n_u, size=min(k, g.n_u), replace=False)
+    cu, cv = [], []
+    for j, u in enumerate(pick):
+        row = g.row_u(int(u))
+        cu += [g.n_u + j] * len(row)
+        cv += list(row)
+    return gg.from_edges(g.n_u + len(pick), g.n_v, np.concatenate([us, cu]).astype(np.int64),
+                         np.concatenate([vs, cv]).astype(np.int64), name=f"{g.name}+twins{k}")
+
+
+def _prune_check(mbe, orc, g, name, **kw):
+    _say("prune", name, g.n_u, g.n_v, g.n_edges)
+    want = orc.imbea(g)
+    got = mbe.mbe_count(g, mbe.Options(diagnostics=True, prune=True, **kw))
+    for k in DIAG_KEYS:
+        assert got[k] == want[k], (name, k, got[k], want[k])
+    fast = mbe.mbe_count(g, mbe.Options(prune=True, **kw))
+    for k in ("count", "hash", "out_ints", "side"):
+        assert fast[k] == want[k], (name, "fast", k, fast[k], want[k])
+    return got
+
+
+def test_prune_closed_forms(mbe, orc):
+    blocks = gg.disjoint_union(gg.disjoint_union(gg.complete(2, 3), gg.complete(4, 1)), gg.complete(3, 3))
+    hand = gg.from_edges(3, 3, [0, 0, 1, 1, 2, 2], [0, 1, 0, 1, 1, 2])
+    for g in (gg.complete(3, 4), gg.complete(12, 30), blocks, hand, gg.crown(7), gg.chain(9), gg.perfect_matching(6),
+              gg.complete_minus_edge(4, 6), gg.complete(2, 1500)):
+        _prune_check(mbe, orc, g, g.name)
+    r = mbe.mbe_count(gg.complete(12, 30), mbe.Options(diagnostics=True, prune=True))
+    assert (r["nodes"], r["nonmaximal"]) == (1, 0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_prune_random_with_twins(mbe, orc, seed):
+    rng = np.random.default_rng(50 + seed)
+    for k in range(12):
+        nu, nv = int(rng.integers(4, 40)), int(rng.integers(8, 50))
+        g = gg.random_small(nu, nv, float(rng.uniform(0.1, 0.6)), 8000 + 100 * seed + k)
+        _prune_check(mbe, orc, _with_twins(g, int(rng.integers(1, 8)), k), f"twins{seed}.{k}")
+
+
+def test_prune_workloads(mbe, orc):
+    g1 = gg.config1()
+    base = _prune_check(mbe, orc, g1, "workload1")
+    plain = orc.mbea(g1)
+    assert base["count"] == plain["count"] and base["nodes"] <= plain["nodes"]
+    _prune_check(mbe, orc, _with_twins(gg.random_small(70, 90, 0.12, 8800), 20, 1), "medium twins")
+    _prune_check(mbe, orc, gg.transpose(_with_twins(gg.random_small(50, 60, 0.2, 8801), 12, 2)), "transposed twins")
+    _prune_check(mbe, orc, _wide(0), "wide0")
+    for i in (3, 13, 0):  # batch graphs of the W = 1, 2, 4 classes
+        _prune_check(mbe, orc, gg.config4_graph(i), f"batch graph {i}")
+    # launch shapes and rank ranges
+    for waves, grid in ((4, 1), (2, 5), (8, 0)):
+        r = mbe.mbe_count(g1, mbe.Options(diagnostics=True, prune=True, wg_waves=waves, grid=grid))
+        for k in DIAG_KEYS:
+            assert r[k] == base[k], (waves, grid, k)
+    n = orc.num_roots(g1)
+    for lo, hi in ((0, n // 3), (n // 3, n - 10), (n - 10, n)):
+        want = orc.imbea(g1, rank_lo=lo, rank_hi=hi)
+        got = mbe.mbe_count(g1, mbe.Options(diagnostics=True, prune=True, root_lo=lo, root_hi=hi))
+        for k in DIAG_KEYS:
+            assert got[k] == want[k], (lo, hi, k)
+
+
+def test_prune_records(mbe, orc):
+    g = _with_twins(gg.config1(), 15, 3)
+    _say("prune records")
+    want = orc.imbea(g, want_list=True)
+    res, flat = mbe.mbe_enumerate(g, mbe.Options(prune=True))
+    assert (res["count"], res["hash"]) == (want["count"], want["hash"])
+    assert mbe.decode_records(flat) == want["list"]
+
+
+def test_prune_rejected_where_unsupported(mbe):
+    g = gg.crown(5)
+    for call in (lambda: mbe.mbe_count_batch([g], mbe.Options(prune=True)),
+                 lambda: mbe.mbe_count(g, mbe.Options(prune=True, diagnostics=2)),
+                 lambda: mbe.mbe_count_loads(g, mbe.Options(prune=True))):
+        with pytest.raises(mbe.MbeError) as e:
+            call()
+        assert e.value.code == -1
