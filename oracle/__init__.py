@@ -29,7 +29,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mbe_oracle.c")
-_LIB = os.path.join(_HERE, "liborc_mbe.so")
+# MBE_ORACLE_SANITIZE=1: a copy built with AddressSanitizer and UndefinedBehaviorSanitizer
+# (the process must preload gcc's libasan and libubsan; tests/test_oracle_sanitized.py does)
+_SANITIZE = os.environ.get("MBE_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liborc_mbe_san.so" if _SANITIZE else "liborc_mbe.so")
 _lib = None
 _lock = threading.Lock()
 
@@ -49,8 +52,9 @@ def build(force: bool = True) -> str:
     """Compile the oracle's C source with gcc into a shared library next to it."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-o", tmp, _SRC])
+        flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                 "-fno-sanitize-recover=all"] if _SANITIZE else ["-O2"]
+        subprocess.check_call(["gcc", *flags, "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 

@@ -21,7 +21,8 @@ __all__ = ["mbe_count", "mbe_count_loads", "mbe_count_noalloc", "mbe_count_batch
            "Options", "Server", "lib_path", "load"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libmbe.so")
+# (MBE_LIB: another build of the same library, e.g. the sanitized host build of the CPU tests)
+_LIB_PATH = os.environ.get("MBE_LIB") or os.path.join(_HERE, "libmbe.so")
 _lib = None
 
 MBE_OK = 0
