@@ -6,9 +6,14 @@ CSR validation, candidate ranking and the persistent depth-first search, through
 call mbe_count.  The graph is the Chung-Lu power-law bipartite workload (|U| = 100k,
 |V| = 50k, 1M edges, exponent 2.1 on both sides, seeded).  Prints one JSON line.
 
+The power-law line also carries, as extra keys, the batched form on the 4,096-graph batch
+workload ("batched": graphs/s of one batched call against one call per graph) and the serving
+form on a Poisson request stream ("served": p50/p99 latency and graphs/s), unless --no-batch /
+--no-serve.  --workload batch and --workload serve print those forms as lines of their own.
+
   python bench.py [--steps K] [--warmup W] [--gpus 1]
-                  [--workload power-law|er-small|skewed-sample|batch|serve] [--batch-n N]
-                  [--serve-n N --rate R --slots S]
+                  [--workload power-law|er-small|skewed-sample|batch|serve|call-overhead] [--batch-n N]
+                  [--serve-n N --rate R --slots S] [--no-batch] [--no-serve]
 """
 import argparse
 import json
@@ -179,96 +184,103 @@ def steal_ablation(mbe, dg, rng, steps=3):
     return out
 
 
-def bench_batch(args, mbe):
-    """Batched form: n independent graphs (|U|, |V| log-uniform in [50, 2000], density uniform
-    in [0.01, 0.1], ER or Chung-Lu) in one mbe_count_batch call, against one mbe_count call
-    per graph.  The launch setting is picked first by the autotuner (mbe_tune_batch) on every
-    eighth graph and then used by both forms.  Both take host graphs, so both include the
-    upload and the preparation."""
+def generate(fn, items, workers=BOX_THREADS):
+    """[fn(x) for x in items], on a pool of forked worker processes when more than one host
+    thread is available (the graphs are seeded per item, so the result is the same).  Called
+    before this process touches the GPU."""
+    items = list(items)
+    workers = min(workers, os.cpu_count() or 1, len(items))
+    if workers <= 1:
+        return [fn(x) for x in items]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(fn, items, chunksize=max(1, len(items) // (8 * workers)))
+
+
+def batch_inputs(n):
     import graphgen as gg
     t0 = time.time()
-    gs = [gg.config4_graph(i) for i in range(args.batch_n)]
-    log(f"generated {len(gs)} graphs, {sum(g.n_edges for g in gs)} edges, in {time.time() - t0:.1f} s")
-    base = mbe.Options(wg_waves=args.waves, grid=args.grid)
+    gs = generate(gg.config4_graph, range(n))
+    log(f"generated {len(gs)} batch graphs, {sum(g.n_edges for g in gs)} edges, in {time.time() - t0:.1f} s")
+    return gs
+
+
+def serve_inputs(n, rate, big_max_u):
+    import graphgen as gg
+    t0 = time.time()
+    arr = gg.config5_arrivals(n, rate, big_max_u=big_max_u)
+    reqs = list(zip([t for t, _ in arr], generate(gg.config5_build, [sp for _, sp in arr])))
+    log(f"generated {len(reqs)} requests ({sum(1 for _, g in reqs if g.n_u >= 20000)} large), "
+        f"{sum(g.n_edges for _, g in reqs)} edges, in {time.time() - t0:.1f} s")
+    return reqs
+
+
+def batch_form(mbe, gs, tune_every, batch_calls=1, plain_defaults=False, waves=0, grid=0):
+    """Batched form against the plain form on the graphs gs.  The launch setting is picked by
+    the autotuner (mbe_tune_batch) on every tune_every-th graph and then used by both forms;
+    with plain_defaults the plain form also runs under the library's defaults and the faster
+    of the two is its time.  Both forms take host graphs, so both include the upload and the
+    preparation.  Per-graph count and hash must agree between the forms."""
+    base = mbe.Options(wg_waves=waves, grid=grid)
     t0 = time.perf_counter()
-    opt, tuned_ms = mbe.mbe_tune_batch(gs[::8], base)
+    sample = gs[::tune_every]
+    opt, tuned_ms = mbe.mbe_tune_batch(sample, base)
     t_tune = time.perf_counter() - t0
-    log(f"tuned on {len(gs[::8])} graphs in {t_tune:.1f} s: wg_waves={opt.wg_waves} steal_k={opt.steal_k} "
+    log(f"tuned on {len(sample)} graphs in {t_tune:.1f} s: wg_waves={opt.wg_waves} steal_k={opt.steal_k} "
         f"({tuned_ms:.0f} ms per sample batch)")
     mbe.mbe_count_batch(gs[:64], opt)
     for g in gs[:8]:
         mbe.mbe_count(g, opt)
-    # the plain form, one call per graph, under the tuned setting and under the defaults;
-    # the faster of the two is the baseline
     t0 = time.perf_counter()
     plain = [mbe.mbe_count(g, opt) for g in gs]
     t_plain_tuned = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    plain_def = [mbe.mbe_count(g, base) for g in gs]
-    t_plain_def = time.perf_counter() - t0
-    t_plain = min(t_plain_tuned, t_plain_def)
-    if t_plain_def < t_plain_tuned:
-        plain = plain_def
-    log(f"plain: {t_plain_tuned:.3f} s tuned setting, {t_plain_def:.3f} s defaults")
-    times = []
-    for _ in range(max(1, args.steps)):
+    t_plain, t_plain_def = t_plain_tuned, None
+    if plain_defaults:
+        t0 = time.perf_counter()
+        plain_def = [mbe.mbe_count(g, base) for g in gs]
+        t_plain_def = time.perf_counter() - t0
+        if t_plain_def < t_plain:
+            t_plain, plain = t_plain_def, plain_def
+    log(f"plain: {t_plain_tuned:.3f} s tuned setting" +
+        (f", {t_plain_def:.3f} s defaults" if t_plain_def is not None else ""))
+    times, attempts = [], []
+    for _ in range(max(1, batch_calls)):
         t0 = time.perf_counter()
         res = mbe.mbe_count_batch(gs, opt)
         times.append(time.perf_counter() - t0)
+        attempts.append(max(r["attempts"] for r in res) if res else 1)
     t_batch = min(times)
+    log(f"batched: {', '.join(f'{t:.3f}' for t in times)} s")
     for i, (a, b) in enumerate(zip(plain, res)):
         assert (a["count"], a["hash"]) == (b["count"], b["hash"]), i
     total = sum(r["count"] for r in res)
     # share of the plain time spent on the graphs that need >= 10% of a second alone
-    heavy = sorted(((r["kernel_ms"], r["count"]) for r in plain), reverse=True)
-    heavy_ms = sum(k for k, _ in heavy if k >= 100.0)
-    out = {
-        "metric": "graphs/s batched vs plain",
-        "value": len(gs) / t_batch,
-        "unit": "graphs/s",
-        "n_gpus": 1,
-        "steps": len(times),
-        "warmup": 1,
-        "ms_per_step": t_batch * 1000.0,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": f"batch of {len(gs)} ER / Chung-Lu bipartite graphs, sides log-uniform [50, 2000], "
-                               f"density U[0.01, 0.1]", "graphs": len(gs), "edges": sum(g.n_edges for g in gs),
-                   "bicliques": total, "tuned": {"wg_waves": opt.wg_waves, "steal_k": opt.steal_k,
-                                                 "tune_s": t_tune, "sample_graphs": len(gs[::8])}},
-        "plain_graphs_per_s": len(gs) / t_plain,
-        "plain_s_tuned_setting": t_plain_tuned,
-        "plain_s_defaults": t_plain_def,
+    heavy = sorted((r["kernel_ms"] for r in plain), reverse=True)
+    return {
+        "graphs": len(gs), "edges": sum(g.n_edges for g in gs), "bicliques": total,
+        "batched_s": t_batch, "batched_calls": len(times), "batched_attempts": attempts,
+        "plain_s": t_plain, "plain_s_tuned_setting": t_plain_tuned, "plain_s_defaults": t_plain_def,
+        "batched_graphs_per_s": len(gs) / t_batch, "plain_graphs_per_s": len(gs) / t_plain,
         "batched_over_plain": t_plain / t_batch,
-        "batch_kernel_ms": res[0]["kernel_ms"] if res else 0.0,
-        "plain_kernel_ms_heaviest_graphs": heavy_ms,
-        "plain_heaviest_graphs": sum(1 for k, _ in heavy if k >= 100.0),
         "bicliques_per_s_batched": total / t_batch,
+        "plain_kernel_ms_heaviest_graphs": sum(k for k in heavy if k >= 100.0),
+        "plain_heaviest_graphs": sum(1 for k in heavy if k >= 100.0),
+        "tuned": {"wg_waves": opt.wg_waves, "steal_k": opt.steal_k, "tune_s": t_tune, "sample_graphs": len(sample)},
     }
-    print(json.dumps(out), flush=True)
 
 
-def bench_serve(args, mbe):
-    """Serving form: requests arrive as a Poisson stream at --rate per second; 90% are
-    batched-workload graphs, 10% Chung-Lu graphs with |U| log-uniform in [20k, --big-max-u],
-    |V| = |U|/2, E = min(5M, 25 |U|).  A continuous-batching server admits them by device
-    footprint (one slot reserved for small requests); latency is submission to completion.
-    Then the same requests are submitted all at once (the server's capacity) and run one
-    mbe_count call at a time (the plain form)."""
+def serve_form(mbe, reqs, slots, saturated=True):
+    """Serving form: the requests are submitted at their Poisson arrival times to a
+    continuous-batching server (admission by device footprint, one slot reserved for small
+    requests); latency is submission to completion.  Then the same requests are submitted all
+    at once (the server's capacity) and run one mbe_count call at a time (the plain form),
+    and every result must be the same in the mix, saturated and alone."""
     import threading
     import numpy as np
-    import graphgen as gg
-    t0 = time.time()
-    reqs = gg.config5_requests(args.serve_n, args.rate, big_max_u=args.big_max_u)
-    n_big = sum(1 for _, g in reqs if g.n_u >= 20000)
-    log(f"generated {len(reqs)} requests ({n_big} large), {sum(g.n_edges for _, g in reqs)} edges, "
-        f"in {time.time() - t0:.1f} s")
     lat = [0.0] * len(reqs)
     res = [None] * len(reqs)
-    with mbe.Server(slots=args.slots) as sv:
+    sat = None
+    with mbe.Server(slots=slots) as sv:
         for tk in [sv.submit(g) for _, g in reqs[:8]]:  # warm the slots' workspaces
             sv.wait(tk)
         tickets = [None] * len(reqs)
@@ -288,29 +300,123 @@ def bench_serve(args, mbe):
             res[i], lat[i] = sv.wait(tickets[i])
         span = time.perf_counter() - start
         log(f"poisson run: {span:.1f} s")
-        # capacity: everything queued at once
-        t0 = time.perf_counter()
-        tks = [sv.submit(g) for _, g in reqs]
-        sat = [sv.wait(tk)[0] for tk in tks]
-        t_sat = time.perf_counter() - t0
-        log(f"saturated run: {t_sat:.1f} s")
+        if saturated:
+            t0 = time.perf_counter()
+            tks = [sv.submit(g) for _, g in reqs]
+            sat = [sv.wait(tk)[0] for tk in tks]
+            t_sat = time.perf_counter() - t0
+            log(f"saturated run: {t_sat:.1f} s")
     t0 = time.perf_counter()
     plain = [mbe.mbe_count(g) for _, g in reqs]
     t_plain = time.perf_counter() - t0
     log(f"plain run: {t_plain:.1f} s")
     for i in range(len(reqs)):
         assert (res[i]["count"], res[i]["hash"]) == (plain[i]["count"], plain[i]["hash"]), i
-        assert (sat[i]["count"], sat[i]["hash"]) == (plain[i]["count"], plain[i]["hash"]), i
+        if sat is not None:
+            assert (sat[i]["count"], sat[i]["hash"]) == (plain[i]["count"], plain[i]["hash"]), i
     lat_a = np.array(lat)
     small = np.array([g.n_u < 20000 for _, g in reqs])
+    n_big = int((~small).sum())
+    return {
+        "requests": len(reqs), "large_requests": n_big, "slots": slots,
+        "edges": sum(g.n_edges for _, g in reqs), "bicliques": sum(r["count"] for r in res),
+        "span_s": span, "graphs_per_s": len(reqs) / span,
+        "p50_ms": float(np.percentile(lat_a, 50)),
+        "p99_ms": float(np.percentile(lat_a, 99)),
+        "p50_ms_small": float(np.percentile(lat_a[small], 50)),
+        "p99_ms_small": float(np.percentile(lat_a[small], 99)),
+        "p50_ms_large": float(np.percentile(lat_a[~small], 50)) if n_big else None,
+        "saturated_graphs_per_s": len(reqs) / t_sat if sat is not None else None,
+        "plain_graphs_per_s": len(reqs) / t_plain,
+        "served_over_plain": t_plain / t_sat if sat is not None else None,
+    }
+
+
+def call_overhead(mbe, dev, calls):
+    """Wall time of one mbe_count call on tiny graphs, from device-resident CSR arrays and from
+    host arrays, against the search time the call reports: what a call costs beyond its
+    search (launches, copies, the waits on the preparation's statistics).  K_{4,4} has one
+    maximal biclique and a four-node tree (the call's fixed cost); crown(9) has 510 and a
+    tree nine levels deep (a small request's dependent steps)."""
+    import numpy as np
+    import torch
+    import graphgen as gg
+    out = {"calls": calls}
+    for name, g in (("k44", gg.complete(4, 4)), ("crown9", gg.crown(9))):
+        dg = gg.BiGraph(g.n_u, g.n_v, *[torch.from_numpy(np.asarray(a)).to(dev) for a in
+                                        (g.u_off, g.u_adj, g.v_off, g.v_adj)])
+        for key, gr in (("device_csr", dg), ("host_csr", g)):
+            for _ in range(10):
+                mbe.mbe_count(gr)
+            torch.cuda.synchronize()
+            ks = []
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                ks.append(mbe.mbe_count(gr)["kernel_ms"])
+            dt = time.perf_counter() - t0
+            out[f"{name}_{key}_ms_per_call"] = dt * 1000.0 / calls
+            out[f"{name}_{key}_search_ms"] = sum(ks) / len(ks)
+    return out
+
+
+def bench_call_overhead(args, mbe, dev):
+    r = call_overhead(mbe, dev, max(1, args.steps))
+    out = {
+        "metric": "wall ms per mbe_count call on a tiny graph",
+        "value": r["k44_device_csr_ms_per_call"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": r["calls"],
+        "warmup": 10,
+        "ms_per_step": r["k44_device_csr_ms_per_call"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "K_{4,4} (one maximal biclique) and crown(9) (9 x 9 vertices, 72 edges, 510 "
+                               "maximal bicliques)"},
+        **r,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, mbe, gs):
+    r = batch_form(mbe, gs, tune_every=8, batch_calls=args.steps, plain_defaults=True,
+                   waves=args.waves, grid=args.grid)
+    out = {
+        "metric": "graphs/s batched vs plain",
+        "value": r["batched_graphs_per_s"],
+        "unit": "graphs/s",
+        "n_gpus": 1,
+        "steps": r["batched_calls"],
+        "warmup": 1,
+        "ms_per_step": r["batched_s"] * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {len(gs)} ER / Chung-Lu bipartite graphs, sides log-uniform [50, 2000], "
+                               f"density U[0.01, 0.1]", "graphs": len(gs), "edges": r["edges"],
+                   "bicliques": r["bicliques"], "tuned": r["tuned"]},
+        **{k: r[k] for k in ("plain_graphs_per_s", "plain_s_tuned_setting", "plain_s_defaults",
+                             "batched_over_plain", "plain_kernel_ms_heaviest_graphs", "plain_heaviest_graphs",
+                             "bicliques_per_s_batched", "batched_attempts")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, mbe, reqs):
+    r = serve_form(mbe, reqs, args.slots)
     out = {
         "metric": "served graphs/s; p50/p99 solve latency",
-        "value": len(reqs) / span,
+        "value": r["graphs_per_s"],
         "unit": "graphs/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 1,
-        "ms_per_step": span * 1000.0,
+        "ms_per_step": r["span_s"] * 1000.0,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -318,17 +424,10 @@ def bench_serve(args, mbe):
         "data": "synthetic",
         "config": {"workload": f"Poisson stream of {len(reqs)} requests at {args.rate}/s, 90% batch-style graphs, "
                                f"10% Chung-Lu |U| up to {args.big_max_u}", "slots": args.slots,
-                   "large_requests": n_big, "edges": sum(g.n_edges for _, g in reqs),
-                   "bicliques": sum(r["count"] for r in res)},
-        "p50_ms": float(np.percentile(lat_a, 50)),
-        "p99_ms": float(np.percentile(lat_a, 99)),
-        "p50_ms_small": float(np.percentile(lat_a[small], 50)),
-        "p99_ms_small": float(np.percentile(lat_a[small], 99)),
-        "p50_ms_large": float(np.percentile(lat_a[~small], 50)) if n_big else None,
+                   "large_requests": r["large_requests"], "edges": r["edges"], "bicliques": r["bicliques"]},
+        **{k: r[k] for k in ("p50_ms", "p99_ms", "p50_ms_small", "p99_ms_small", "p50_ms_large",
+                             "saturated_graphs_per_s", "plain_graphs_per_s", "served_over_plain")},
         "offered_rate": args.rate,
-        "saturated_graphs_per_s": len(reqs) / t_sat,
-        "plain_graphs_per_s": len(reqs) / t_plain,
-        "served_over_plain": t_plain / t_sat,
     }
     print(json.dumps(out), flush=True)
 
@@ -355,6 +454,12 @@ def main():
     ap.add_argument("--traffic-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-load-study", action="store_true",
                     help="skip the per-workgroup load study (k = 1, 2, 3) on the skewed sample")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="power-law line: skip the batched-form figures (--batch-n graphs)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="power-law line: skip the serving-form figures (--line-serve-n requests at --line-rate)")
+    ap.add_argument("--line-serve-n", type=int, default=100)
+    ap.add_argument("--line-rate", type=float, default=4.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the search runs on one GPU (sharding across GPUs is a design only); --gpus must be 1",
@@ -366,6 +471,15 @@ def main():
     if args.workload in ("power-law", "skewed-sample", "er-small") and not args.no_traffic:
         # (before this process initialises the GPU: the profiled children are started from here)
         traffic = measure_traffic(args)
+    # the batched and served inputs are generated here too, on forked workers, before the GPU
+    # is touched
+    gs = reqs = None
+    if args.workload == "batch" or (args.workload == "power-law" and not args.no_batch):
+        gs = batch_inputs(args.batch_n)
+    if args.workload == "serve":
+        reqs = serve_inputs(args.serve_n, args.rate, args.big_max_u)
+    elif args.workload == "power-law" and not args.no_serve:
+        reqs = serve_inputs(args.line_serve_n, args.line_rate, args.big_max_u)
 
     import numpy as np
     import torch
@@ -375,9 +489,11 @@ def main():
         raise SystemExit("no HIP device")
     mbe.load()
     if args.workload == "batch":
-        return bench_batch(args, mbe)
+        return bench_batch(args, mbe, gs)
     if args.workload == "serve":
-        return bench_serve(args, mbe)
+        return bench_serve(args, mbe, reqs)
+    if args.workload == "call-overhead":
+        return bench_call_overhead(args, mbe, torch.device("cuda:0"))
     g, desc, rng_range = make_workload(args.workload)
     log("graph", desc)
     dev = torch.device("cuda:0")
@@ -475,6 +591,22 @@ def main():
         # the same oracle on one core, on a smaller sample (about half the parallel leg's work)
         log("cpu baseline on 1 thread")
         out["cpu_baseline_serial"] = cpu_baseline(g, rng_range, 1, frac=0.1, chunks=32)
+    if gs is not None:
+        # the batched form on the batch workload's own graphs: tuner on every 32nd graph, one
+        # batched call against one mbe_count call per graph (the faster of the tuned setting
+        # and the defaults)
+        del dg
+        torch.cuda.empty_cache()
+        log("batched form")
+        out["batched"] = dict(workload=f"{len(gs)} ER / Chung-Lu bipartite graphs, sides log-uniform [50, 2000], "
+                                       "density U[0.01, 0.1]", **batch_form(mbe, gs, tune_every=32, plain_defaults=True))
+        del gs
+    out["call_overhead"] = call_overhead(mbe, dev, 200)
+    if reqs is not None:
+        log("serving form")
+        out["served"] = dict(workload=f"Poisson stream of {len(reqs)} requests at {args.line_rate}/s, 90% batch-style "
+                                      f"graphs, 10% Chung-Lu |U| in [20k, {args.big_max_u}]",
+                             offered_rate=args.line_rate, **serve_form(mbe, reqs, args.slots))
     print(json.dumps(out), flush=True)
 
 

@@ -24,6 +24,7 @@ __all__ = [
     "BiGraph", "stream_u64", "stream_uniform", "from_edges", "erdos_renyi_pairs",
     "erdos_renyi_m", "chung_lu", "planted_bicliques", "union",
     "config1", "config2", "config3", "config4_graph", "config4_batch", "config5_requests",
+    "config5_arrivals", "config5_build",
     "complete", "perfect_matching", "crown", "chain", "complete_minus_edge", "edgeless",
     "disjoint_union", "transpose", "relabel", "random_small",
 ]
@@ -316,13 +317,12 @@ def config4_batch(n: int = 4096, base_seed: int = _BASE_SEED) -> List[BiGraph]:
     return [config4_graph(i, base_seed) for i in range(n)]
 
 
-def config5_requests(n: int, rate: float, seed: int = _BASE_SEED + 5,
+def config5_arrivals(n: int, rate: float, seed: int = _BASE_SEED + 5,
                      big_frac: float = 0.1, big_max_u: int = 200_000,
-                     big_min_u: int = 20_000) -> List[Tuple[float, BiGraph]]:
-    """Serving workload: Poisson arrivals at `rate` requests/s; each request is a batched-
-    workload graph with probability 1 - big_frac, else a Chung-Lu graph (exponent 2.1)
-    with |U| log-uniform in [big_min_u, big_max_u], |V| = |U|/2, E = min(5e6, 25 |U|).
-    Returns (arrival time in seconds, graph) pairs in arrival order."""
+                     big_min_u: int = 20_000) -> List[Tuple[float, tuple]]:
+    """Arrival times and graph specifications of the serving workload (see config5_requests);
+    config5_build turns a specification into its graph, so that the graphs can be generated
+    in parallel."""
     r = stream_uniform(seed, 10, 3 * n)
     t = 0.0
     out = []
@@ -331,13 +331,30 @@ def config5_requests(n: int, rate: float, seed: int = _BASE_SEED + 5,
         if r[3 * k + 1] < big_frac:
             lu = math.log(big_min_u) + r[3 * k + 2] * (math.log(big_max_u) - math.log(big_min_u))
             n_u = int(round(math.exp(lu)))
-            n_v = n_u // 2
-            m = min(5_000_000, 25 * n_u)
-            g = chung_lu(n_u, n_v, m, 2.1, 2.1, seed * 1000 + k, name=f"req{k}-cl-{n_u}x{n_v}")
+            out.append((t, ("big", k, n_u, seed)))
         else:
-            g = config4_graph(k, base_seed=seed)
-        out.append((t, g))
+            out.append((t, ("small", k, 0, seed)))
     return out
+
+
+def config5_build(spec: tuple) -> BiGraph:
+    kind, k, n_u, seed = spec
+    if kind == "big":
+        n_v = n_u // 2
+        m = min(5_000_000, 25 * n_u)
+        return chung_lu(n_u, n_v, m, 2.1, 2.1, seed * 1000 + k, name=f"req{k}-cl-{n_u}x{n_v}")
+    return config4_graph(k, base_seed=seed)
+
+
+def config5_requests(n: int, rate: float, seed: int = _BASE_SEED + 5,
+                     big_frac: float = 0.1, big_max_u: int = 200_000,
+                     big_min_u: int = 20_000) -> List[Tuple[float, BiGraph]]:
+    """Serving workload: Poisson arrivals at `rate` requests/s; each request is a batched-
+    workload graph with probability 1 - big_frac, else a Chung-Lu graph (exponent 2.1)
+    with |U| log-uniform in [big_min_u, big_max_u], |V| = |U|/2, E = min(5e6, 25 |U|).
+    Returns (arrival time in seconds, graph) pairs in arrival order."""
+    return [(t, config5_build(spec)) for t, spec in
+            config5_arrivals(n, rate, seed, big_frac, big_max_u, big_min_u)]
 
 
 def wide_hubs(n_u: int, n_v: int, hub_degrees: Sequence[int], p: float, seed: int, name: str = "") -> BiGraph:

@@ -38,6 +38,8 @@ extern "C" {
 #define MBE_ERR_DEVICE           -5  /* a HIP runtime call failed */
 #define MBE_ERR_UNSUPPORTED      -6  /* (kept for binary compatibility; no longer returned) */
 #define MBE_ERR_SCRATCH_LIMIT    -7  /* mbe_count_noalloc: the call does not fit the fixed scratch */
+#define MBE_ERR_TIMEOUT          -8  /* server: the request passed its deadline (result unspecified) */
+#define MBE_ERR_CANCELLED        -9  /* server: the request was cancelled (result unspecified) */
 
 /* Widest fixed mask class: top-level candidates of degree up to this many are searched with
  * neighbour sets held in registers as bit masks of 64 * 2^c bits (c = 0..4); candidates of any
@@ -285,6 +287,17 @@ int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_
  *                     edges, so that small requests do not queue behind large ones
  *                     (default 65536; negative: no reserved slot)
  *   search            per-search options (side, wg_waves, grid, diagnostics, no_validate)
+ *   request_timeout_ms  deadline of every request submitted with mbe_server_submit, counted
+ *                     from its submission (0: none); see mbe_server_submit_timeout
+ *
+ * Deadlines and cancellation: a request that passes its deadline, or is cancelled, before a
+ * slot took it leaves the queue at once.  One that is already on the device stops being
+ * worked on: its top-level candidates that no workgroup has claimed are skipped (each graph
+ * of a batch has a word in pinned host memory that the search reads before it claims a
+ * candidate of that graph), while those in flight run to their end, so the batch it shares
+ * finishes early by what the skipped candidates would have cost.  Either way its wait
+ * returns MBE_ERR_TIMEOUT or MBE_ERR_CANCELLED with an unspecified result; the other
+ * requests of the batch are not affected.
  */
 typedef struct mbe_server mbe_server;
 typedef struct mbe_server_options {
@@ -293,13 +306,24 @@ typedef struct mbe_server_options {
     int32_t max_batch;
     int64_t small_edges;
     mbe_options search;
+    double request_timeout_ms;
 } mbe_server_options;
 
 /* Start a server on the current device (opt may be NULL).  *out receives the handle. */
 int mbe_server_create(const mbe_server_options *opt, mbe_server **out);
 
-/* Queue a host graph (copied before the call returns); *ticket identifies the request. */
+/* Queue a host graph (copied before the call returns); *ticket identifies the request.  Its
+ * deadline is the server's request_timeout_ms. */
 int mbe_server_submit(mbe_server *s, const mbe_graph *g, uint64_t *ticket);
+
+/* mbe_server_submit with a deadline of timeout_ms after submission for this request
+ * (0: none; negative or NaN: MBE_ERR_INVALID_ARG). */
+int mbe_server_submit_timeout(mbe_server *s, const mbe_graph *g, double timeout_ms, uint64_t *ticket);
+
+/* Cancel a request that has not been waited for: its wait returns MBE_ERR_CANCELLED unless
+ * it was already done (then the cancellation has no effect).  MBE_ERR_INVALID_ARG for an
+ * unknown ticket. */
+int mbe_server_cancel(mbe_server *s, uint64_t ticket);
 
 /* Block until the request is done; out receives its result and latency_ms (may be NULL)
  * the time from submission to completion.  Returns the request's status.  A ticket can be

@@ -33,6 +33,8 @@ MBE_ERR_OUT_OF_MEMORY = -4
 MBE_ERR_DEVICE = -5
 MBE_ERR_UNSUPPORTED = -6
 MBE_ERR_SCRATCH_LIMIT = -7
+MBE_ERR_TIMEOUT = -8
+MBE_ERR_CANCELLED = -9
 MBE_NOALLOC_SCRATCH_BYTES = 256 << 20
 MBE_MAX_DEGREE = 1024
 
@@ -78,7 +80,7 @@ class Options:
 
 class _ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("small_edges", ctypes.c_int64), ("search", _Options)]
+                ("small_edges", ctypes.c_int64), ("search", _Options), ("request_timeout_ms", ctypes.c_double)]
 
 
 class MbeError(RuntimeError):
@@ -122,6 +124,11 @@ def load():
     lib.mbe_server_create.restype = ctypes.c_int
     lib.mbe_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Graph), ctypes.POINTER(ctypes.c_uint64)]
     lib.mbe_server_submit.restype = ctypes.c_int
+    lib.mbe_server_submit_timeout.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Graph), ctypes.c_double,
+                                              ctypes.POINTER(ctypes.c_uint64)]
+    lib.mbe_server_submit_timeout.restype = ctypes.c_int
+    lib.mbe_server_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    lib.mbe_server_cancel.restype = ctypes.c_int
     lib.mbe_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(_Result),
                                     ctypes.POINTER(ctypes.c_double)]
     lib.mbe_server_wait.restype = ctypes.c_int
@@ -294,22 +301,33 @@ class Server:
     thread, wait for each result; results equal those of ``mbe_count`` on the graph alone."""
 
     def __init__(self, hbm_budget_bytes: int = 0, slots: int = 2, max_batch: int = 0,
-                 opt: Optional[Options] = None, small_edges: int = 0):
+                 opt: Optional[Options] = None, small_edges: int = 0, request_timeout_ms: float = 0.0):
         lib = load()
-        so = _ServerOptions(hbm_budget_bytes, slots, max_batch, small_edges, _marshal_opts(opt, False))
+        so = _ServerOptions(hbm_budget_bytes, slots, max_batch, small_edges, _marshal_opts(opt, False),
+                            request_timeout_ms)
         h = ctypes.c_void_p()
         rc = lib.mbe_server_create(ctypes.byref(so), ctypes.byref(h))
         if rc != MBE_OK:
             raise MbeError(rc)
         self._h = h
 
-    def submit(self, g) -> int:
+    def submit(self, g, timeout_ms: Optional[float] = None) -> int:
+        """Queue g; timeout_ms (None: the server's request_timeout_ms) is its deadline."""
         cg, keep = _marshal_graph(g)
         t = ctypes.c_uint64()
-        rc = load().mbe_server_submit(self._h, ctypes.byref(cg), ctypes.byref(t))
+        if timeout_ms is None:
+            rc = load().mbe_server_submit(self._h, ctypes.byref(cg), ctypes.byref(t))
+        else:
+            rc = load().mbe_server_submit_timeout(self._h, ctypes.byref(cg), ctypes.c_double(timeout_ms),
+                                                  ctypes.byref(t))
         if rc != MBE_OK:
             raise MbeError(rc)
         return int(t.value)
+
+    def cancel(self, ticket: int) -> None:
+        rc = load().mbe_server_cancel(self._h, ctypes.c_uint64(ticket))
+        if rc != MBE_OK:
+            raise MbeError(rc)
 
     def wait(self, ticket: int) -> Tuple[Dict[str, Any], float]:
         """(result dict, latency in ms from submission to completion)."""

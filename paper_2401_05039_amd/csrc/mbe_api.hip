@@ -815,7 +815,7 @@ int batch_totals(const mbe_graph *gs, int32_t n, int side_opt, int64_t *nc_tot, 
 // The batched pass on a given workspace and stream (the caller holds the workspace and has
 // run check_graphs).
 int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n, const mbe_options *opt_in,
-                 mbe_result *outs);
+                 mbe_result *outs, const unsigned int *cancel = nullptr);
 
 int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_result *outs) {
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
@@ -843,7 +843,7 @@ int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_res
 }
 
 int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n, const mbe_options *opt_in,
-                 mbe_result *outs) {
+                 mbe_result *outs, const unsigned int *cancel) {
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
     Opts opt = read_opts(opt_in);
     if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
@@ -1016,6 +1016,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
     a.tasks = task_sorted;
     a.acc = acc;
     a.flags = flags;
+    a.cancel = cancel;
     unsigned long long hacc[ACC_SLOTS];
     unsigned int hflags = 0;
     float ms = 0.f;
@@ -1064,10 +1065,15 @@ struct ServerRequest {
     std::vector<int32_t> u_off, u_adj, v_off, v_adj;
     mbe_graph g{};
     size_t csr_bytes = 0, arena_bytes = 0;
-    Clock::time_point arrival, finish;
+    Clock::time_point arrival, finish, deadline;
+    bool has_deadline = false;
     mbe_result result{};
     int rc = 0;
     bool done = false;
+    // on the device: the slot and position in its batch (their cancel word); stop: the
+    // return code (timeout or cancelled) it ends with, 0 while it is wanted
+    int slot = -1, pos = -1;
+    int stop = 0;
 };
 
 void free_state(DeviceState *st) {
@@ -1107,10 +1113,55 @@ struct mbe_server {
     int device = 0;
     int cus = 256;
     mbe_options search{};
+    double timeout_ms = 0.0;  // default deadline of a request (0: none)
     std::vector<std::thread> workers;
+    std::thread watchdog;
+    std::condition_variable cv_deadline;
     std::vector<DeviceState *> states;
     std::vector<hipStream_t> streams;
+    std::vector<unsigned int *> cancel;      // per slot, max_batch words of pinned host memory
+    std::vector<unsigned int *> cancel_dev;  // the same words' device addresses
     uint64_t batches = 0, served = 0;
+
+    // End a request that will not be run or whose run no longer counts (mu held): one still
+    // queued leaves the queue and is done at once; one on the device has its cancel word set
+    // and ends when its batch does.
+    void stop_request(const std::shared_ptr<ServerRequest> &r, int why) {
+        if (r->done || r->stop) return;
+        r->stop = why;
+        if (r->slot < 0) {
+            for (auto it = pending.begin(); it != pending.end(); ++it)
+                if (it->get() == r.get()) {
+                    pending.erase(it);
+                    break;
+                }
+            r->rc = why;
+            r->finish = Clock::now();
+            r->done = true;
+            std::vector<int32_t>().swap(r->u_adj);
+            std::vector<int32_t>().swap(r->v_adj);
+            cv_done.notify_all();
+        } else {
+            __atomic_store_n(&cancel[r->slot][r->pos], 1u, __ATOMIC_RELEASE);
+        }
+    }
+
+    // Ends the requests that passed their deadline, sleeping until the next one.
+    void watch() {
+        std::unique_lock<std::mutex> lk(mu);
+        while (!stopping) {
+            const Clock::time_point now = Clock::now();
+            Clock::time_point next = Clock::time_point::max();
+            for (auto &kv : live) {
+                const std::shared_ptr<ServerRequest> &r = kv.second;
+                if (!r->has_deadline || r->done || r->stop) continue;
+                if (r->deadline <= now) stop_request(r, MBE_ERR_TIMEOUT);
+                else next = std::min(next, r->deadline);
+            }
+            if (next == Clock::time_point::max()) cv_deadline.wait(lk);
+            else cv_deadline.wait_until(lk, next);
+        }
+    }
 
     // device bytes a request adds: its CSR and preparation arrays, and the search arena its
     // largest local universe needs (the arena is shared by a batch, so only its maximum counts)
@@ -1165,6 +1216,11 @@ struct mbe_server {
                     edges = edges2;
                     csr += r.csr_bytes;
                     arena = std::max(arena, r.arena_bytes);
+                    // its cancel word is cleared before it is marked as on the device (the
+                    // previous batch of this slot has finished reading the words)
+                    (*it)->slot = slot;
+                    (*it)->pos = (int)batch.size();
+                    cancel[slot][batch.size()] = 0u;
                     batch.push_back(*it);
                     it = pending.erase(it);
                 }
@@ -1175,13 +1231,15 @@ struct mbe_server {
             mbe_options o = search;
             o.stream = streams[slot];
             o.no_validate = 1;  // checked at submission
-            const int rc = run_batch_on(states[slot], streams[slot], gs.data(), (int32_t)gs.size(), &o, rs.data());
+            const int rc = run_batch_on(states[slot], streams[slot], gs.data(), (int32_t)gs.size(), &o, rs.data(),
+                                        cancel_dev[slot]);
             const Clock::time_point now = Clock::now();
             {
                 std::lock_guard<std::mutex> lk(mu);
                 for (size_t i = 0; i < batch.size(); ++i) {
                     batch[i]->result = rs[i];
-                    batch[i]->rc = rc != MBE_OK ? rc : rs[i].status;
+                    batch[i]->rc = batch[i]->stop ? batch[i]->stop : rc != MBE_OK ? rc : rs[i].status;
+                    if (batch[i]->stop) batch[i]->result.status = batch[i]->stop;
                     batch[i]->finish = now;
                     batch[i]->done = true;
                     // the graph copy is no longer needed
@@ -1208,6 +1266,8 @@ int server_create(const mbe_server_options *opt, mbe_server **out) {
         sv->search = opt->search;
         if (opt->max_batch > 0) sv->max_batch = opt->max_batch;
         if (opt->small_edges != 0) sv->small_edges = opt->small_edges;
+        if (!(opt->request_timeout_ms >= 0.0)) return MBE_ERR_INVALID_ARG;  // (NaN too)
+        sv->timeout_ms = opt->request_timeout_ms;
     }
     sv->search.root_lo = sv->search.root_hi = 0;
     if (sv->search.wg_waves < 0 || sv->search.wg_waves > 8 || sv->search.side < 0 || sv->search.side > 2 ||
@@ -1235,9 +1295,20 @@ int server_create(const mbe_server_options *opt, mbe_server **out) {
         hipStream_t strm = nullptr;
         MBE_TRY(hipStreamCreateWithFlags(&strm, hipStreamNonBlocking));
         sv->streams.push_back(strm);
+        // cancel words: fine-grained pinned host memory, which a running kernel reads
+        void *cw = nullptr;
+        if (hipHostMalloc(&cw, (size_t)sv->max_batch * sizeof(unsigned int), hipHostMallocCoherent | hipHostMallocMapped) !=
+            hipSuccess)
+            return MBE_ERR_OUT_OF_MEMORY;
+        std::memset(cw, 0, (size_t)sv->max_batch * sizeof(unsigned int));
+        sv->cancel.push_back(static_cast<unsigned int *>(cw));
+        void *cwd = nullptr;
+        MBE_TRY(hipHostGetDevicePointer(&cwd, cw, 0));
+        sv->cancel_dev.push_back(static_cast<unsigned int *>(cwd));
     }
     mbe_server *raw = sv.get();
     for (int k = 0; k < slots; ++k) sv->workers.emplace_back([raw, k] { raw->worker(k); });
+    sv->watchdog = std::thread([raw] { raw->watch(); });
     *out = sv.release();
     return MBE_OK;
 }
@@ -1249,7 +1320,12 @@ extern "C" {
 int mbe_server_create(const mbe_server_options *opt, mbe_server **out) { return server_create(opt, out); }
 
 int mbe_server_submit(mbe_server *sv, const mbe_graph *g, uint64_t *ticket) {
-    if (!sv || !g || !ticket) return MBE_ERR_INVALID_ARG;
+    if (!sv) return MBE_ERR_INVALID_ARG;
+    return mbe_server_submit_timeout(sv, g, sv->timeout_ms, ticket);
+}
+
+int mbe_server_submit_timeout(mbe_server *sv, const mbe_graph *g, double timeout_ms, uint64_t *ticket) {
+    if (!sv || !g || !ticket || !(timeout_ms >= 0.0)) return MBE_ERR_INVALID_ARG;
     if (g->on_device || g->n_u < 0 || g->n_v < 0 || g->n_edges < 0) return MBE_ERR_INVALID_ARG;
     if ((g->n_u > 0 && !g->u_off) || (g->n_v > 0 && !g->v_off) || (g->n_edges > 0 && (!g->u_adj || !g->v_adj)))
         return MBE_ERR_INVALID_ARG;
@@ -1260,6 +1336,12 @@ int mbe_server_submit(mbe_server *sv, const mbe_graph *g, uint64_t *ticket) {
     }
     auto r = std::make_shared<ServerRequest>();
     r->arrival = Clock::now();
+    if (timeout_ms > 0.0) {
+        r->has_deadline = true;
+        const double capped = std::min(timeout_ms, 1e12);  // (about 30 years)
+        r->deadline = r->arrival + std::chrono::duration_cast<Clock::duration>(
+                                       std::chrono::duration<double, std::milli>(capped));
+    }
     r->u_off.assign(g->u_off ? g->u_off : nullptr, g->u_off ? g->u_off + g->n_u + 1 : nullptr);
     r->v_off.assign(g->v_off ? g->v_off : nullptr, g->v_off ? g->v_off + g->n_v + 1 : nullptr);
     r->u_adj.assign(g->u_adj ? g->u_adj : nullptr, g->u_adj ? g->u_adj + g->n_edges : nullptr);
@@ -1278,7 +1360,17 @@ int mbe_server_submit(mbe_server *sv, const mbe_graph *g, uint64_t *ticket) {
         sv->pending.push_back(r);
     }
     sv->cv_work.notify_all();  // the small-request lane may be the one that can take it
+    if (r->has_deadline) sv->cv_deadline.notify_all();
     *ticket = r->ticket;
+    return MBE_OK;
+}
+
+int mbe_server_cancel(mbe_server *sv, uint64_t ticket) {
+    if (!sv) return MBE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->live.find(ticket);
+    if (it == sv->live.end()) return MBE_ERR_INVALID_ARG;
+    sv->stop_request(it->second, MBE_ERR_CANCELLED);
     return MBE_OK;
 }
 
@@ -1305,13 +1397,16 @@ int mbe_server_destroy(mbe_server *sv) {
         sv->stopping = true;
     }
     sv->cv_work.notify_all();
+    sv->cv_deadline.notify_all();
     for (auto &t : sv->workers) t.join();
+    if (sv->watchdog.joinable()) sv->watchdog.join();
     for (size_t k = 0; k < sv->states.size(); ++k) {
         (void)hipStreamSynchronize(sv->streams[k]);
         free_state(sv->states[k]);
         delete sv->states[k];
         (void)hipStreamDestroy(sv->streams[k]);
     }
+    for (unsigned int *cw : sv->cancel) (void)hipHostFree(cw);
     delete sv;
     return MBE_OK;
 }
@@ -1418,6 +1513,8 @@ const char *mbe_strerror(int code) {
         case MBE_ERR_DEVICE: return "HIP runtime error";
         case MBE_ERR_UNSUPPORTED: return "unsupported input";
         case MBE_ERR_SCRATCH_LIMIT: return "the call needs more device memory than the fixed scratch of mbe_count_noalloc";
+        case MBE_ERR_TIMEOUT: return "the request passed its deadline";
+        case MBE_ERR_CANCELLED: return "the request was cancelled";
         default: return "unknown error";
     }
 }

@@ -194,6 +194,10 @@ struct SearchArgs {
     // load records (tally instances only, when not NULL): per workgroup of the launch, its
     // start and end on the wall clock and the time it spent finding work (3 u64 each)
     unsigned long long *wg_load;
+    // cancellation (batched work lists only, when not NULL): one word per graph in host
+    // memory that the device reads at system scope; a graph whose word is nonzero has its
+    // top-level candidates that no workgroup has claimed yet skipped (those in flight finish)
+    const unsigned int *cancel;
     // record arena (mbe_enumerate only)
     int32_t *rec;
     unsigned long long rec_cap;

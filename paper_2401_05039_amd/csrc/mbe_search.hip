@@ -146,6 +146,14 @@ __device__ __forceinline__ void see_atomics() {
     asm volatile("buffer_inv sc0" ::: "memory");
 }
 
+// Whether the graph of work-list entry ti has been cancelled by the host (batched calls of a
+// server only): the word lives in host memory, so it is read at system scope.
+__device__ __forceinline__ bool root_cancelled(const SearchArgs &a, int64_t ti) {
+    if (!a.cancel || !a.tasks) return false;
+    const int g = (int)(a.tasks[ti] >> 32);
+    return __hip_atomic_load(a.cancel + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u;
+}
+
 // Workgroup memory (LDS) pointers carry their address space, so that accesses and atomics
 // through them are LDS instructions even where the compiler cannot trace them to the shared
 // array (through a generic pointer they would be flat instructions).
@@ -1509,9 +1517,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
                     if (f & FLAG_RERUN) {
                         mode = -1;
                     } else if (!sh->roots_done) {
-                        t = atomicAdd(counter, 1u);
-                        if (lo + (int64_t)t < hi) mode = 1;
-                        else sh->roots_done = 1;
+                        for (;;) {
+                            t = atomicAdd(counter, 1u);
+                            if (lo + (int64_t)t >= hi) {
+                                sh->roots_done = 1;
+                                break;
+                            }
+                            if (!root_cancelled(a, lo + (int64_t)t)) {
+                                mode = 1;
+                                break;
+                            }
+                        }
                     }
                 }
                 mode = __builtin_amdgcn_readlane(mode, 0);
@@ -2953,7 +2969,10 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
     for (;;) {
         if (tid == 0) {
             const unsigned int f = __hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sh->task = (f & FLAG_RERUN) ? ~0ull : (unsigned long long)atomicAdd(counter, 1u);
+            unsigned long long t = (f & FLAG_RERUN) ? ~0ull : (unsigned long long)atomicAdd(counter, 1u);
+            while (t != ~0ull && (int64_t)t < ntasks && root_cancelled(a, lo + (int64_t)t % nroots))
+                t = (unsigned long long)atomicAdd(counter, 1u);
+            sh->task = t;
         }
         __syncthreads();
         const unsigned long long tt = sh->task;

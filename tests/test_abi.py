@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_strerror_and_version(lib):
     m, _ = lib
     assert m.mbe_strerror(0) == "ok"
-    for code in range(-7, 0):
+    for code in range(-9, 0):
         assert m.mbe_strerror(code) and m.mbe_strerror(code) != "unknown error"
     assert m.mbe_strerror(-99) == "unknown error"
     assert re.match(r"^\d+\.\d+\.\d+$", m.mbe_version())
@@ -133,6 +133,19 @@ def test_server_rejects_bad_options():
     with pytest.raises(m.MbeError) as e:
         m.Server(slots=99)
     assert e.value.code == -1
+
+
+def test_server_rejects_bad_deadlines(lib):
+    import paper_2401_05039_amd as m
+    _, so = lib
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(m.MbeError) as e:
+            m.Server(request_timeout_ms=bad)
+        assert e.value.code == -1
+    g, keep = m._marshal_graph(gg.complete(2, 2))
+    t = ctypes.c_uint64()
+    assert so.mbe_server_submit_timeout(None, ctypes.byref(g), ctypes.c_double(1.0), ctypes.byref(t)) == -1
+    assert so.mbe_server_cancel(None, ctypes.c_uint64(1)) == -1
 
 
 def test_batch_totals_past_int32_refused_before_device_work():

@@ -459,6 +459,81 @@ def test_server_results_equal_alone(mbe, slots, small_edges):
             assert lat >= 0.0
 
 
+# ----------------------------------------------------------------------------- deadlines and cancellation
+
+def _small_mix():
+    gs = [gg.config4_graph(i) for i in range(0, 120, 7)]
+    return [g for g in gs if g.n_edges < 20000] + [gg.config1(), gg.crown(9)]
+
+
+def _same(mbe, sv, gs, alone):
+    tks = [sv.submit(g) for g in gs]
+    for i, tk in enumerate(tks):
+        r, _ = sv.wait(tk)
+        assert (r["count"], r["hash"]) == (alone[i]["count"], alone[i]["hash"]), gs[i].name
+
+
+def test_server_deadline_stops_a_running_request(mbe):
+    """A request whose deadline passes while it is on the device (the skewed graph: about a
+    minute of search alone) stops early, its unclaimed top-level candidates skipped, and
+    returns MBE_ERR_TIMEOUT; small requests served beside it and after it are unaffected."""
+    import time
+    big = gg.config3()
+    small = _small_mix()
+    alone = [mbe.mbe_count(g) for g in small]
+    _say("server deadline", big.n_edges, len(small))
+    with mbe.Server(slots=2, small_edges=65536) as sv:
+        t0 = time.perf_counter()
+        tb = sv.submit(big, timeout_ms=1000.0)
+        _same(mbe, sv, small, alone)
+        with pytest.raises(mbe.MbeError) as e:
+            sv.wait(tb)
+        waited = time.perf_counter() - t0
+        assert e.value.code == mbe.MBE_ERR_TIMEOUT
+        assert waited < 40.0, waited
+        _same(mbe, sv, small, alone)
+
+
+def test_server_cancel_running_and_queued(mbe):
+    """One slot: a request cancelled on the device and one cancelled in the queue behind it
+    both return MBE_ERR_CANCELLED, a queued one past its deadline MBE_ERR_TIMEOUT; the
+    requests after them run on the same slot and cancel words and equal their results alone;
+    cancelling a finished request changes nothing, and a waited ticket is unknown."""
+    import time
+    big = gg.config3()
+    small = _small_mix()
+    alone = [mbe.mbe_count(g) for g in small]
+    _say("server cancel", big.n_edges, len(small))
+    with mbe.Server(slots=1) as sv:
+        with pytest.raises(mbe.MbeError) as e:
+            sv.submit(small[0], timeout_ms=-1.0)
+        assert e.value.code == mbe.MBE_ERR_INVALID_ARG
+        t0 = time.perf_counter()
+        tb = sv.submit(big)
+        time.sleep(1.0)
+        tq = sv.submit(small[0])
+        tt = sv.submit(small[1], timeout_ms=50.0)
+        sv.cancel(tq)
+        with pytest.raises(mbe.MbeError) as e:
+            sv.wait(tt)
+        assert e.value.code == mbe.MBE_ERR_TIMEOUT
+        sv.cancel(tb)
+        for tk in (tq, tb):
+            with pytest.raises(mbe.MbeError) as e:
+                sv.wait(tk)
+            assert e.value.code == mbe.MBE_ERR_CANCELLED
+        assert time.perf_counter() - t0 < 40.0
+        _same(mbe, sv, small, alone)
+        tk = sv.submit(small[2])
+        time.sleep(0.5)
+        sv.cancel(tk)  # done by now: no effect
+        r, _ = sv.wait(tk)
+        assert (r["count"], r["hash"]) == (alone[2]["count"], alone[2]["hash"])
+        with pytest.raises(mbe.MbeError) as e:
+            sv.cancel(tk)
+        assert e.value.code == mbe.MBE_ERR_INVALID_ARG
+
+
 # ----------------------------------------------------------------------------- the configs' own inputs
 
 def _gold(key):
