@@ -13,7 +13,10 @@ Routes to the set of maximal bicliques (paper, section II-A):
                    of section III-E and the ascending common-neighbour candidate order.
 
 All three return the same canonical record list; ``mbea`` also returns the count, the
-order-independent 64-bit hash and the tree diagnostics.  The C part is compiled by
+order-independent 64-bit hash and the tree diagnostics.  Two variants of ``mbea`` prune the
+tree (section II-C) with the same answer and their own tallies: ``imbea`` (candidates with the
+pivot's neighbourhood within R leave P with it) and ``pivot`` (one pivot per list below the top
+level, taken first, covering the candidates whose neighbourhoods within R it contains).  The C part is compiled by
 ``oracle.build()`` (gcc) into ``oracle/liborc_mbe.so``.
 """
 from __future__ import annotations
@@ -73,6 +76,8 @@ def _load():
             lib.orc_mbea.restype = ctypes.c_int
             lib.orc_imbea.argtypes = lib.orc_mbea.argtypes
             lib.orc_imbea.restype = ctypes.c_int
+            lib.orc_pivot.argtypes = lib.orc_mbea.argtypes
+            lib.orc_pivot.restype = ctypes.c_int
             lib.orc_brute.argtypes = [ctypes.c_int32, ctypes.c_int32, p32, p32, p32, ctypes.c_int64,
                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
             lib.orc_brute.restype = ctypes.c_int64
@@ -188,6 +193,27 @@ def imbea(g, side: int = 0, rank_lo: int = 0, rank_hi: int = -1, want_list: bool
                        rank_lo, rank_hi, _p32(buf) if want_list else None, buf.size, ctypes.byref(res))
     if rc != 0:
         raise RuntimeError("oracle imbea failed")
+    out = {k: getattr(res, k) for k, _ in OrcResult._fields_}
+    if want_list:
+        if res.written < 0:
+            raise RuntimeError("oracle record buffer too small")
+        out["list"] = canonical(split_records(buf, res.written))
+    return out
+
+
+def pivot(g, side: int = 0, rank_lo: int = 0, rank_hi: int = -1, want_list: bool = False,
+          list_cap: int = 1 << 26) -> Dict:
+    """MBEA with the pivot rule (the pivot pruning of section II-C, one pivot per list below
+    the top level covering the candidates whose neighbourhoods within R it contains): the same
+    answer as mbea, its own tree tallies.  Fields as mbea's."""
+    lib = _load()
+    u_off, u_adj, v_off, v_adj = _arrays(g)
+    res = OrcResult()
+    buf = np.zeros(list_cap if want_list else 1, dtype=np.int32)
+    rc = lib.orc_pivot(g.n_u, g.n_v, _p32(u_off), _p32(u_adj), _p32(v_off), _p32(v_adj), side,
+                       rank_lo, rank_hi, _p32(buf) if want_list else None, buf.size, ctypes.byref(res))
+    if rc != 0:
+        raise RuntimeError("oracle pivot failed")
     out = {k: getattr(res, k) for k, _ in OrcResult._fields_}
     if want_list:
         if res.written < 0:

@@ -34,7 +34,9 @@
  *       order and is then stably sorted by the counts found while building it;
  *   r6  a candidate v enters P' when 0 < |N(v) n R'| < |R'| (Algorithm 1, expansion step;
  *       the fine-grained section prints the inequality garbled);
- *   r7  the hash of a biclique follows the SplitMix64 output function (see orc_hash_pair).
+ *   r7  the hash of a biclique follows the SplitMix64 output function (see orc_hash_pair);
+ *   r13 the pivot rule of orc_pivot (see pivot_mbea): one pivot per list below the top
+ *       level, the first candidate of the largest count, covering by containment within R.
  *
  * Diagnostics (nodes, non-maximal nodes, depth, algorithmic bytes) follow the same tree.
  */
@@ -369,6 +371,118 @@ static void imbea(orc_ctx *g, const int32_t *L, int32_t nL, const int32_t *R, in
     free(Lp); free(Rp); free(Pp); free(Qp); free(Cs); free(gone);
 }
 
+/*
+ * Algorithm 1 with a pivot rule: the pivot pruning that section II-C describes (after PMBEA's
+ * containment of neighbourhoods, NCR), in the reading this file takes (r13).  In every list
+ * below the top level, the candidate p with the largest |N(p) n R| (the first such in the
+ * list's order) is taken first, and every other candidate v whose neighbours within R are all
+ * neighbours of p (N(v) n R a subset of N(p) n R) is covered by p: a maximal biclique whose L
+ * holds v holds p as well, so p's subtree finds it and v is never taken at this node.  The list
+ * is regrouped as p, then the candidates p covers, then the others (each group in the list's
+ * order), and the loop of Algorithm 1 runs over the regrouped list with the covered
+ * candidates passed over: they are candidates for p's node and, like every entry the loop has
+ * passed, Q entries for the nodes after them.  The top-level list keeps its order (its
+ * candidates are the independent root tasks of section III-C).
+ */
+static void pivot_mbea(orc_ctx *g, const int32_t *L, int32_t nL, const int32_t *R, int32_t nR,
+                       const orc_cand *P0, int32_t nP, int32_t *Q, int32_t nQ, uint32_t depth,
+                       int32_t stop_after) {
+    orc_cand *P = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(nP + 1));
+    unsigned char *covered = (unsigned char *)calloc((size_t)nP + 1, 1);
+    if (depth == 1 || nP < 2) {
+        memcpy(P, P0, sizeof(orc_cand) * (size_t)nP);
+    } else {
+        int32_t ip = 0;
+        for (int32_t i = 1; i < nP; i++)
+            if (P0[i].key > P0[ip].key) ip = i;             /* the first of the largest count */
+        const int32_t pv = P0[ip].v;
+        int32_t *Np = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nR + 1));
+        int32_t nNp = intersect(R, nR, g->c_adj + g->c_off[pv], (int32_t)deg_c(g, pv), Np);
+        unsigned char *in = (unsigned char *)calloc((size_t)nP + 1, 1);
+        for (int32_t i = 0; i < nP; i++) {
+            if (i == ip) continue;
+            const int32_t *nv = g->c_adj + g->c_off[P0[i].v];
+            int32_t dv = (int32_t)deg_c(g, P0[i].v);
+            /* N(v) n R inside N(p) n R: v meets N(p) n R as often as it meets R */
+            in[i] = meet_count(Np, nNp, nv, dv) == meet_count(R, nR, nv, dv);
+        }
+        int32_t k = 0;
+        P[k++] = P0[ip];
+        for (int32_t i = 0; i < nP; i++)
+            if (i != ip && in[i]) { covered[k] = 1; P[k++] = P0[i]; }
+        for (int32_t i = 0; i < nP; i++)
+            if (i != ip && !in[i]) P[k++] = P0[i];
+        free(Np); free(in);
+    }
+    int32_t *Lp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nL + nP + 1));
+    int32_t *Rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nR + 1));
+    orc_cand *Pp = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(nP + 1));
+    int32_t *Qp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nQ + nP + 1));
+    int32_t taken = 0;
+
+    for (int32_t ip = 0; ip < nP; ip++) {
+        if (stop_after >= 0 && taken >= stop_after) break;
+        int32_t x = P[ip].v;
+        if (covered[ip]) { Q[nQ++] = x; continue; }      /* passed over: a Q entry from here on */
+        taken++;
+        const orc_cand *Prest = P + ip + 1;
+        int32_t nPrest = nP - ip - 1;
+        g->res->nodes += 1;
+        if (depth > g->res->max_depth) g->res->max_depth = depth;
+        int32_t nLp = 0;
+        for (int32_t i = 0; i < nL; i++) Lp[nLp++] = L[i];
+        Lp[nLp++] = x;
+        const int32_t *nx = g->c_adj + g->c_off[x];
+        int32_t nRp = intersect(R, nR, nx, (int32_t)deg_c(g, x), Rp);
+        for (int32_t i = 0; i < nRp; i++) {
+            int32_t w = Rp[i];
+            for (int32_t e = g->o_off[w]; e < g->o_off[w + 1]; e++) g->cnt[g->o_adj[e]] += 1;
+        }
+        uint64_t rs = 0, fw = 0;
+        for (int32_t i = 0; i < nRp; i++) rs += 2 + (uint64_t)deg_o(g, Rp[i]);
+        for (int32_t i = 0; i < nPrest; i++) fw += 2 + (uint64_t)deg_c(g, Prest[i].v);
+        for (int32_t i = 0; i < nQ; i++) fw += 2 + (uint64_t)deg_c(g, Q[i]);
+        int maximal = 1;
+        int32_t nQp = 0;
+        for (int32_t i = 0; i < nQ; i++) {
+            int32_t c = g->cnt[Q[i]];
+            if (c == nRp) { maximal = 0; break; }
+            else if (c > 0) Qp[nQp++] = Q[i];
+        }
+        int32_t nPp = 0;
+        if (maximal) {
+            for (int32_t i = 0; i < nPrest; i++) {
+                int32_t v = Prest[i].v, c = g->cnt[v];
+                if (c == nRp) Lp[nLp++] = v;
+                else if (c > 0) { Pp[nPp].key = c; Pp[nPp].v = v; Pp[nPp].seq = nPp; nPp++; }
+            }
+        } else {
+            g->res->nonmaximal += 1;
+            nQp = 0;
+        }
+        for (int32_t i = 0; i < nRp; i++) {
+            int32_t w = Rp[i];
+            for (int32_t e = g->o_off[w]; e < g->o_off[w + 1]; e++) g->cnt[g->o_adj[e]] = 0;
+        }
+        uint64_t state = (uint64_t)nPrest + (uint64_t)nQ + (uint64_t)nRp + (uint64_t)nPp + (uint64_t)nQp;
+        uint64_t base = 2 + (uint64_t)deg_c(g, x) + state;
+        g->res->bytes_alg += 4 * (base + (rs < fw ? rs : fw));
+        g->res->bytes_rs += 4 * (base + rs);
+        if (maximal) {
+            report(g, Lp, nLp, Rp, nRp);
+            if (nPp > 0) {
+                qsort(Pp, (size_t)nPp, sizeof(orc_cand), cmp_cand);
+                int32_t *Qchild = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nQp + nPp + 1));
+                memcpy(Qchild, Qp, sizeof(int32_t) * (size_t)nQp);
+                pivot_mbea(g, Lp, nLp, Rp, nRp, Pp, nPp, Qchild, nQp, depth + 1, -1);
+                free(Qchild);
+            }
+        }
+        Q[nQ++] = x;
+    }
+    free(P); free(covered); free(Lp); free(Rp); free(Pp); free(Qp);
+}
+
 /* Candidate side: 1 = U, 2 = V, 0 = the smaller side, U on a tie (reading r4). */
 static int pick_side(int32_t n_u, int32_t n_v, int side) {
     if (side == 1 || side == 2) return side;
@@ -469,6 +583,53 @@ int orc_imbea(int32_t n_u, int32_t n_v, const int32_t *u_off, const int32_t *u_a
     g.cnt = (int32_t *)calloc((size_t)g.nc, sizeof(int32_t));
     if (!P || !R || !Q || !g.cnt) { free(P); free(R); free(Q); free(g.cnt); return -1; }
     if (rank_lo < rank_hi) imbea(&g, NULL, 0, R, g.no, P, nP, Q, 0, 1, (int32_t)rank_lo, (int32_t)rank_hi);
+    free(P); free(R); free(Q); free(g.cnt);
+    return 0;
+}
+
+/*
+ * As orc_mbea, with the pivot rule (see pivot_mbea).  The top-level list keeps the plain
+ * order, so rank ranges split the run exactly as they do for orc_mbea.
+ */
+int orc_pivot(int32_t n_u, int32_t n_v, const int32_t *u_off, const int32_t *u_adj,
+              const int32_t *v_off, const int32_t *v_adj, int side, int64_t rank_lo,
+              int64_t rank_hi, int32_t *buf, int64_t buf_cap, orc_result *res) {
+    if (!res || n_u < 0 || n_v < 0) return -1;
+    memset(res, 0, sizeof(*res));
+    side = pick_side(n_u, n_v, side);
+    res->side = (uint32_t)side;
+    orc_ctx g;
+    memset(&g, 0, sizeof(g));
+    g.c_is_v = (side == 2);
+    g.nc = g.c_is_v ? n_v : n_u;
+    g.no = g.c_is_v ? n_u : n_v;
+    g.c_off = g.c_is_v ? v_off : u_off;
+    g.c_adj = g.c_is_v ? v_adj : u_adj;
+    g.o_off = g.c_is_v ? u_off : v_off;
+    g.o_adj = g.c_is_v ? u_adj : v_adj;
+    g.buf = buf;
+    g.buf_cap = buf_cap;
+    g.res = res;
+    if (g.nc == 0 || g.no == 0) return 0;
+    orc_cand *P = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)g.nc);
+    int32_t nP = 0;
+    for (int32_t v = 0; v < g.nc; v++) {
+        int64_t d = deg_c(&g, v);
+        if (d > 0) { P[nP].key = (int32_t)d; P[nP].v = v; P[nP].seq = v; nP++; }
+    }
+    qsort(P, (size_t)nP, sizeof(orc_cand), cmp_cand);
+    if (rank_lo < 0) rank_lo = 0;
+    if (rank_hi < 0 || rank_hi > nP) rank_hi = nP;
+    int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (size_t)g.no);
+    for (int32_t w = 0; w < g.no; w++) R[w] = w;
+    int32_t *Q = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nP + 1));
+    int32_t nQ = 0;
+    for (int64_t i = 0; i < rank_lo && i < nP; i++) Q[nQ++] = P[i].v;
+    g.cnt = (int32_t *)calloc((size_t)g.nc, sizeof(int32_t));
+    if (!P || !R || !Q || !g.cnt) { free(P); free(R); free(Q); free(g.cnt); return -1; }
+    if (rank_lo < rank_hi)
+        pivot_mbea(&g, NULL, 0, R, g.no, P + rank_lo, (int32_t)(nP - rank_lo), Q, nQ, 1,
+                   (int32_t)(rank_hi - rank_lo));
     free(P); free(R); free(Q); free(g.cnt);
     return 0;
 }

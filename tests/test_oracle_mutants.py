@@ -9,8 +9,9 @@ oracle's C source (on the CPU), builds it, and runs the pins on the copy alone:
 * the tree: node, non-maximal, depth and byte tallies of the hand-derived closed forms.
 
 A mutant must fail at least one of them.  The plain search's mutants are planted outside the
-iMBEA variant's code, and the variant's mutants inside it; the variant's pins are its
-definition list (brute force) and its hand-derived trees (tests/test_oracle_imbea.py)."""
+variants' code, and each variant's mutants inside its own; a variant's pins are its
+definition list (brute force) and its hand-derived trees (tests/test_oracle_imbea.py,
+tests/test_oracle_pivot.py)."""
 import ctypes
 import os
 import subprocess
@@ -53,33 +54,50 @@ IMBEA_MUTANTS = {
     "imbea_silent_prefix_counted": ("if (!silent) {\n            g->res->nodes += 1;", "{\n            g->res->nodes += 1;"),
 }
 
-# the iMBEA variant's code: from its count-only merge to the plain entry's side rule, and its
-# entry point
-_IMBEA_SPANS = [("/* |R n N(v)| for ascending R and N(v)", "/* Candidate side: 1 = U, 2 = V"),
-                ("/*\n * As orc_mbea, with iMBEA's candidate pruning", "/* Number of top-level candidates")]
+PIVOT_MUTANTS = {
+    "pivot_containment_reversed": ("in[i] = meet_count(Np, nNp, nv, dv) == meet_count(R, nR, nv, dv);",
+                                   "in[i] = meet_count(Np, nNp, nv, dv) == nNp;"),
+    "pivot_first_entry_not_largest": ("if (P0[i].key > P0[ip].key) ip = i;", "if (0) ip = i;"),
+    "pivot_last_of_largest": ("if (P0[i].key > P0[ip].key) ip = i;", "if (P0[i].key >= P0[ip].key) ip = i;"),
+    "pivot_covered_still_taken": ("if (covered[ip]) { Q[nQ++] = x; continue; }", "if (0) { Q[nQ++] = x; continue; }"),
+    "pivot_covered_not_in_q": ("if (covered[ip]) { Q[nQ++] = x; continue; }", "if (covered[ip]) { continue; }"),
+    "pivot_at_top_level": ("if (depth == 1 || nP < 2) {", "if (nP < 2) {"),
+}
+
+# each variant's code: (start marker, end marker) spans of the source
+_SPANS = {
+    "imbea": [("/* |R n N(v)| for ascending R and N(v)", "/*\n * Algorithm 1 with a pivot rule"),
+              ("/*\n * As orc_mbea, with iMBEA's candidate pruning", "/*\n * As orc_mbea, with the pivot rule")],
+    "pivot": [("/*\n * Algorithm 1 with a pivot rule", "/* Candidate side: 1 = U, 2 = V"),
+              ("/*\n * As orc_mbea, with the pivot rule", "/* Number of top-level candidates")],
+}
 
 
 def _split(src):
-    """(text outside the iMBEA code with placeholders, the iMBEA pieces)."""
-    pieces = []
-    for a, b in _IMBEA_SPANS:
-        i, j = src.index(a), src.index(b)
-        pieces.append(src[i:j])
-        src = src[:i] + f"@@IMBEA{len(pieces) - 1}@@" + src[j:]
+    """(text outside the variants' code with placeholders, {variant: its pieces})."""
+    pieces = {}
+    for name, spans in _SPANS.items():
+        for a, b in spans:
+            i, j = src.index(a), src.index(b)
+            pieces.setdefault(name, []).append(src[i:j])
+            src = src[:i] + f"@@{name}{len(pieces[name]) - 1}@@" + src[j:]
     return src, pieces
 
 
 def _join(outside, pieces):
-    for k, p in enumerate(pieces):
-        outside = outside.replace(f"@@IMBEA{k}@@", p)
+    for name, ps in pieces.items():
+        for k, p in enumerate(ps):
+            outside = outside.replace(f"@@{name}{k}@@", p)
     return outside
 
 
-def _plant(src, old, new, inside):
+def _plant(src, old, new, inside=None):
+    """The source with old replaced by new, inside one variant's code (inside = its name) or
+    outside every variant's; old must occur there exactly once."""
     outside, pieces = _split(src)
     if inside:
-        assert sum(p.count(old) for p in pieces) == 1, old
-        pieces = [p.replace(old, new) for p in pieces]
+        assert sum(p.count(old) for p in pieces[inside]) == 1, old
+        pieces[inside] = [p.replace(old, new) for p in pieces[inside]]
     else:
         assert outside.count(old) == 1, old
         outside = outside.replace(old, new)
@@ -105,6 +123,7 @@ class _Copy:
         lib.orc_mbea.argtypes = [ctypes.c_int32, ctypes.c_int32, p32, p32, p32, p32, ctypes.c_int, ctypes.c_int64,
                                  ctypes.c_int64, p32, ctypes.c_int64, ctypes.POINTER(orc.OrcResult)]
         lib.orc_imbea.argtypes = lib.orc_mbea.argtypes
+        lib.orc_pivot.argtypes = lib.orc_mbea.argtypes
         lib.orc_hash_pair.argtypes = [p32, ctypes.c_int64, p32, ctypes.c_int64]
         lib.orc_hash_pair.restype = ctypes.c_uint64
         self.lib, self.p32 = lib, p32
@@ -192,21 +211,55 @@ def _imbea_pins_fail(orc, cp):
     return None
 
 
+def _pivot_pins_fail(orc, cp):
+    """Name of the first pivot pin the copy fails, or None (tests/test_oracle_pivot.py)."""
+    g1 = gg.from_edges(3, 7, [0, 0, 0, 1, 1, 1, 1, 2, 2, 2], [0, 1, 2, 0, 1, 3, 4, 0, 5, 6])
+    res, _ = cp.mbea(g1, "orc_pivot")
+    if (res.nodes, res.nonmaximal, res.count, res.max_depth, res.bytes_alg) != (6, 1, 5, 3, 416):
+        return "hand-worked tree (deeper)"
+    g2 = gg.from_edges(4, 7, [0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3], [0, 1, 2, 0, 3, 4, 0, 1, 5, 1, 2, 6])
+    res, _ = cp.mbea(g2, "orc_pivot")
+    if (res.nodes, res.nonmaximal, res.count, res.max_depth, res.bytes_alg) != (10, 2, 8, 3, 772):
+        return "hand-worked tree (covered entries in Q)"
+    us, vs = [], []
+    for i in range(5):
+        us += [i] * 4
+        vs += [0, 1, 2, 3 + i]
+    res, _ = cp.mbea(gg.from_edges(5, 8, us, vs), "orc_pivot")
+    if (res.nodes, res.nonmaximal, res.count, res.max_depth) != (9, 3, 6, 2):
+        return "private-neighbour family"
+    graphs = [gg.crown(6), gg.chain(7), gg.complete_minus_edge(4, 5)] + [gg.random_small(10, 12, 0.4, s) for s in range(30)]
+    for g in graphs:
+        b = orc.brute(g)
+        res, lst = cp.mbea(g, "orc_pivot")
+        if res.count != len(b["list"]) or lst != b["list"] or res.hash != hc.total(b["list"]):
+            return "definition " + g.name
+    return None
+
+
 def test_unmodified_source_passes_every_pin(orc):
     cp = _Copy(orc, _build(open(SRC).read()))
     assert _pins_fail(orc, cp) is None
     assert _imbea_pins_fail(orc, cp) is None
+    assert _pivot_pins_fail(orc, cp) is None
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(orc, name):
     old, new = MUTANTS[name]
-    cp = _Copy(orc, _build(_plant(open(SRC).read(), old, new, inside=False)))
+    cp = _Copy(orc, _build(_plant(open(SRC).read(), old, new)))
     assert _pins_fail(orc, cp) is not None, f"mutant {name} passed every pin"
 
 
 @pytest.mark.parametrize("name", sorted(IMBEA_MUTANTS))
 def test_imbea_pins_catch_mutant(orc, name):
     old, new = IMBEA_MUTANTS[name]
-    cp = _Copy(orc, _build(_plant(open(SRC).read(), old, new, inside=True)))
+    cp = _Copy(orc, _build(_plant(open(SRC).read(), old, new, inside="imbea")))
     assert _imbea_pins_fail(orc, cp) is not None, f"mutant {name} passed every pin"
+
+
+@pytest.mark.parametrize("name", sorted(PIVOT_MUTANTS))
+def test_pivot_pins_catch_mutant(orc, name):
+    old, new = PIVOT_MUTANTS[name]
+    cp = _Copy(orc, _build(_plant(open(SRC).read(), old, new, inside="pivot")))
+    assert _pivot_pins_fail(orc, cp) is not None, f"mutant {name} passed every pin"

@@ -27,7 +27,8 @@ def test_oracle_pins_under_sanitizers():
            "import oracle; oracle.build(force=True)"]
     subprocess.run(cmd, cwd=ROOT, env=env, check=True, timeout=300)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        "tests/test_oracle.py", "tests/test_oracle_pins.py", "tests/test_oracle_imbea.py"],
+                        "tests/test_oracle.py", "tests/test_oracle_pins.py", "tests/test_oracle_imbea.py",
+                        "tests/test_oracle_pivot.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
     assert "passed" in r.stdout
