@@ -184,6 +184,23 @@ def steal_ablation(mbe, dg, rng, steps=3):
     return out
 
 
+def prune_study(mbe, dg, rng, plain, steps=3):
+    """The tree and search time under the pruning of section II-C (same answers): iMBEA's
+    candidate pruning (prune = 1) and the pivot rule (prune = 2), both run by the generic-width
+    search, beside the plain tree of the fixed-width classes (plain: its diagnostics result)."""
+    lo, hi = rng if rng else (0, 0)
+    out = {"plain": {"nodes": plain["nodes"], "nonmaximal": plain["nonmaximal"], "max_depth": plain["max_depth"]}}
+    for name, mode in (("imbea", 1), ("pivot", 2)):
+        d = mbe.mbe_count(dg, mbe.Options(prune=mode, diagnostics=1, root_lo=lo, root_hi=hi))
+        assert (d["count"], d["hash"]) == (plain["count"], plain["hash"]), name
+        opt = mbe.Options(prune=mode, root_lo=lo, root_hi=hi)
+        mbe.mbe_count(dg, opt)
+        ks = [mbe.mbe_count(dg, opt)["kernel_ms"] for _ in range(steps)]
+        out[name] = {"nodes": d["nodes"], "nonmaximal": d["nonmaximal"], "max_depth": d["max_depth"],
+                     "search_ms": sum(ks) / len(ks)}
+    return out
+
+
 def generate(fn, items, workers=BOX_THREADS):
     """[fn(x) for x in items], on a pool of forked worker processes when more than one host
     thread is available (the graphs are seeded per item, so the result is the same).  Called
@@ -567,6 +584,8 @@ def main():
         "phase_share": phase_share,
     }
     out["steal_ablation"] = steal_ablation(mbe, dg, rng_range)
+    log("prune study")
+    out["prune_study"] = prune_study(mbe, dg, rng_range, diag)
     if not args.no_load_study:
         # the load study on the skewed graph's sample of 64 top-level candidates (deep,
         # unbalanced subtrees)

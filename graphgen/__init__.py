@@ -25,7 +25,7 @@ __all__ = [
     "erdos_renyi_m", "chung_lu", "planted_bicliques", "union",
     "config1", "config2", "config3", "config4_graph", "config4_batch", "config5_requests",
     "config5_arrivals", "config5_build",
-    "complete", "perfect_matching", "crown", "chain", "complete_minus_edge", "edgeless",
+    "complete", "perfect_matching", "crown", "chain", "private_neighbours", "complete_minus_edge", "edgeless",
     "disjoint_union", "transpose", "relabel", "random_small",
 ]
 
@@ -411,6 +411,16 @@ def crown(n: int) -> BiGraph:
     vs = np.tile(np.arange(n), n)
     keep = us != vs
     return from_edges(n, n, us[keep], vs[keep], name=f"crown{n}")
+
+
+def private_neighbours(m: int, n: int) -> BiGraph:
+    """K_{m,n} (U = u_0 .. u_{m-1}, V = w_0 .. w_{n-1}) plus one private neighbour p_i of each
+    u_i (V id n + i)."""
+    us, vs = [], []
+    for i in range(m):
+        us.extend([i] * (n + 1))
+        vs.extend(list(range(n)) + [n + i])
+    return from_edges(m, n + m, us, vs, name=f"private{m}x{n}")
 
 
 def chain(n: int) -> BiGraph:

@@ -146,14 +146,21 @@ typedef struct mbe_result {
  *                candidates of degree > 0); root_hi <= 0 means "to the end".  Results over
  *                disjoint rank ranges add up to the whole result.
  *   stream       hipStream_t to run on, or NULL.
- *   prune        1: iMBEA's candidate pruning (the embedded pruning of section II-C): when a
- *                node's candidate x is maximal, every other candidate that joins L' and has no
- *                neighbour in R outside R' leaves P and joins Q with x.  The answer is the
- *                same; the tree and its tallies are the pruned ones.  Every top-level
- *                candidate is then searched by the wide search (a preparation pass finds the
- *                candidates with equal rows), Q lists are kept whole, and the fixed mask
- *                classes are not used.  Not with diagnostics = 2, mbe_count_loads or the
- *                batched and served forms (MBE_ERR_INVALID_ARG).
+ *   prune        the embedded pruning of section II-C; the answer is the same, the tree and
+ *                its tallies are the pruned ones:
+ *                1: iMBEA's candidate pruning: when a node's candidate x is maximal, every
+ *                   other candidate that joins L' and has no neighbour in R outside R' leaves
+ *                   P and joins Q with x (a preparation pass finds the candidates with equal
+ *                   rows);
+ *                2: the pivot rule: in every candidate list below the top level, the first
+ *                   candidate p of the largest count |N(p) n R| is taken first, and the
+ *                   candidates whose neighbours within R are all neighbours of p (every
+ *                   maximal biclique holding one of them holds p) are never taken: they are
+ *                   candidates for p's node and Q entries for the nodes after them.
+ *                Either way every top-level candidate is searched by the wide search, Q
+ *                lists are kept whole, and the fixed mask classes are not used.  Other
+ *                values, and pruning with diagnostics = 2, mbe_count_loads or the batched
+ *                and served forms: MBE_ERR_INVALID_ARG.
  */
 typedef struct mbe_options {
     int32_t side;

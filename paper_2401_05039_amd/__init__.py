@@ -75,7 +75,9 @@ class Options:
     root_lo: int = 0
     root_hi: int = 0
     stream: Optional[int] = None  # hipStream_t as an integer; None = torch's current stream
-    prune: bool = False  # iMBEA's candidate pruning (the same answer, the pruned tree's tallies)
+    # pruning of section II-C (the same answer, the pruned tree's tallies): 0 / False none,
+    # 1 / True iMBEA's candidate pruning, 2 the pivot rule
+    prune: int = 0
 
 
 class _ServerOptions(ctypes.Structure):
@@ -186,7 +188,7 @@ def _marshal_opts(opt: Optional[Options], on_device: bool) -> _Options:
         import torch
         stream = torch.cuda.current_stream().cuda_stream
     return _Options(opt.side, opt.wg_waves, opt.grid, int(opt.diagnostics), int(bool(opt.no_validate)),
-                    opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0), int(bool(opt.prune)))
+                    opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0), int(opt.prune))
 
 
 PHASES = ("root", "light", "check", "expand", "child", "wait")

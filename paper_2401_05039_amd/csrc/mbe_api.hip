@@ -180,7 +180,7 @@ constexpr size_t kWideArenaBytes = (size_t)4 << 30;
 struct Opts {
     int side, waves, grid, diag, no_validate, steal_k;
     int tb;     // diagnostics = 2: the production search with its design-byte tally
-    int prune;  // the candidate pruning of section II-C
+    int prune;  // section II-C: 1 iMBEA's candidate pruning, 2 the pivot rule
     int64_t root_lo, root_hi;
     hipStream_t stream;
 };
@@ -193,8 +193,9 @@ Opts read_opts(const mbe_options *o) {
     r.grid = o->grid > 0 ? o->grid : 0;
     r.diag = o->diagnostics == 1;
     r.tb = o->diagnostics == 2;
-    r.prune = o->prune != 0;
-    if (r.prune && r.tb) r.side = -1;  // (no tally instance with pruning: rejected)
+    r.prune = o->prune;
+    if (r.prune < 0 || r.prune > 2) r.side = -1;  // (rejected as an invalid argument)
+    if (r.prune && r.tb) r.side = -1;             // (no tally instance with pruning: rejected)
     if (o->diagnostics < 0 || o->diagnostics > 2) r.side = -1;  // (rejected as an invalid argument)
     r.no_validate = o->no_validate != 0;
     r.steal_k = o->steal_k == 0 ? 2 : o->steal_k;
@@ -368,6 +369,8 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         wr.lo = lo;
         wr.hi = hi;
         for (int c = 0; c < 5; ++c) cls_lo[c] = cls_hi[c] = 0;
+    }
+    if (opt.prune == 1) {
         // twins: candidates with equal rows, found by a sort of row keys; twin[v] = the lowest
         // rank with v's row
         const size_t b_k = align_up((size_t)nc * 8, 256), b_v = align_up((size_t)nc * 4, 256);
@@ -442,6 +445,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
 
     SearchArgs a{};
     a.twin = twin;
+    a.pivot = opt.prune == 2 ? 1 : 0;
     a.steal_on = opt.steal_k >= 2 ? 1 : 0;
     a.k3 = opt.steal_k >= 3 ? 1 : 0;
     a.c_off = c_off;
@@ -718,7 +722,8 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
                 load_launch.push_back({0, wgrid});
                 load_off += wgrid;
             }
-            MBE_TRY(launch_wide(ac, diag, enumerate, tb, wr.lo, wr.hi, counters + 5, wgrid, waves, s, a.twin != nullptr));
+            MBE_TRY(launch_wide(ac, diag, enumerate, tb, wr.lo, wr.hi, counters + 5, wgrid, waves, s,
+                                a.twin != nullptr ? 1 : (a.pivot ? 2 : 0)));
         }
         MBE_TRY(hipEventRecord(st->ev1, s));
         MBE_TRY(hipMemcpyAsync(hacc, run_acc, ACC_SLOTS * 8, hipMemcpyDeviceToHost, s));

@@ -191,6 +191,8 @@ struct SearchArgs {
     // candidate pruning (wide search only, when not NULL): twin[v] = the lowest rank of a
     // candidate whose row equals v's
     const int32_t *twin;
+    // pivot rule (wide search only, when nonzero): child lists are regrouped around a pivot
+    int32_t pivot;
     // load records (tally instances only, when not NULL): per workgroup of the launch, its
     // start and end on the wall clock and the time it spent finding work (3 u64 each)
     unsigned long long *wg_load;
@@ -222,8 +224,9 @@ hipError_t launch_search(const SearchArgs &a, int W, bool diag, bool enumerate, 
 // over tasks [lo, hi) of the work list (or ranks [lo, hi) of graph 0), each of whose
 // top-level candidates is shared by wl.reps workgroups; counter must be zero.
 WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdepth, int waves);
+// prune: 0 the plain search, 1 iMBEA's candidate pruning (a.twin set), 2 the pivot rule.
 hipError_t launch_wide(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi,
-                       unsigned int *counter, int grid, int waves, hipStream_t s, bool prune = false);
+                       unsigned int *counter, int grid, int waves, hipStream_t s, int prune = 0);
 
 // Graph preparation and validation (mbe_prep.hip).
 hipError_t launch_validate(int32_t n_u, int32_t n_v, int32_t n_edges, const int32_t *u_off, const int32_t *u_adj,

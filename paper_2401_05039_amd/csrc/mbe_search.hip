@@ -2379,7 +2379,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
 //    top-level node itself.
 
 // ids[n] | hs[n] (u64) | masks[n][wf] (u64) | first[rb] | cnt[rb] | H[rb] (u64) | orig[rb] |
-// rows[rb][nw] (u64), with wf = ceil(rb / 64), nw = ceil(n / 64); 32-bit words.
+// rows[rb][nw] (u64) | skip[2], with wf = ceil(rb / 64), nw = ceil(n / 64); 32-bit words.
+// skip[0] (pivot rule only): the number of covered candidates right after the pivot.
 __device__ __forceinline__ uint64_t wframe_words(int n, int rb) {
     const uint64_t wf = ((uint64_t)rb + 63u) >> 6, nw = ((uint64_t)n + 63u) >> 6;
     uint64_t o = align2((uint32_t)n);
@@ -2389,6 +2390,7 @@ __device__ __forceinline__ uint64_t wframe_words(int n, int rb) {
     o += (uint64_t)rb;         // orig
     o = (o + 1ull) & ~1ull;
     o += 2ull * (uint64_t)rb * nw;
+    o += 2ull;                 // skip
     return o;
 }
 
@@ -2401,6 +2403,7 @@ struct WFrameView {
     uint64_t *H;
     uint32_t *orig;
     uint64_t *rows;
+    uint32_t *skip;
     int nw, wf;
 };
 
@@ -2424,6 +2427,8 @@ __device__ __forceinline__ WFrameView wframe_view(uint32_t *base, int n, int rb)
     o += (uint64_t)rb;
     o = (o + 1ull) & ~1ull;
     v.rows = reinterpret_cast<uint64_t *>(base + o);
+    o += 2ull * (uint64_t)rb * (uint64_t)v.nw;
+    v.skip = base + o;
     return v;
 }
 
@@ -2442,13 +2447,16 @@ struct WCtx {
 // IMB: the candidate pruning of section II-C (see heavy_wide); a single-bit candidate whose
 // bit is first held by an earlier candidate of the list (a twin, maximal as the first holder)
 // left the list with it and is not a node.
-template <bool DIAG, bool ENUM, bool TB, bool IMB = false>
+// PIV: the pivot rule (see heavy_wide); the candidates the pivot covers, right after it, are
+// not taken.
+template <bool DIAG, bool ENUM, bool TB, bool IMB = false, bool PIV = false>
 __device__ __forceinline__ uint64_t light_wide(const WCtx &w, const FrameState &F, const WFrameView &v, int base,
                                                WaveAcc &acc) {
     const Ctx &c = w.c;
     const int ln = lane_id();
     const int i = base + ln;
-    const bool act = i < F.n;
+    const int nskip = PIV ? (int)uni(*v.skip) : 0;
+    const bool act = i < F.n && !(PIV && i > F.nq && i <= F.nq + nskip);
     int r = 0, b = 0;
     if (act)
         for (int q = 0; q < v.wf; ++q) {
@@ -2503,7 +2511,13 @@ __device__ __forceinline__ void wide_table_add(const WFrameView &v2, int q, uint
 // earliest) is maximal is never a node, and for the nodes between the two it is a Q entry --
 // their child lists take it into Q' instead of P'.  The first twin is maximal exactly when no
 // Q entry of the list holds the mask.
-template <bool DIAG, bool ENUM, bool TB, bool IMB = false>
+// PIV: the pivot pruning of section II-C.  A child list's candidates, sorted by count, are
+// regrouped as the pivot p (the first of the largest count), then the candidates whose masks
+// lie inside p's (covered: every maximal biclique with one of them holds p), then the rest,
+// each group in sorted order; skip[0] of the child frame holds the number covered.  The
+// covered ones are never taken: they are candidates for p's node and Q entries (positions
+// before) for the nodes after them.
+template <bool DIAG, bool ENUM, bool TB, bool IMB = false, bool PIV = false>
 __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, const WFrameView &v, int i, FrameState &C,
                                            WaveAcc &acc) {
     const Ctx &c = w.c;
@@ -2698,6 +2712,7 @@ __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, c
     for (int b = ln; b <= r; b += 64) w.hist[b] = 0u;
     wait_mem();
     uint64_t fwc = 0;
+    int cmax = 0;  // (PIV) the largest count
     for (int base = 0; base < nu; base += 64) {
         const int j = base + ln;
         if (j < nu) {
@@ -2709,6 +2724,7 @@ __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, c
                     if (mq) cnt += __popcll(v.masks[(size_t)k * wf + q] & mq);
                 }
                 atomicAdd(&w.hist[cnt], 1u);
+                if (PIV) cmax = cnt > cmax ? cnt : cmax;
             }
             if (DIAG) fwc += 2ull + deg_of(c, v.ids[k]);
         }
@@ -2776,11 +2792,74 @@ __device__ __forceinline__ bool heavy_wide(const WCtx &w, const FrameState &F, c
     }
     wait_mem();
     const int nbits = r <= 1 ? 1 : 32 - __clz(r - 1);
+    if (PIV) {
+        // the P' entries in sorted order into stu2 (the placement the plain build makes), then
+        // regrouped into stu[qn, nu): the pivot, the entries it covers, the others
+        const int cm = __builtin_amdgcn_readfirstlane(wave_max_u32((uint32_t)cmax));
+        const int pslot = (int)uni(w.hist[cm]) - qn;  // the first slot of the largest count
+        wait_mem();
+        for (int base = qn; base < nu; base += 64) {
+            const int j = base + ln;
+            const bool inp = j < nu;
+            const int k = inp ? (int)c.stu[j] : 0;
+            int cnt = 0;
+            if (inp)
+                for (int q = 0; q < wf; ++q) {
+                    const uint64_t mq = w.mR[q];
+                    if (mq) cnt += __popcll(v.masks[(size_t)k * wf + q] & mq);
+                }
+            uint64_t same = __ballot(inp);
+            for (int bit = 0; bit < nbits; ++bit) {
+                const bool on = (cnt >> bit) & 1;
+                const uint64_t bb = __ballot(inp && on);
+                same &= on ? bb : ~bb;
+            }
+            uint32_t start = 0;
+            if (inp) start = w.hist[cnt];
+            if (inp) {
+                w.stu2[start + (uint32_t)__popcll(same & below) - (uint32_t)qn] = (uint32_t)k;
+                if ((same >> ln) == 1ull) w.hist[cnt] = start + (uint32_t)__popcll(same);
+            }
+            see_atomics();  // (the next round reads the updated histogram entries; stu2 after)
+        }
+        const int kp = (int)uni(w.stu2[pslot]);
+        int ncov = 0;
+        for (int base = 0; base < pn; base += 64) {
+            const int t = base + ln;
+            bool cov = false;
+            if (t < pn && t != pslot) {
+                const int k = (int)w.stu2[t];
+                cov = true;
+                for (int q = 0; q < wf && cov; ++q) {
+                    const uint64_t mq = w.mR[q];
+                    if (mq) cov = ((v.masks[(size_t)k * wf + q] & mq) & ~v.masks[(size_t)kp * wf + q]) == 0ull;
+                }
+            }
+            if (t < pn) w.stu2[t] |= cov ? 0x80000000u : 0u;  // (positions are below 2^31)
+            ncov += __popcll(__ballot(cov));
+        }
+        wait_mem();
+        int ac = qn + 1, ao = qn + 1 + ncov;
+        if (ln == 0) c.stu[qn] = (uint32_t)kp;
+        for (int base = 0; base < pn; base += 64) {
+            const int t = base + ln;
+            const bool act = t < pn && t != pslot;
+            const uint32_t e = t < pn ? w.stu2[t] : 0u;
+            const bool cov = act && (e & 0x80000000u);
+            const uint64_t bc = __ballot(cov), bo = __ballot(act && !cov);
+            if (cov) c.stu[ac + __popcll(bc & below)] = e & 0x7FFFFFFFu;
+            if (act && !cov) c.stu[ao + __popcll(bo & below)] = e;
+            ac += __popcll(bc);
+            ao += __popcll(bo);
+        }
+        if (ln == 0) *v2.skip = (uint32_t)ncov;
+        wait_mem();
+    }
     for (int base = 0; base < nu; base += 64) {
         const int j = base + ln;
         const bool act = j < nu;
         const int k = act ? (int)c.stu[j] : 0;
-        const bool inp = act && j >= qn;
+        const bool inp = !PIV && act && j >= qn;  // (PIV: stu is in its final order)
         int cnt = 0;
         if (inp)
             for (int q = 0; q < wf; ++q) {
@@ -2908,7 +2987,7 @@ __device__ __forceinline__ void wave_sort_by_key_g(const uint32_t *src, const ui
 // then): see heavy_wide; at the top level a candidate's twins are the candidates with its exact
 // row (a.twin), every first twin is maximal (no earlier candidate can hold its row), and the
 // later twins are never nodes.
-template <bool DIAG, bool ENUM, bool TB, bool IMB = false>
+template <bool DIAG, bool ENUM, bool TB, bool IMB = false, bool PIV = false>
 __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int64_t hi, unsigned int *counter) {
     extern __shared__ unsigned char lds_raw[];
     WGShared *sh = reinterpret_cast<WGShared *>(lds_raw);
@@ -3194,6 +3273,49 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
             wait_mem();
             const int q1 = nq0 + nmv;
             wave_sort_by_key_g(t1v, t1c, pn, d, whist, [&](uint32_t slot, uint32_t li) { ids1[q1 + slot] = li; });
+            if (PIV) {
+                // (PIV) regrouped: the pivot (the first of the largest count), the candidates
+                // whose masks lie inside its mask, the others; t1v is free after the sort
+                wait_mem();
+                const uint32_t cm = cnt1[uni(ids1[q1 + pn - 1])];
+                int nmax = 0;
+                for (int base = 0; base < pn; base += 64) {
+                    const int t = base + ln;
+                    nmax += __popcll(__ballot(t < pn && cnt1[ids1[q1 + t]] == cm));
+                }
+                const int pslot = pn - nmax;
+                const uint32_t lp = uni(ids1[q1 + pslot]);
+                int ncov = 0;
+                for (int base = 0; base < pn; base += 64) {
+                    const int t = base + ln;
+                    bool cov = false;
+                    uint32_t li = 0;
+                    if (t < pn) li = ids1[q1 + t];
+                    if (t < pn && t != pslot) {
+                        cov = true;
+                        for (int q = 0; q < wd && cov; ++q)
+                            cov = (M[(size_t)li * Wx + q] & ~M[(size_t)lp * Wx + q]) == 0ull;
+                    }
+                    if (t < pn) t1v[t] = li | (cov ? 0x80000000u : 0u);  // (indices are below 2^31)
+                    ncov += __popcll(__ballot(cov));
+                }
+                wait_mem();
+                int ac = 1, ao = 1 + ncov;
+                if (ln == 0) ids1[q1] = lp;
+                for (int base = 0; base < pn; base += 64) {
+                    const int t = base + ln;
+                    const bool act = t < pn && t != pslot;
+                    const uint32_t e = t < pn ? t1v[t] : 0u;
+                    const bool cov = act && (e & 0x80000000u);
+                    const uint64_t bc = __ballot(cov), bo = __ballot(act && !cov);
+                    if (cov) ids1[q1 + ac + __popcll(bc & lanes_below())] = e & 0x7FFFFFFFu;
+                    if (act && !cov) ids1[q1 + ao + __popcll(bo & lanes_below())] = e;
+                    ac += __popcll(bc);
+                    ao += __popcll(bo);
+                }
+                if (ln == 0) *v1.skip = (uint32_t)ncov;
+                wait_mem();
+            }
         }
         for (int b = tid; b < d; b += nt) {
             v1.first[b] = kNone;
@@ -3264,7 +3386,7 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
             if (uni(__hip_atomic_load(a.flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & FLAG_RERUN) break;
             FrameState cur = top;
             cur.chunk = top.nq + 64 * q;
-            cur.heavy = light_wide<DIAG, ENUM, TB, IMB>(w, cur, v1, cur.chunk, acc);
+            cur.heavy = light_wide<DIAG, ENUM, TB, IMB, PIV>(w, cur, v1, cur.chunk, acc);
             int depth = 0;
             while (!aborted) {
                 const WFrameView v = wframe_view(frame_base(c, cur.off), cur.n, cur.rbits);
@@ -3277,13 +3399,13 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
                         continue;
                     }
                     cur.chunk = base;
-                    cur.heavy = light_wide<DIAG, ENUM, TB, IMB>(w, cur, v, base, acc);
+                    cur.heavy = light_wide<DIAG, ENUM, TB, IMB, PIV>(w, cur, v, base, acc);
                     continue;
                 }
                 const int lane = __ffsll((unsigned long long)cur.heavy) - 1;
                 cur.heavy &= cur.heavy - 1ull;
                 FrameState ch;
-                if (heavy_wide<DIAG, ENUM, TB, IMB>(w, cur, v, cur.chunk + lane, ch, acc)) {
+                if (heavy_wide<DIAG, ENUM, TB, IMB, PIV>(w, cur, v, cur.chunk + lane, ch, acc)) {
                     if (depth + 1 >= L.maxdepth) {
                         if (ln == 0) atomicOr(a.flags, (unsigned int)FLAG_DEPTH_OVERFLOW);
                         aborted = true;
@@ -3384,7 +3506,7 @@ WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdep
     L.off_t1c = take(ucap * 4);
     L.off_whist = take((bits + 1) * 4);
     // the top-level list: ids | hs | masks | first, cnt | H | orig | rows (see wframe_view)
-    const size_t s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 4 * bits + bits + 2 + 2 * bits * ((ucap + 63) / 64);
+    const size_t s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 4 * bits + bits + 2 + 2 * bits * ((ucap + 63) / 64) + 2;
     L.off_S1 = take(s1_words * 4);
     L.off_waves = o;
     size_t w = 0;
@@ -3407,10 +3529,19 @@ WideLayout wide_layout(const SearchDims &d, int Wx, int64_t scap, int32_t maxdep
 }
 
 hipError_t launch_wide(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi,
-                       unsigned int *counter, int grid, int waves, hipStream_t s, bool prune) {
+                       unsigned int *counter, int grid, int waves, hipStream_t s, int prune) {
     dim3 g(grid), b(64 * waves);
     const size_t lds = sizeof(WGShared);
-    if (prune) {
+    if (prune == 2) {
+        if (enumerate)
+            hipLaunchKernelGGL((wide_kernel<false, true, false, false, true>), g, b, lds, s, a, lo, hi, counter);
+        else if (diag)
+            hipLaunchKernelGGL((wide_kernel<true, false, false, false, true>), g, b, lds, s, a, lo, hi, counter);
+        else
+            hipLaunchKernelGGL((wide_kernel<false, false, false, false, true>), g, b, lds, s, a, lo, hi, counter);
+        return hipGetLastError();
+    }
+    if (prune == 1) {
         if (enumerate)
             hipLaunchKernelGGL((wide_kernel<false, true, false, true>), g, b, lds, s, a, lo, hi, counter);
         else if (diag)

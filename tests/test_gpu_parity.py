@@ -755,3 +755,100 @@ def test_prune_rejected_where_unsupported(mbe):
         with pytest.raises(mbe.MbeError) as e:
             call()
         assert e.value.code == -1
+
+
+# ----------------------------------------------------------------------------- pivot rule
+
+def _with_covers(g, k, seed):
+    """g plus k candidate-side rows copied from its rows, every other one cut to half its
+    length (candidates that cover one another)."""
+    us, vs = g.edges()
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(g.n_u, size=min(k, g.n_u), replace=False)
+    cu, cv = [], []
+    for j, u in enumerate(pick):
+        row = g.row_u(int(u))
+        keep = row if j % 2 == 0 else row[: max(1, len(row) // 2)]
+        cu += [g.n_u + j] * len(keep)
+        cv += list(keep)
+    return gg.from_edges(g.n_u + len(pick), g.n_v, np.concatenate([us, cu]).astype(np.int64),
+                         np.concatenate([vs, cv]).astype(np.int64), name=f"{g.name}+covers{k}")
+
+
+def _pivot_check(mbe, orc, g, name, **kw):
+    _say("pivot", name, g.n_u, g.n_v, g.n_edges)
+    want = orc.pivot(g)
+    got = mbe.mbe_count(g, mbe.Options(diagnostics=True, prune=2, **kw))
+    for k in DIAG_KEYS:
+        assert got[k] == want[k], (name, k, got[k], want[k])
+    fast = mbe.mbe_count(g, mbe.Options(prune=2, **kw))
+    for k in ("count", "hash", "out_ints", "side"):
+        assert fast[k] == want[k], (name, "fast", k, fast[k], want[k])
+    return got
+
+
+def test_pivot_closed_forms(mbe, orc):
+    hand1 = gg.from_edges(3, 7, [0, 0, 0, 1, 1, 1, 1, 2, 2, 2], [0, 1, 2, 0, 1, 3, 4, 0, 5, 6])
+    hand2 = gg.from_edges(4, 7, [0, 0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3], [0, 1, 2, 0, 3, 4, 0, 1, 5, 1, 2, 6])
+    for g in (hand1, hand2, gg.crown(7), gg.chain(9), gg.perfect_matching(6), gg.complete(3, 4),
+              gg.complete_minus_edge(4, 6), gg.complete(2, 1500)):
+        _pivot_check(mbe, orc, g, g.name)
+    r = mbe.mbe_count(hand1, mbe.Options(diagnostics=True, prune=2))
+    assert (r["nodes"], r["nonmaximal"], r["max_depth"], r["bytes_alg"]) == (6, 1, 3, 416)
+    for m, n in ((4, 3), (9, 2), (70, 5), (130, 3)):
+        # lists of up to 129 twins below u_0: the pivot covers more than a wave's 64 lanes
+        r = _pivot_check(mbe, orc, gg.private_neighbours(m, n), f"private{m}x{n}")
+        assert (r["nodes"], r["nonmaximal"], r["count"]) == (2 * m - 1, m - 2, m + 1)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pivot_random_with_covers(mbe, orc, seed):
+    rng = np.random.default_rng(60 + seed)
+    for k in range(12):
+        nu, nv = int(rng.integers(4, 40)), int(rng.integers(8, 50))
+        g = gg.random_small(nu, nv, float(rng.uniform(0.1, 0.6)), 8500 + 100 * seed + k)
+        _pivot_check(mbe, orc, _with_covers(g, int(rng.integers(1, 10)), k), f"covers{seed}.{k}")
+
+
+def test_pivot_workloads(mbe, orc):
+    g1 = gg.config1()
+    base = _pivot_check(mbe, orc, g1, "workload1")
+    # long lists (top-level lists of ~180 entries) in a denser graph, and its transpose
+    dense = gg.random_small(200, 220, 0.1, 4242)
+    d = _pivot_check(mbe, orc, dense, "dense 200x220")
+    assert d["nodes"] < orc.mbea(dense)["nodes"]
+    _pivot_check(mbe, orc, gg.transpose(_with_covers(gg.random_small(50, 60, 0.2, 8802), 12, 2)), "transposed covers")
+    _pivot_check(mbe, orc, _wide(0), "wide0")
+    for i in (3, 13, 0):  # batch graphs of the W = 1, 2, 4 classes
+        _pivot_check(mbe, orc, gg.config4_graph(i), f"batch graph {i}")
+    for waves, grid in ((4, 1), (2, 5), (8, 0)):
+        r = mbe.mbe_count(g1, mbe.Options(diagnostics=True, prune=2, wg_waves=waves, grid=grid))
+        for k in DIAG_KEYS:
+            assert r[k] == base[k], (waves, grid, k)
+    n = orc.num_roots(g1)
+    for lo, hi in ((0, n // 3), (n // 3, n - 10), (n - 10, n)):
+        want = orc.pivot(g1, rank_lo=lo, rank_hi=hi)
+        got = mbe.mbe_count(g1, mbe.Options(diagnostics=True, prune=2, root_lo=lo, root_hi=hi))
+        for k in DIAG_KEYS:
+            assert got[k] == want[k], (lo, hi, k)
+
+
+def test_pivot_records(mbe, orc):
+    g = _with_covers(gg.config1(), 15, 3)
+    _say("pivot records")
+    want = orc.pivot(g, want_list=True)
+    res, flat = mbe.mbe_enumerate(g, mbe.Options(prune=2))
+    assert (res["count"], res["hash"]) == (want["count"], want["hash"])
+    assert mbe.decode_records(flat) == want["list"]
+
+
+def test_pivot_rejected_where_unsupported(mbe):
+    g = gg.crown(5)
+    for call in (lambda: mbe.mbe_count_batch([g], mbe.Options(prune=2)),
+                 lambda: mbe.mbe_count(g, mbe.Options(prune=2, diagnostics=2)),
+                 lambda: mbe.mbe_count_loads(g, mbe.Options(prune=2)),
+                 lambda: mbe.mbe_count(g, mbe.Options(prune=3)),
+                 lambda: mbe.mbe_count(g, mbe.Options(prune=-1))):
+        with pytest.raises(mbe.MbeError) as e:
+            call()
+        assert e.value.code == -1

@@ -19,13 +19,7 @@ TALLY = ("count", "hash", "out_ints", "nodes", "nonmaximal", "bytes_alg", "bytes
 
 
 def private_neighbours(m, n):
-    """K_{m,n} (U = u_0 .. u_{m-1}, V = w_0 .. w_{n-1}) plus one private neighbour p_i of each
-    u_i (V ids n + i)."""
-    us, vs = [], []
-    for i in range(m):
-        us += [i] * (n + 1)
-        vs += list(range(n)) + [n + i]
-    return gg.from_edges(m, n + m, us, vs)
+    return gg.private_neighbours(m, n)
 
 
 @pytest.mark.parametrize("chunk", range(4))
