@@ -37,7 +37,8 @@ extern "C" {
 #define MBE_ERR_OUT_OF_MEMORY    -4  /* device allocation failed */
 #define MBE_ERR_DEVICE           -5  /* a HIP runtime call failed */
 #define MBE_ERR_UNSUPPORTED      -6  /* (kept for binary compatibility; no longer returned) */
-#define MBE_ERR_SCRATCH_LIMIT    -7  /* mbe_count_noalloc: the call does not fit the fixed scratch */
+#define MBE_ERR_SCRATCH_LIMIT    -7  /* the call does not fit the fixed scratch (mbe_count_noalloc) or the
+                                        caller's workspace (mbe_options.workspace) */
 #define MBE_ERR_TIMEOUT          -8  /* server: the request passed its deadline (result unspecified) */
 #define MBE_ERR_CANCELLED        -9  /* server: the request was cancelled (result unspecified) */
 
@@ -161,6 +162,18 @@ typedef struct mbe_result {
  *                lists are kept whole, and the fixed mask classes are not used.  Other
  *                values, and pruning with diagnostics = 2, mbe_count_loads or the batched
  *                and served forms: MBE_ERR_INVALID_ARG.
+ *   workspace, workspace_bytes
+ *                (mbe_count only) device memory owned by the caller, on the current device,
+ *                from which every device buffer of the call is carved instead of the
+ *                library's per-device buffers: nothing is allocated, the class launches run
+ *                one after another on the call's stream, and the search grid shrinks to the
+ *                arena slots that fit.  The caller keeps the memory valid until the call
+ *                returns and must not share it with a concurrent call; its contents are
+ *                unspecified afterwards.  A call that needs more returns
+ *                MBE_ERR_SCRATCH_LIMIT.  NULL: the library's buffers.  A non-NULL workspace
+ *                with workspace_bytes 0, a NULL one with workspace_bytes > 0, or a workspace
+ *                with mbe_enumerate, mbe_count_noalloc, mbe_count_loads,
+ *                mbe_workspace_size, the batched or the served form: MBE_ERR_INVALID_ARG.
  */
 typedef struct mbe_options {
     int32_t side;
@@ -173,6 +186,8 @@ typedef struct mbe_options {
     int64_t root_hi;
     void *stream;
     int32_t prune;
+    void *workspace;
+    uint64_t workspace_bytes;
 } mbe_options;
 
 /*

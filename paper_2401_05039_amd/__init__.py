@@ -60,7 +60,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("side", ctypes.c_int32), ("wg_waves", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("diagnostics", ctypes.c_int32), ("no_validate", ctypes.c_int32),
                 ("steal_k", ctypes.c_int32), ("root_lo", ctypes.c_int64),
-                ("root_hi", ctypes.c_int64), ("stream", ctypes.c_void_p), ("prune", ctypes.c_int32)]
+                ("root_hi", ctypes.c_int64), ("stream", ctypes.c_void_p), ("prune", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
 
 
 @dataclasses.dataclass
@@ -78,6 +79,10 @@ class Options:
     # pruning of section II-C (the same answer, the pruned tree's tallies): 0 / False none,
     # 1 / True iMBEA's candidate pruning, 2 the pivot rule
     prune: int = 0
+    # mbe_count only: device memory of the caller (a torch tensor, or an address with
+    # workspace_bytes) that every device buffer of the call is carved from
+    workspace: Any = None
+    workspace_bytes: int = 0
 
 
 class _ServerOptions(ctypes.Structure):
@@ -187,8 +192,13 @@ def _marshal_opts(opt: Optional[Options], on_device: bool) -> _Options:
     if stream is None and on_device:
         import torch
         stream = torch.cuda.current_stream().cuda_stream
+    ws, ws_bytes = opt.workspace, int(opt.workspace_bytes)
+    if ws is not None and not isinstance(ws, int):  # a tensor: its device memory
+        ws_bytes = ws_bytes or int(ws.numel()) * int(ws.element_size())
+        ws = int(ws.data_ptr())
     return _Options(opt.side, opt.wg_waves, opt.grid, int(opt.diagnostics), int(bool(opt.no_validate)),
-                    opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0), int(opt.prune))
+                    opt.steal_k, opt.root_lo, opt.root_hi, ctypes.c_void_p(stream or 0), int(opt.prune),
+                    ctypes.c_void_p(ws or 0), ws_bytes)
 
 
 PHASES = ("root", "light", "check", "expand", "child", "wait")

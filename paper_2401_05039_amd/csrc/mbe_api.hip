@@ -183,10 +183,12 @@ struct Opts {
     int prune;  // section II-C: 1 iMBEA's candidate pruning, 2 the pivot rule
     int64_t root_lo, root_hi;
     hipStream_t stream;
+    char *ws;         // the caller's workspace (mbe_count), or NULL
+    size_t ws_bytes;
 };
 
 Opts read_opts(const mbe_options *o) {
-    Opts r{0, 8, 0, 0, 0, 2, 0, 0, 0, -1, nullptr};
+    Opts r{0, 8, 0, 0, 0, 2, 0, 0, 0, -1, nullptr, nullptr, 0};
     if (!o) return r;
     r.side = o->side;
     r.waves = o->wg_waves > 0 ? o->wg_waves : 8;
@@ -202,6 +204,9 @@ Opts read_opts(const mbe_options *o) {
     r.root_lo = o->root_lo > 0 ? o->root_lo : 0;
     r.root_hi = o->root_hi > 0 ? o->root_hi : -1;
     r.stream = static_cast<hipStream_t>(o->stream);
+    r.ws = static_cast<char *>(o->workspace);
+    r.ws_bytes = (size_t)o->workspace_bytes;
+    if ((r.ws != nullptr) != (r.ws_bytes > 0)) r.side = -1;  // (rejected as an invalid argument)
     return r;
 }
 
@@ -228,6 +233,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         opt.steal_k < 1 || opt.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
     if (enumerate && !ubuf && ucap_ints > 0) return MBE_ERR_INVALID_ARG;
+    if (opt.ws && (fixed || enumerate || ws_out || loads)) return MBE_ERR_INVALID_ARG;  // (mbe_count only)
     const int side = opt.side ? opt.side : (g->n_v < g->n_u ? 2 : 1);
     out->side = (uint32_t)side;
     if (g->n_edges > 0 && (g->n_u == 0 || g->n_v == 0)) return MBE_ERR_INVALID_GRAPH;
@@ -251,7 +257,14 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
     hipStream_t s = opt.stream;
 
     FixedRegion fxr, *fx = nullptr;
-    if (fixed) {
+    if (opt.ws) {
+        // the caller's workspace: every buffer of the call is carved from it
+        const size_t skip = align_up((size_t)(uintptr_t)opt.ws, 256) - (size_t)(uintptr_t)opt.ws;
+        if (skip >= opt.ws_bytes) return MBE_ERR_SCRATCH_LIMIT;
+        fxr.base = opt.ws + skip;
+        fxr.cap = opt.ws_bytes - skip;
+        fx = &fxr;
+    } else if (fixed) {
         if (enumerate || ws_out) return MBE_ERR_INVALID_ARG;
         if (!st->scratch) {
             // set-up, once per device (this device is current): the address of its copy
@@ -825,7 +838,7 @@ int run_batch_on(DeviceState *st, hipStream_t s, const mbe_graph *gs, int32_t n,
 int run_batch(const mbe_graph *gs, int32_t n, const mbe_options *opt_in, mbe_result *outs) {
     if (n < 0 || (n > 0 && (!gs || !outs))) return MBE_ERR_INVALID_ARG;
     const Opts opt = read_opts(opt_in);
-    if (opt.prune) return MBE_ERR_INVALID_ARG;
+    if (opt.prune || opt.ws) return MBE_ERR_INVALID_ARG;
     if (opt.side < 0 || opt.side > 2 || opt.waves < 1 || opt.waves > 8 ||
         opt.steal_k < 1 || opt.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
@@ -1172,10 +1185,12 @@ struct mbe_server {
     // largest local universe needs (the arena is shared by a batch, so only its maximum counts)
     void estimate(ServerRequest &r) const {
         const mbe_graph &g = r.g;
-        const int64_t nc = std::min(g.n_u, g.n_v), no = std::max(g.n_u, g.n_v);
+        // the candidate side the search takes (search.side, else the smaller side)
+        const bool c_is_v = search.side == 2 || (search.side == 0 && g.n_v < g.n_u);
+        const int64_t nc = c_is_v ? g.n_v : g.n_u, no = c_is_v ? g.n_u : g.n_v;
         r.csr_bytes = (size_t)4 * ((size_t)g.n_u + g.n_v + 2 + 2 * (size_t)g.n_edges) + (size_t)48 * nc + 4096;
         int64_t dmax = 0;
-        const int32_t *off = g.n_v < g.n_u ? g.v_off : g.u_off;
+        const int32_t *off = c_is_v ? g.v_off : g.u_off;
         for (int64_t v = 0; v < nc && off; ++v) dmax = std::max<int64_t>(dmax, off[v + 1] - off[v]);
         int64_t W = 1;
         while (64 * W < dmax && W < 16) W *= 2;
@@ -1275,6 +1290,7 @@ int server_create(const mbe_server_options *opt, mbe_server **out) {
         sv->timeout_ms = opt->request_timeout_ms;
     }
     sv->search.root_lo = sv->search.root_hi = 0;
+    if (sv->search.workspace || sv->search.workspace_bytes) return MBE_ERR_INVALID_ARG;
     if (sv->search.wg_waves < 0 || sv->search.wg_waves > 8 || sv->search.side < 0 || sv->search.side > 2 ||
         sv->search.steal_k < 0 || sv->search.steal_k > 3)
         return MBE_ERR_INVALID_ARG;
@@ -1517,7 +1533,7 @@ const char *mbe_strerror(int code) {
         case MBE_ERR_OUT_OF_MEMORY: return "out of device memory";
         case MBE_ERR_DEVICE: return "HIP runtime error";
         case MBE_ERR_UNSUPPORTED: return "unsupported input";
-        case MBE_ERR_SCRATCH_LIMIT: return "the call needs more device memory than the fixed scratch of mbe_count_noalloc";
+        case MBE_ERR_SCRATCH_LIMIT: return "the call needs more device memory than the fixed scratch of mbe_count_noalloc or the caller's workspace";
         case MBE_ERR_TIMEOUT: return "the request passed its deadline";
         case MBE_ERR_CANCELLED: return "the request was cancelled";
         default: return "unknown error";

@@ -148,6 +148,24 @@ def test_server_rejects_bad_deadlines(lib):
     assert so.mbe_server_cancel(None, ctypes.c_uint64(1)) == -1
 
 
+def test_workspace_arguments_checked_before_device_work():
+    import paper_2401_05039_amd as m
+    g = gg.complete(2, 3)
+    for kw in (dict(workspace=0, workspace_bytes=1 << 20), dict(workspace=4096, workspace_bytes=0)):
+        with pytest.raises(m.MbeError) as e:
+            m.mbe_count(g, m.Options(**kw))
+        assert e.value.code == -1
+    ws = dict(workspace=1 << 20, workspace_bytes=1 << 20)  # (never touched: refused first)
+    for call in (lambda: m.mbe_count_batch([g], m.Options(**ws)),
+                 lambda: m.mbe_enumerate(g, m.Options(**ws), cap_ints=64),
+                 lambda: m.mbe_count_noalloc(g, m.Options(**ws)),
+                 lambda: m.mbe_workspace_size(g, m.Options(**ws)),
+                 lambda: m.Server(opt=m.Options(**ws))):
+        with pytest.raises(m.MbeError) as e:
+            call()
+        assert e.value.code == -1
+
+
 def test_batch_totals_past_int32_refused_before_device_work():
     # the same host arrays repeated until the packed edge count passes 2^31 - 1: refused with
     # MBE_ERR_INVALID_ARG by the 64-bit size check, before any packing or device work

@@ -852,3 +852,33 @@ def test_pivot_rejected_where_unsupported(mbe):
         with pytest.raises(mbe.MbeError) as e:
             call()
         assert e.value.code == -1
+
+
+# ----------------------------------------------------------------------------- caller workspace
+
+def test_caller_workspace(mbe, orc):
+    """mbe_count with a workspace of the caller's device memory: the same answers as with the
+    library's buffers, on device and host CSR, wide candidates included, twice in a row with a
+    smaller graph second, at an unaligned start; a workspace too small is refused."""
+    import torch
+    dev = torch.device("cuda:0")
+    ws = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    g2 = gg.config2()
+    dg2 = gg.BiGraph(g2.n_u, g2.n_v, *[torch.from_numpy(np.asarray(a)).to(dev) for a in
+                                       (g2.u_off, g2.u_adj, g2.v_off, g2.v_adj)])
+    want2 = _gold("config2")
+    cases = [(dg2, "power-law (device CSR)", (want2["count"], want2["hash"])),
+             (gg.config1(), "workload1", None), (_wide(0), "wide0", None), (gg.crown(9), "crown9", None)]
+    for g, name, want in cases:
+        _say("workspace", name)
+        if want is None:
+            w = orc.mbea(g)
+            want = (w["count"], w["hash"])
+        for opt in (mbe.Options(workspace=ws), mbe.Options(workspace=ws[3:]),
+                    mbe.Options(workspace=ws, diagnostics=1)):
+            r = mbe.mbe_count(g, opt)
+            assert (r["count"], r["hash"]) == want, name
+    with pytest.raises(mbe.MbeError) as e:
+        mbe.mbe_count(gg.config1(), mbe.Options(workspace=ws[: 64 << 10]))
+    assert e.value.code == mbe.MBE_ERR_SCRATCH_LIMIT
+    torch.cuda.synchronize()
