@@ -24,6 +24,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+
+def _hw_queues() -> str:
+    """Hardware queues for this process (GPU_MAX_HW_QUEUES, read when the GPU is first used).
+    A search runs one persistent kernel per mask-width class, concurrently on streams of their
+    own, and each needs a queue of its own: HIP gives a process 4 by default, and streams
+    beyond that share queues, so two class launches then run one after the other (measured on
+    the power-law step: 38.9 ms with 4 queues, 35.5 ms with 8).  So at least 8, unless
+    --hw-queues says otherwise.  Hardware counters are read per dispatch and count whatever
+    runs meanwhile, so counter runs want one queue (launches one at a time): the traffic
+    children take 1, and so does a run given --hw-queues 1."""
+    if "--traffic-child" in sys.argv:
+        return "1"
+    for i, a in enumerate(sys.argv[:-1]):
+        if a == "--hw-queues":
+            return sys.argv[i + 1]
+    try:
+        cur = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+    except ValueError:
+        cur = 0
+    return str(max(cur, 8))
+
+
+os.environ["GPU_MAX_HW_QUEUES"] = _hw_queues()
+
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 BOX_THREADS = 16       # host threads of one GPU's share of the box
 
@@ -66,9 +90,10 @@ def _counter_rows(out_dir, counter):
 def measure_traffic(args):
     """HBM bytes of one step's search launches, measured: this script runs twice as a child
     under rocprofv3 --pmc (FETCH_SIZE, then WRITE_SIZE), each child making one plain 1 GiB
-    device copy and one production step.  Each counter is scaled by what it reads for the
-    copy (1 GiB read and 1 GiB written).  Runs before this process touches the GPU; returns
-    None when the profiler is missing or its output is incomplete."""
+    device copy and one production step, with one hardware queue so that the class launches
+    run one at a time and each dispatch's counters are its own.  Each counter is scaled by
+    what it reads for the copy (1 GiB read and 1 GiB written).  Runs before this process
+    touches the GPU; returns None when the profiler is missing or its output is incomplete."""
     import shutil
     import subprocess
     import tempfile
@@ -475,6 +500,9 @@ def main():
                     help="power-law line: skip the batched-form figures (--batch-n graphs)")
     ap.add_argument("--no-serve", action="store_true",
                     help="power-law line: skip the serving-form figures (--line-serve-n requests at --line-rate)")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="GPU_MAX_HW_QUEUES for this run (default: at least 8; 1 serialises the class "
+                         "launches, for hardware-counter runs)")
     ap.add_argument("--line-serve-n", type=int, default=100)
     ap.add_argument("--line-rate", type=float, default=4.0)
     args = ap.parse_args()

@@ -17,6 +17,12 @@
  *   - Input arrays are owned by the caller and never written or freed by the library.
  *   - The library allocates device memory for its own working state and keeps it cached per
  *     device between calls.  Calls on one device are serialised by an internal lock.
+ *   - A search runs one persistent kernel per mask-width class of top-level candidates,
+ *     concurrently, on streams the library creates per device (five).  HIP maps a process's
+ *     streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default), and kernels of streams
+ *     that share a queue run one after another: for the concurrent form, set
+ *     GPU_MAX_HW_QUEUES to 8 or more before the process first uses the GPU.  Results never
+ *     depend on it.
  */
 #ifndef MBE_H
 #define MBE_H
