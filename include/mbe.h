@@ -40,11 +40,10 @@ extern "C" {
 #define MBE_ERR_INVALID_GRAPH    -2  /* bad offsets, unsorted/duplicate row, id out of range,
                                         or the two CSR arrays are not transposes */
 #define MBE_ERR_BUFFER_TOO_SMALL -3  /* records did not fit; the mbe_result is still complete */
-#define MBE_ERR_OUT_OF_MEMORY    -4  /* device allocation failed */
+#define MBE_ERR_OUT_OF_MEMORY    -4  /* device allocation failed, or the caller's workspace is too small */
 #define MBE_ERR_DEVICE           -5  /* a HIP runtime call failed */
 #define MBE_ERR_UNSUPPORTED      -6  /* (kept for binary compatibility; no longer returned) */
-#define MBE_ERR_SCRATCH_LIMIT    -7  /* the call does not fit the fixed scratch (mbe_count_noalloc) or the
-                                        caller's workspace (mbe_options.workspace) */
+#define MBE_ERR_SCRATCH_LIMIT    -7  /* mbe_count_noalloc: the call does not fit the fixed scratch */
 #define MBE_ERR_TIMEOUT          -8  /* server: the request passed its deadline (result unspecified) */
 #define MBE_ERR_CANCELLED        -9  /* server: the request was cancelled (result unspecified) */
 
@@ -176,7 +175,7 @@ typedef struct mbe_result {
  *                arena slots that fit.  The caller keeps the memory valid until the call
  *                returns and must not share it with a concurrent call; its contents are
  *                unspecified afterwards.  A call that needs more returns
- *                MBE_ERR_SCRATCH_LIMIT.  NULL: the library's buffers.  A non-NULL workspace
+ *                MBE_ERR_OUT_OF_MEMORY.  NULL: the library's buffers.  A non-NULL workspace
  *                with workspace_bytes 0, a NULL one with workspace_bytes > 0, or a workspace
  *                with mbe_enumerate, mbe_count_noalloc, mbe_count_loads,
  *                mbe_workspace_size, the batched or the served form: MBE_ERR_INVALID_ARG.

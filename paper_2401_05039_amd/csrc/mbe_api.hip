@@ -1476,7 +1476,9 @@ int mbe_tune_batch(const mbe_graph *gs, int32_t n, const mbe_options *base, mbe_
 
 
 int mbe_count(const mbe_graph *g, const mbe_options *opt, mbe_result *out) {
-    return run(g, opt, out, nullptr, 0, 0, false);
+    const int rc = run(g, opt, out, nullptr, 0, 0, false);
+    // a caller's workspace that is too small reads as out of memory
+    return rc == MBE_ERR_SCRATCH_LIMIT && opt && opt->workspace ? MBE_ERR_OUT_OF_MEMORY : rc;
 }
 
 int mbe_count_loads(const mbe_graph *g, const mbe_options *opt, mbe_result *out, uint64_t *rec, int64_t cap_records,
@@ -1530,10 +1532,10 @@ const char *mbe_strerror(int code) {
         case MBE_ERR_INVALID_ARG: return "invalid argument";
         case MBE_ERR_INVALID_GRAPH: return "invalid graph (offsets, row order, id range or transpose mismatch)";
         case MBE_ERR_BUFFER_TOO_SMALL: return "record buffer too small";
-        case MBE_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case MBE_ERR_OUT_OF_MEMORY: return "out of device memory (or the caller's workspace is too small)";
         case MBE_ERR_DEVICE: return "HIP runtime error";
         case MBE_ERR_UNSUPPORTED: return "unsupported input";
-        case MBE_ERR_SCRATCH_LIMIT: return "the call needs more device memory than the fixed scratch of mbe_count_noalloc or the caller's workspace";
+        case MBE_ERR_SCRATCH_LIMIT: return "the call needs more device memory than the fixed scratch of mbe_count_noalloc";
         case MBE_ERR_TIMEOUT: return "the request passed its deadline";
         case MBE_ERR_CANCELLED: return "the request was cancelled";
         default: return "unknown error";

@@ -885,5 +885,5 @@ def test_caller_workspace(mbe, orc):
             assert (r["count"], r["hash"]) == want, name
     with pytest.raises(mbe.MbeError) as e:
         mbe.mbe_count(gg.config1(), mbe.Options(workspace=ws[: 64 << 10]))
-    assert e.value.code == mbe.MBE_ERR_SCRATCH_LIMIT
+    assert e.value.code == mbe.MBE_ERR_OUT_OF_MEMORY
     torch.cuda.synchronize()
