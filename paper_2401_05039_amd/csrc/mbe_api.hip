@@ -1154,6 +1154,7 @@ struct mbe_server {
                     break;
                 }
             r->rc = why;
+            r->result.status = why;
             r->finish = Clock::now();
             r->done = true;
             std::vector<int32_t>().swap(r->u_adj);
@@ -1276,6 +1277,20 @@ struct mbe_server {
 
 namespace {
 
+// Free the slots' device state, streams and cancel words (no worker is running).
+void release_slots(mbe_server *sv) {
+    for (DeviceState *st : sv->states) {
+        free_state(st);
+        delete st;
+    }
+    for (hipStream_t strm : sv->streams) (void)hipStreamDestroy(strm);
+    for (unsigned int *cw : sv->cancel) (void)hipHostFree(cw);
+    sv->states.clear();
+    sv->streams.clear();
+    sv->cancel.clear();
+    sv->cancel_dev.clear();
+}
+
 int server_create(const mbe_server_options *opt, mbe_server **out) {
     if (!out) return MBE_ERR_INVALID_ARG;
     *out = nullptr;
@@ -1306,25 +1321,36 @@ int server_create(const mbe_server_options *opt, mbe_server **out) {
     sv->slot_budget = budget / (size_t)slots;
     sv->nslots = slots;
     for (int k = 0; k < slots; ++k) {
+        // (on a failure, what the slots made so far is released)
         DeviceState *st = new DeviceState();
-        if (hipEventCreate(&st->ev0) != hipSuccess || hipEventCreate(&st->ev1) != hipSuccess) {
-            delete st;
-            return MBE_ERR_DEVICE;
-        }
         st->cus = sv->cus;
         sv->states.push_back(st);
+        if (hipEventCreate(&st->ev0) != hipSuccess || hipEventCreate(&st->ev1) != hipSuccess) {
+            release_slots(sv.get());
+            return MBE_ERR_DEVICE;
+        }
         hipStream_t strm = nullptr;
-        MBE_TRY(hipStreamCreateWithFlags(&strm, hipStreamNonBlocking));
+        hipError_t e = hipStreamCreateWithFlags(&strm, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            release_slots(sv.get());
+            return map_err(e);
+        }
         sv->streams.push_back(strm);
         // cancel words: fine-grained pinned host memory, which a running kernel reads
         void *cw = nullptr;
-        if (hipHostMalloc(&cw, (size_t)sv->max_batch * sizeof(unsigned int), hipHostMallocCoherent | hipHostMallocMapped) !=
-            hipSuccess)
+        e = hipHostMalloc(&cw, (size_t)sv->max_batch * sizeof(unsigned int), hipHostMallocCoherent | hipHostMallocMapped);
+        if (e != hipSuccess) {
+            release_slots(sv.get());
             return MBE_ERR_OUT_OF_MEMORY;
+        }
         std::memset(cw, 0, (size_t)sv->max_batch * sizeof(unsigned int));
         sv->cancel.push_back(static_cast<unsigned int *>(cw));
         void *cwd = nullptr;
-        MBE_TRY(hipHostGetDevicePointer(&cwd, cw, 0));
+        e = hipHostGetDevicePointer(&cwd, cw, 0);
+        if (e != hipSuccess) {
+            release_slots(sv.get());
+            return map_err(e);
+        }
         sv->cancel_dev.push_back(static_cast<unsigned int *>(cwd));
     }
     mbe_server *raw = sv.get();
@@ -1421,13 +1447,8 @@ int mbe_server_destroy(mbe_server *sv) {
     sv->cv_deadline.notify_all();
     for (auto &t : sv->workers) t.join();
     if (sv->watchdog.joinable()) sv->watchdog.join();
-    for (size_t k = 0; k < sv->states.size(); ++k) {
-        (void)hipStreamSynchronize(sv->streams[k]);
-        free_state(sv->states[k]);
-        delete sv->states[k];
-        (void)hipStreamDestroy(sv->streams[k]);
-    }
-    for (unsigned int *cw : sv->cancel) (void)hipHostFree(cw);
+    for (hipStream_t strm : sv->streams) (void)hipStreamSynchronize(strm);
+    release_slots(sv);
     delete sv;
     return MBE_OK;
 }
