@@ -609,8 +609,19 @@ def main():
         # the paper's reverse-scanning method would move bytes_alg for the same tree; this
         # design never performs those scans, so the rate is an effective one, not traffic
         "paper_method_rate": {"bytes_alg": diag["bytes_alg"], "gbs": diag["bytes_alg"] / (kavg / 1000.0) / 1e9},
+        "search_ms_median": sorted(kms)[len(kms) // 2],
         "phase_share": phase_share,
     }
+    # end to end from host arrays: validation on the host, the upload of the CSR (PCIe), the
+    # preparation, the search and the result (the line's value starts from device arrays)
+    mbe.mbe_count(g, opt)
+    e2e = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        r = mbe.mbe_count(g, opt)
+        e2e.append((time.perf_counter() - t1) * 1000.0)
+        assert (r["count"], r["hash"]) == (diag["count"], diag["hash"])
+    out["host_csr_end_to_end_ms"] = sorted(e2e)[1]
     out["steal_ablation"] = steal_ablation(mbe, dg, rng_range)
     log("prune study")
     out["prune_study"] = prune_study(mbe, dg, rng_range, diag)
