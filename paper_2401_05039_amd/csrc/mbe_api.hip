@@ -144,26 +144,35 @@ int map_err(hipError_t e) {
         if (_r != MBE_OK) return _r;                   \
     } while (0)
 
-// Host-side check of one CSR direction against its transpose (same rules as the device
-// validator): offsets start at 0, never decrease and end at n_edges; rows strictly ascend
-// with ids in range; every (r, c) appears as (c, r) in the other direction.
-bool host_valid(int32_t n_rows, int32_t n_cols, int32_t n_edges, const int32_t *off, const int32_t *adj,
-                const int32_t *t_off, const int32_t *t_adj) {
-    if (off[0] != 0 || off[n_rows] != n_edges) return false;
-    for (int32_t r = 0; r < n_rows; ++r) {
-        const int32_t b = off[r], e = off[r + 1];
-        if (b > e || b < 0 || e > n_edges) return false;
+// Host-side check of a CSR pair (the same rules as the device validator): both offset arrays
+// start at 0, never decrease and end at n_edges; the U rows strictly ascend with V ids in
+// range; and the V side is exactly their transpose.  One pass in U-row order keeps a cursor
+// per V row: the entry (r, c) must be the next entry of V row c, so each V row is consumed in
+// ascending r (which also makes the V rows sorted, duplicate-free and in range), and every
+// V row must be consumed to its end.  O(|E|).
+bool host_valid_pair(int32_t n_u, int32_t n_v, int32_t n_edges, const int32_t *u_off, const int32_t *u_adj,
+                     const int32_t *v_off, const int32_t *v_adj) {
+    auto offsets_ok = [&](int32_t n, const int32_t *off) {
+        if (off[0] != 0 || off[n] != n_edges) return false;
+        for (int32_t r = 0; r < n; ++r)
+            if (off[r] > off[r + 1]) return false;
+        return true;
+    };
+    if (!offsets_ok(n_u, u_off) || !offsets_ok(n_v, v_off)) return false;
+    std::vector<int32_t> cur(v_off, v_off + n_v);
+    for (int32_t r = 0; r < n_u; ++r) {
         int32_t prev = -1;
-        for (int32_t p = b; p < e; ++p) {
-            const int32_t c = adj[p];
-            if (c <= prev || c >= n_cols) return false;
+        for (int32_t p = u_off[r]; p < u_off[r + 1]; ++p) {
+            const int32_t c = u_adj[p];
+            if (c <= prev || c >= n_v) return false;
             prev = c;
-            const int32_t *lo = t_adj + t_off[c], *hi = t_adj + t_off[c + 1];
-            if (t_off[c] < 0 || t_off[c + 1] > n_edges || t_off[c] > t_off[c + 1]) return false;
-            const int32_t *it = std::lower_bound(lo, hi, r);
-            if (it == hi || *it != r) return false;
+            const int32_t q = cur[c];
+            if (q >= v_off[c + 1] || v_adj[q] != r) return false;
+            cur[c] = q + 1;
         }
     }
+    for (int32_t c = 0; c < n_v; ++c)
+        if (cur[c] != v_off[c + 1]) return false;
     return true;
 }
 
@@ -242,8 +251,7 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
         // host arrays: check before any device work
         if ((g->n_u > 0 && !g->u_off) || (g->n_v > 0 && !g->v_off)) return MBE_ERR_INVALID_ARG;
         if (g->n_edges > 0 || (g->u_off && g->v_off)) {
-            if (!host_valid(g->n_u, g->n_v, g->n_edges, g->u_off, g->u_adj, g->v_off, g->v_adj) ||
-                !host_valid(g->n_v, g->n_u, g->n_edges, g->v_off, g->v_adj, g->u_off, g->u_adj))
+            if (!host_valid_pair(g->n_u, g->n_v, g->n_edges, g->u_off, g->u_adj, g->v_off, g->v_adj))
                 return MBE_ERR_INVALID_GRAPH;
         }
     }
@@ -803,8 +811,7 @@ int check_graphs(const mbe_graph *gs, int32_t n, bool validate) {
         if ((g.n_u > 0 && !g.u_off) || (g.n_v > 0 && !g.v_off) || (g.n_edges > 0 && (!g.u_adj || !g.v_adj)))
             return MBE_ERR_INVALID_ARG;
         if (validate && g.u_off && g.v_off &&
-            (!host_valid(g.n_u, g.n_v, g.n_edges, g.u_off, g.u_adj, g.v_off, g.v_adj) ||
-             !host_valid(g.n_v, g.n_u, g.n_edges, g.v_off, g.v_adj, g.u_off, g.u_adj)))
+            !host_valid_pair(g.n_u, g.n_v, g.n_edges, g.u_off, g.u_adj, g.v_off, g.v_adj))
             return MBE_ERR_INVALID_GRAPH;
     }
     return MBE_OK;

@@ -74,6 +74,32 @@ def test_invalid_graphs_rejected_on_host():
     assert _bad(_mk(2, 3, good.u_off, good.u_adj, [0, 2, 4, 5], [0, 1, 0, 1, 0])) == -2
 
 
+def test_host_validation_transpose_rules():
+    """The host check accepts exactly the CSR pairs whose V side is the transpose of the U side
+    with sorted rows: a V row with its entries out of order, an entry moved to another V row
+    (the counts of the sides still agree), or V offsets that decrease are refused; valid
+    random graphs pass the check (the call then needs a device, so on a machine without one it
+    fails later, with MBE_ERR_DEVICE, not MBE_ERR_INVALID_GRAPH)."""
+    import paper_2401_05039_amd as m
+    good = gg.complete(2, 3)  # N(u0) = N(u1) = {0, 1, 2}; V rows [0, 1] each
+    # V row 0 holds its entries in the wrong order
+    assert _bad(_mk(2, 3, good.u_off, good.u_adj, [0, 2, 4, 6], [1, 0, 0, 1, 0, 1])) == -2
+    # u0-v2 missing from V row 2, u1 listed twice: same count, not the transpose
+    assert _bad(_mk(2, 3, good.u_off, good.u_adj, [0, 2, 4, 6], [0, 1, 0, 1, 1, 1])) == -2
+    # an entry moved from V row 2 to V row 0 (offsets adjusted)
+    assert _bad(_mk(2, 3, good.u_off, good.u_adj, [0, 3, 5, 6], [0, 1, 1, 0, 1, 1])) == -2
+    # V offsets that decrease
+    assert _bad(_mk(2, 3, good.u_off, good.u_adj, [0, 4, 2, 6], [0, 1, 0, 1, 0, 1])) == -2
+    for s in range(20):
+        g = gg.random_small(9, 13, 0.4, 300 + s)
+        if g.n_edges == 0:
+            continue
+        try:
+            m.mbe_count(g)
+        except m.MbeError as e:
+            assert e.code != -2, g.name
+
+
 def test_bad_options_rejected():
     g = gg.complete(2, 2)
     assert _bad(g, side=3) == -1
