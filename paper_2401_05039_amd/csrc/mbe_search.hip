@@ -235,6 +235,7 @@ struct FrameView {
     uint32_t *cnt;
     uint64_t *H;
     uint32_t *orig;
+    uint64_t *hR;  // (narrow frames) the R-side hash term of each bit: hvl[orig[b]]
     uint64_t *rows;
     int nw;
 };
@@ -247,6 +248,7 @@ __device__ __forceinline__ uint32_t frame_words_fixed(int n, int wf, int rbits) 
     o += 2u * bits;                        // first, cnt
     o += 2u * bits;                        // H
     o += 64u;                              // orig
+    o += 128u;                             // hR
     o += 2u * (uint32_t)rbits * nw;        // rows
     return o;
 }
@@ -269,6 +271,8 @@ __device__ __forceinline__ FrameView frame_view(uint32_t *base, int n, int wf, i
     o += 2u * bits;
     v.orig = base + o;
     o += 64u;
+    v.hR = reinterpret_cast<uint64_t *>(base + o);
+    o += 128u;
     v.rows = reinterpret_cast<uint64_t *>(base + o);
     return v;
 }
@@ -340,6 +344,12 @@ __device__ __forceinline__ uint32_t *frame_base(const Ctx &c, uint32_t off) { re
 
 __device__ __forceinline__ uint32_t root_pos(const FrameState &F, const FrameView &v, uint32_t b) {
     return F.narrow ? v.orig[b] : b;
+}
+
+// The R-side hash term of frame bit b: narrow frames keep it per bit (hR), other frames'
+// bits are positions of N(x) already.
+__device__ __forceinline__ uint64_t root_hash(const Ctx &c, const FrameState &F, const FrameView &v, uint32_t b) {
+    return F.narrow ? v.hR[b] : c.hvl[b];
 }
 __device__ __forceinline__ uint64_t deg_of(const Ctx &c, uint32_t li) {
     const int32_t g = c.gid[li];
@@ -539,7 +549,7 @@ __device__ __forceinline__ uint64_t light_chunk(const Ctx &c, const FrameState &
             // L' = L u {every entry with bit b}: all of them sit at positions >= i
             const uint64_t sL = F.sL + v.H[b];
             acc.count += 1;
-            acc.hash += pair_hash(c.c_is_v, sL, c.hvl[rp]);
+            acc.hash += pair_hash(c.c_is_v, sL, root_hash(c, F, v, (uint32_t)b));
             acc.out_ints += 2ull + (uint64_t)F.nL + (uint64_t)v.cnt[b] + 1ull;
         }
         if (DIAG) {
@@ -552,7 +562,7 @@ __device__ __forceinline__ uint64_t light_chunk(const Ctx &c, const FrameState &
             acc.bytes += 4ull * ((2ull + dx) + (rs < fw ? rs : fw) + (uint64_t)(F.n - 1) + 1ull);
         }
         // first[b]; for a maximal node H[b], cnt[b], the R-side hash term (and orig[b])
-        if (TB) acc.dbytes += 4ull + (maximal ? 20ull + (F.narrow ? 4ull : 0ull) : 0ull);
+        if (TB) acc.dbytes += 4ull + (maximal ? 20ull : 0ull);
     }
     if (TB && act && settle) acc.dbytes += 8ull * WF;  // the entry's mask
     return __ballot(act && r >= 2);
@@ -724,7 +734,11 @@ __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, c
         for (int w = 0; w < WF; ++w) {
             const bool on = (m[w] >> ln) & 1ull;
             const uint64_t bb = __ballot(on);
-            if (on) v2.orig[t0 + __popcll(bb & below)] = root_pos(F, v, (uint32_t)(64 * w + ln));
+            if (on) {
+                const int at = t0 + __popcll(bb & below);
+                v2.orig[at] = root_pos(F, v, (uint32_t)(64 * w + ln));
+                v2.hR[at] = root_hash(c, F, v, (uint32_t)(64 * w + ln));
+            }
             t0 += __popcll(bb);
         }
         narrow_table_clear(c);
@@ -821,7 +835,8 @@ __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, c
         uint64_t b = nloop * (4ull + 8ull * (uint64_t)wf2) + 16ull * (uint64_t)pn;  // stu; child masks; hs in and out
         if (preq < 0) b += nloop * 8ull * (uint64_t)nzw;                           // the entries' masks over R'
         if (NARROW) {
-            b += 8ull * (uint64_t)(pruned ? nq2 : 0) + 4ull * (uint64_t)r * (F.narrow ? 2ull : 1ull);  // kept Q'; orig
+            b += 8ull * (uint64_t)(pruned ? nq2 : 0) + 4ull * (uint64_t)r * (F.narrow ? 2ull : 1ull) +  // kept Q'; orig
+                 16ull * (uint64_t)r;                                                                    // hR
             b += 16ull * (uint64_t)r + 8ull * (uint64_t)n2 + 8ull * (uint64_t)r * (uint64_t)v2.nw;   // tables; rows
         } else {
             // tables cleared, each entry's hash term and mask words read, its bits' table atomics
@@ -1105,7 +1120,7 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
         for (int w = 0; w < WF; ++w) nzw += m[w] ? 1 : 0;
         uint64_t b = 8ull * (uint64_t)r * (uint64_t)v.nw + 8ull * (uint64_t)ne + 4ull * (uint64_t)nu;
         if (!fastq) b += (uint64_t)pn * (4ull + 8ull * (uint64_t)nzw);
-        b += (uint64_t)r * (8ull + (F.narrow ? 4ull : 0ull));
+        b += (uint64_t)r * 8ull;
         acc.dbytes += b;
     }
 
@@ -1114,7 +1129,7 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
     uint64_t sr = 0;
 #pragma unroll
     for (int w = 0; w < WF; ++w)
-        if ((m[w] >> ln) & 1ull) sr += c.hvl[root_pos(F, v, (uint32_t)(64 * w + ln))];
+        if ((m[w] >> ln) & 1ull) sr += root_hash(c, F, v, (uint32_t)(64 * w + ln));
     sr = wave_sum_u64(sr);
     const int nL = F.nL + 1 + ne;
     if (ln == 0 && report) {
@@ -3582,7 +3597,7 @@ ArenaLayout search_layout(const SearchDims &d) {
     L.off_t1v = take(ucap * 4);
     L.off_t1c = take(ucap * 4);
     // ids | hs | masks | first, cnt | H | orig | rows (see frame_view)
-    L.s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 2 * bits + 2 * bits + 64 + 2 * bits * ((ucap + 63) / 64) + 2;
+    L.s1_words = align_up(ucap, 2) + 2 * ucap + 2 * ucap * W + 2 * bits + 2 * bits + 64 + 128 + 2 * bits * ((ucap + 63) / 64) + 2;
     L.off_S1 = take(L.s1_words * 4);
     L.off_hb = take((ucap / 64 + 1) * 8);
     L.off_hpre = take((ucap / 64 + 2) * 4);
