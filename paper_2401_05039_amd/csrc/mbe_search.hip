@@ -57,7 +57,10 @@ constexpr int kQKeep = 256;      // most incomparable Q' masks a compressed chil
 // of scalar registers with it)
 template <int W>
 constexpr bool kSmallRPrune = W <= 4;
-constexpr int kWaveLds = 1024 + 8 * kQKeep;  // LDS bytes per wave besides the histogram
+// A maximal node's listed entries (stu) stay in the wave's LDS for lists of at most this many
+// entries, in global scratch for longer ones.
+constexpr int kStuLds = 256;
+constexpr int kWaveLds = 1024 + 8 * kQKeep + 4 * kStuLds;  // LDS bytes per wave besides the histogram
 
 // LDS after the workgroup header: the waves' histograms (4 bytes per bit each), which the
 // top-level list build reuses for its tables (16 bytes per bit), hence at least that much.
@@ -310,6 +313,7 @@ struct Ctx {
     uint32_t *s1;                     // the workgroup's top-level list frame
     uint32_t *stk;                    // this wave's stack
     uint32_t *stu;                    // a maximal node's Q' and P' positions in list order
+    uint32_t *stu_l;                  // the same in this wave's LDS (lists of at most kStuLds entries)
     lds_u32 *tl_first, *tl_cnt;       // this wave's LDS tables for narrow children
     lds_u64 *tl_H;
     lds_u64 *qk;                      // this wave's LDS list of kept Q' masks (kQKeep)
@@ -602,7 +606,8 @@ __device__ __forceinline__ uint64_t compress_mask(const FrameView &v, const uint
 // incomparable (then nothing is dropped).  Cost per chunk of 64 entries: one pass over the
 // kept masks, and one over the chunk's candidates.
 template <int WF, bool SMALL_R>
-__device__ __forceinline__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn, int r) {
+__device__ __forceinline__ int prune_q(const Ctx &c, const FrameView &v, const uint64_t (&m)[WF], int qn, int r,
+                                       const uint32_t *stu) {
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     if (SMALL_R && r <= 6) {
@@ -612,7 +617,7 @@ __device__ __forceinline__ int prune_q(const Ctx &c, const FrameView &v, const u
         uint64_t pres = 0;
         for (int base = 0; base < qn; base += 64) {
             const int j = base + ln;
-            if (j < qn) pres |= 1ull << compress_mask<WF>(v, m, (int)c.stu[j]);
+            if (j < qn) pres |= 1ull << compress_mask<WF>(v, m, (int)stu[j]);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) pres |= __shfl_xor(pres, o);
@@ -638,7 +643,7 @@ __device__ __forceinline__ int prune_q(const Ctx &c, const FrameView &v, const u
     for (int base = 0; base < qn; base += 64) {
         const int j = base + ln;
         const bool act = j < qn;
-        const uint64_t x = act ? compress_mask<WF>(v, m, (int)c.stu[j]) : 0ull;
+        const uint64_t x = act ? compress_mask<WF>(v, m, (int)stu[j]) : 0ull;
         bool cand = act;
         for (int t = 0; t < nk; ++t) {
             const uint64_t y = c.qk[t];  // same address on every lane
@@ -688,7 +693,9 @@ __device__ __forceinline__ int prune_q(const Ctx &c, const FrameView &v, const u
 // layout fields of C; false when the stack is full.
 template <int WF, int W, bool NARROW, bool DIAG, bool TB = false>
 __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, const FrameView &v, const uint64_t (&m)[WF], int nu,
-                            int r, int qn, int pn, FrameState &C, int preq, WaveAcc &acc, bool tally) {
+                            int r, int qn, int pn, FrameState &C, int preq, WaveAcc &acc, bool tally,
+                            const uint32_t *stu) {
+    const bool stu_g = stu == c.stu;  // (design bytes: the listed entries are global only then)
     const int ln = lane_id();
     const uint64_t below = lanes_below();
     int nzw = 0;  // words of R' (the mask words an entry's gathers read)
@@ -705,8 +712,8 @@ __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, c
         pruned = true;
     } else if constexpr (NARROW && !DIAG) {
         if (qn > 1) {
-            const int nk = prune_q<WF, kSmallRPrune<W>>(c, v, m, qn, r);
-            if (TB && tally && ln == 0) acc.dbytes += (uint64_t)qn * (4ull + 8ull * (uint64_t)nzw);  // stu, masks
+            const int nk = prune_q<WF, kSmallRPrune<W>>(c, v, m, qn, r, stu);
+            if (TB && tally && ln == 0) acc.dbytes += (uint64_t)qn * ((stu_g ? 4ull : 0ull) + 8ull * (uint64_t)nzw);  // stu, masks
             if (nk >= 0) {
                 nq2 = nk;
                 pruned = true;
@@ -764,7 +771,7 @@ __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, c
     for (int base = pruned ? qn : 0; base < nu; base += 64) {
         const int j = base + ln;
         const bool act = j < nu;
-        const uint32_t e = act ? c.stu[j] : 0u;
+        const uint32_t e = act ? stu[j] : 0u;
         const int k = preq >= 0 ? (int)(e & 0x3FFFFFFu) : (int)e;
         uint64_t x[WF];
         int cnt = 0;
@@ -832,7 +839,7 @@ __device__ __forceinline__ bool build_child(const Ctx &c, const FrameState &F, c
     wait_mem();
     if (TB && tally && ln == 0) {
         const uint64_t nloop = (uint64_t)(nu - (pruned ? qn : 0));
-        uint64_t b = nloop * (4ull + 8ull * (uint64_t)wf2) + 16ull * (uint64_t)pn;  // stu; child masks; hs in and out
+        uint64_t b = nloop * ((stu_g ? 4ull : 0ull) + 8ull * (uint64_t)wf2) + 16ull * (uint64_t)pn;  // stu; child masks; hs in and out
         if (preq < 0) b += nloop * 8ull * (uint64_t)nzw;                           // the entries' masks over R'
         if (NARROW) {
             b += 8ull * (uint64_t)(pruned ? nq2 : 0) + 4ull * (uint64_t)r * (F.narrow ? 2ull : 1ull) +  // kept Q'; orig
@@ -981,6 +988,8 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
     // maximal masks through the presence word (as in prune_q) and only P' is listed, each
     // stu word packing the position (low 26 bits) with the compressed mask.
     int qn = 0, nu = 0;
+    // the listed entries (at most F.n - 1): in the wave's LDS when they fit
+    uint32_t *const stu = F.n <= kStuLds ? c.stu_l : c.stu;
     int ne_l = 0, qn_l = 0;
     uint64_t exps = 0, fwc = 0;
     // (the two-word class takes it on its own two-word lists only: register budget)
@@ -1037,7 +1046,7 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
                 const int b = __ffsll((unsigned long long)pm) - 1;
                 pm &= pm - 1ull;
                 const uint32_t cm = cmask(b);
-                c.stu[at++] = (uint32_t)(64 * wd + b) | (cm << 26);
+                stu[at++] = (uint32_t)(64 * wd + b) | (cm << 26);
                 lds_add32(&c.hist[__popc(cm)], 1u);
             }
             nu += last_lane(incl);
@@ -1086,7 +1095,7 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
             while (qp) {
                 const int b = __ffsll((unsigned long long)qp) - 1;
                 qp &= qp - 1ull;
-                c.stu[at++] = (uint32_t)(64 * wd + b);
+                stu[at++] = (uint32_t)(64 * wd + b);
             }
             nu += last_lane(incl);
         }
@@ -1097,7 +1106,7 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
         for (int base = DIAG ? 0 : qn; base < nu; base += 64) {
             const int j = base + ln;
             if (j < nu) {
-                const int k = (int)c.stu[j];
+                const int k = (int)stu[j];
                 if (j >= qn) {
                     int cnt = 0;
 #pragma unroll
@@ -1118,8 +1127,9 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
         int nzw = 0;
 #pragma unroll
         for (int w = 0; w < WF; ++w) nzw += m[w] ? 1 : 0;
-        uint64_t b = 8ull * (uint64_t)r * (uint64_t)v.nw + 8ull * (uint64_t)ne + 4ull * (uint64_t)nu;
-        if (!fastq) b += (uint64_t)pn * (4ull + 8ull * (uint64_t)nzw);
+        const uint64_t sb = stu == c.stu ? 4ull : 0ull;  // (listed entries in global scratch)
+        uint64_t b = 8ull * (uint64_t)r * (uint64_t)v.nw + 8ull * (uint64_t)ne + sb * (uint64_t)nu;
+        if (!fastq) b += (uint64_t)pn * (sb + 8ull * (uint64_t)nzw);
         b += (uint64_t)r * 8ull;
         acc.dbytes += b;
     }
@@ -1168,10 +1178,10 @@ __device__ __forceinline__ bool heavy_node(const Ctx &c, const FrameState &F, co
     // |R'| <= 64, compressed to |R'| bits
     bool ok;
     if constexpr (WF == 1) {
-        ok = build_child<1, W, true, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report);
+        ok = build_child<1, W, true, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report, stu);
     } else {
-        ok = r <= 64 ? build_child<WF, W, true, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report)
-                     : build_child<WF, W, false, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report);
+        ok = r <= 64 ? build_child<WF, W, true, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report, stu)
+                     : build_child<WF, W, false, DIAG, TB>(c, F, v, m, nu, r, qn, pn, C, preq, acc, report, stu);
     }
     if (!ok) return false;
     C.level = F.level + 1;
@@ -1481,6 +1491,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
         c.tl_cnt = c.tl_first + 64;
         c.tl_H = lds_at<lds_u64>(lds_raw, tb + 512);
         c.qk = lds_at<lds_u64>(lds_raw, tb + 1024);
+        c.stu_l = reinterpret_cast<uint32_t *>(lds_raw + tb + 1024 + 8 * kQKeep);
     }
     c.scap = a.dims.scap;
     c.c_is_v = 0;
