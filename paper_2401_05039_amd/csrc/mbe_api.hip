@@ -540,12 +540,12 @@ int run(const mbe_graph *g, const mbe_options *opt_in, mbe_result *out, int32_t 
 // once or than the launches have workgroups; one class at a time, the largest of each class's
 // grid and residency.  cls_grid / cls_res receive each class's grid and residency.
 int search_slots(DeviceState *st, const int64_t *cls_lo, const int64_t *cls_hi, bool diag, bool enumerate, int grid,
-                 int waves, bool sequential, int *cls_grid, int *cls_res) {
+                 int waves, int nwords, bool sequential, int *cls_grid, int *cls_res) {
     int64_t cap = 1, sum_grid = 0;
     for (int c = 0; c < 5; ++c) {
         cls_grid[c] = cls_res[c] = 0;
         if (cls_lo[c] >= cls_hi[c]) continue;
-        cls_res[c] = st->cus * search_occupancy(1 << c, diag, enumerate, waves);
+        cls_res[c] = st->cus * search_occupancy(1 << c, diag, enumerate, waves, nwords);
         cls_grid[c] = grid > 0 ? grid : cls_res[c];
         cap = std::max<int64_t>(cap, cls_res[c]);
         sum_grid += cls_grid[c];
@@ -580,7 +580,7 @@ size_t search_footprint(DeviceState *st, SearchDims dims, const int64_t *cls_lo,
     dims.scap = std::max<int64_t>(dims.scap, st->scap_floor);
     dims.maxdepth = std::max<int32_t>(dims.maxdepth, st->depth_floor);
     int cls_grid[5], cls_res[5];
-    const size_t nslots = (size_t)search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, false, cls_grid, cls_res);
+    const size_t nslots = (size_t)search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, dims.nwords, false, cls_grid, cls_res);
     size_t bytes = search_layout(dims).wg_bytes * nslots + sizeof(unsigned int) * nslots + sizeof(StealSlot) * nslots * 5 +
                    sizeof(PubSlot) * nslots * (size_t)waves * 5;
     if (wr.lo < wr.hi) {
@@ -617,7 +617,7 @@ int run_search(DeviceState *st, SearchArgs &a, SearchDims dims, const int64_t *c
     bool sequential = fx != nullptr;
     const size_t mark = fx ? fx->used : 0;
     for (int attempt = 0;; ++attempt) {
-        int nslots = search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, sequential, cls_grid, cls_res);
+        int nslots = search_slots(st, cls_lo, cls_hi, diag, enumerate, grid, waves, dims.nwords, sequential, cls_grid, cls_res);
         a.dims = dims;
         a.lay = search_layout(dims);
         // per arena slot: its busy flag, and per class one top-level and `waves` third-level

@@ -210,8 +210,9 @@ struct SearchArgs {
 // Arena layout for the given capacities (host side).
 ArenaLayout search_layout(const SearchDims &d);
 
-// Workgroups of one search launch that fit on a compute unit at once.
-int search_occupancy(int W, bool diag, bool enumerate, int waves);
+// Workgroups of one search launch that fit on a compute unit at once (nwords: words of the
+// launch's rank bitmap, which small graphs keep in LDS).
+int search_occupancy(int W, bool diag, bool enumerate, int waves, int nwords);
 
 // Launch the search over tasks [lo, hi) of the work list (or ranks [lo, hi) of graph 0 when
 // it is NULL), all of whose top-level candidates have degree at most 64*W.  counter must be

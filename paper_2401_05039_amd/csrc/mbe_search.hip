@@ -61,6 +61,13 @@ constexpr bool kSmallRPrune = W <= 4;
 // entries, in global scratch for longer ones.
 constexpr int kStuLds = 256;
 constexpr int kWaveLds = 1024 + 8 * kQKeep + 4 * kStuLds;  // LDS bytes per wave besides the histogram
+// The fixed-width classes keep a graph's rank bitmap and its popcount prefix in LDS, after the
+// waves' regions, when the bitmap has at most this many words (131,072 candidates); larger
+// graphs keep them in the workgroup's arena slot.
+constexpr int kRankLdsWords = 2048;
+__host__ __device__ constexpr size_t rank_lds_bytes(int nwords) {
+    return nwords <= kRankLdsWords ? ((size_t)nwords * 12 + 4 + 15) / 16 * 16 : 0;
+}
 
 // LDS after the workgroup header: the waves' histograms (4 bytes per bit each), which the
 // top-level list build reuses for its tables (16 bytes per bit), hence at least that much.
@@ -183,6 +190,13 @@ __device__ __forceinline__ void lds_max(void *p, uint64_t v) {
 }
 __device__ __forceinline__ void lds_or(void *p, uint64_t v) {
     __hip_atomic_fetch_or((lds_u64 *)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// Set bits of a rank-bitmap word, in the workgroup's arena slot or in LDS.
+__device__ __forceinline__ void bm_or(uint64_t *p, uint64_t v) {
+    atomicOr(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+__device__ __forceinline__ void bm_or(lds_u64 *p, uint64_t v) {
+    __hip_atomic_fetch_or(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // ------------------------------------------------------------------------------ frames
@@ -1302,7 +1316,8 @@ __device__ __forceinline__ int claim_chunk(unsigned long long *word, unsigned in
 // Block-wide exclusive prefix of popcounts over nwords bitmap words into bpre; total in
 // sh->s0.  All threads call it; on return every thread sees all of bpre (a thread writes a
 // run of ceil(nwords / threads) entries, so callers read entries other threads wrote).
-__device__ __forceinline__ void block_popcount_prefix(const uint64_t *bitmap, uint32_t *bpre, int nwords, WGShared *sh) {
+template <typename BM, typename BP>  // global or LDS words
+__device__ __forceinline__ void block_popcount_prefix(const BM *bitmap, BP *bpre, int nwords, WGShared *sh) {
     const int tid = threadIdx.x, nt = blockDim.x, wid = tid >> 6, nw = nt >> 6;
     const int per = (nwords + nt - 1) / nt;
     const int b0 = tid * per;
@@ -1425,9 +1440,10 @@ __device__ __forceinline__ bool find_shared_list(const SearchArgs &a, WGShared *
 }
 
 // The classes of up to eight mask words keep four waves per SIMD resident (two 8-wave
-// workgroups per compute unit): their register budget is capped at 128.  For two to eight
-// words that spills some state to scratch (about 300 bytes per lane), and still measured
-// faster than 203-234 registers at two waves per SIMD: power-law step 47.8 -> 39.1 ms,
+// workgroups per compute unit): their register budget is capped at 128.  That spills some
+// state to scratch (up to about 90 bytes per lane in the production instances, several
+// hundred in the diagnostics instances), and still measured faster than 203-234 registers at
+// two waves per SIMD: power-law step 47.8 -> 39.1 ms,
 // skewed sample 1.76 -> 1.27 s.  The search waits on memory latency, and more resident waves
 // hide it.
 // TB (with DIAG and ENUM off): the production search, also tallying its design bytes.
@@ -1493,6 +1509,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
         c.qk = lds_at<lds_u64>(lds_raw, tb + 1024);
         c.stu_l = reinterpret_cast<uint32_t *>(lds_raw + tb + 1024 + 8 * kQKeep);
     }
+    // the rank bitmap and its prefix: in LDS when the launch's graphs are small enough
+    const bool rl = a.dims.nwords <= kRankLdsWords;
+    lds_u64 *const lbm = lds_at<lds_u64>(lds_raw, sizeof(WGShared) + hist_region_bytes(BITS, nw) + (size_t)nw * kWaveLds);
+    lds_u32 *const lbp = reinterpret_cast<lds_u32 *>(lbm + (rl ? a.dims.nwords : 0));
+    auto with_rank = [&](auto &&f) {
+        if (rl) f(lbm, lbp);
+        else f(bitmap, bpre);
+    };
+    if (rl)
+        for (int wd = tid; wd < a.dims.nwords; wd += nt) lbm[wd] = 0ull;
     c.scap = a.dims.scap;
     c.c_is_v = 0;
     c.cbase = 0;
@@ -1734,28 +1760,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
         };
 
         // -- reverse scan 1: mark the ranks of all 2-hop neighbours of x
-        if constexpr (kFlatWalk) {
-            for (int t = tid; t < walk; t += nt) {
-                int j;
-                const int32_t v = walk_at(t, j);
-                if (v != x) {
-                    const int32_t rk = a.rank[v];
-                    atomicOr(reinterpret_cast<unsigned long long *>(&bitmap[rk >> 6]), 1ull << (rk & 63));
-                }
-            }
-        } else {
-            for (int j = wid; j < d; j += nw) {
-                const int32_t w = row[j];
-                const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
-                for (int p = e0 + ln; p < e1; p += 64) {
-                    const int32_t v = a.o_adj[p];
+        with_rank([&](auto *bm, auto *) {
+            if constexpr (kFlatWalk) {
+                for (int t = tid; t < walk; t += nt) {
+                    int j;
+                    const int32_t v = walk_at(t, j);
                     if (v != x) {
                         const int32_t rk = a.rank[v];
-                        atomicOr(reinterpret_cast<unsigned long long *>(&bitmap[rk >> 6]), 1ull << (rk & 63));
+                        bm_or(&bm[rk >> 6], 1ull << (rk & 63));
+                    }
+                }
+            } else {
+                for (int j = wid; j < d; j += nw) {
+                    const int32_t w = row[j];
+                    const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
+                    for (int p = e0 + ln; p < e1; p += 64) {
+                        const int32_t v = a.o_adj[p];
+                        if (v != x) {
+                            const int32_t rk = a.rank[v];
+                            bm_or(&bm[rk >> 6], 1ull << (rk & 63));
+                        }
                     }
                 }
             }
-        }
+        });
         uint64_t hv_local = 0, rs_local = 0;
         for (int j = tid; j < BITS; j += nt) {
             if (j < d) {
@@ -1794,13 +1822,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
         }
 
         // -- universe numbering: prefix of bitmap popcounts (rank order)
-        block_popcount_prefix(bitmap, bpre, nwords, sh);
+        with_rank([&](auto *bm, auto *bp) { block_popcount_prefix(bm, bp, nwords, sh); });
         wait_mem();
         __syncthreads();
         const int s0 = uni(sh->s0);
         if (s0 > ucap) {
             // the universe does not fit: clear the bitmap, note the size, skip (rerun later)
-            for (int wd = tid; wd < nwords; wd += nt) bitmap[wd] = 0ull;
+            with_rank([&](auto *bm, auto *) {
+                for (int wd = tid; wd < nwords; wd += nt) bm[wd] = 0ull;
+            });
             if (tid == 0) {
                 atomicOr(a.flags, (unsigned int)FLAG_UNIVERSE_OVERFLOW);
                 atomicMax(&a.acc[ACC_NEED_UCAP], (unsigned long long)s0);
@@ -1813,53 +1843,61 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
             }
             continue;
         }
-        const int nq0 = (int)bpre[k >> 6] + __popcll(bitmap[k >> 6] & ((1ull << (k & 63)) - 1ull));
-        c.s0 = s0;
-        for (int wd = tid; wd < nwords; wd += nt) {
-            uint64_t bits = bitmap[wd];
-            uint32_t pos = bpre[wd];
-            while (bits) {
-                const int b = __ffsll((unsigned long long)bits) - 1;
-                bits &= bits - 1ull;
-                gid[pos++] = gd.order[wd * 64 + b];
+        int nq0 = 0;
+        with_rank([&](auto *bm, auto *bp) {
+            nq0 = (int)bp[k >> 6] + __popcll(bm[k >> 6] & ((1ull << (k & 63)) - 1ull));
+            for (int wd = tid; wd < nwords; wd += nt) {
+                uint64_t bits = bm[wd];
+                uint32_t pos = bp[wd];
+                while (bits) {
+                    const int b = __ffsll((unsigned long long)bits) - 1;
+                    bits &= bits - 1ull;
+                    gid[pos++] = gd.order[wd * 64 + b];
+                }
             }
-        }
+        });
+        nq0 = uni(nq0);
+        c.s0 = s0;
         for (size_t q = tid; q < (size_t)s0 * W; q += nt) M[q] = 0ull;
         wait_mem();
         __syncthreads();
 
         // -- reverse scan 2: M[v] gets bit j for every w_j in N(x) adjacent to v
-        if constexpr (kFlatWalk) {
-            for (int t = tid; t < walk; t += nt) {
-                int j;
-                const int32_t v = walk_at(t, j);
-                if (v != x) {
-                    const int32_t rk = a.rank[v];
-                    const uint32_t li =
-                        bpre[rk >> 6] + (uint32_t)__popcll(bitmap[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
-                    atomicOr(reinterpret_cast<unsigned long long *>(&M[(size_t)li * W + (j >> 6)]), 1ull << (j & 63));
-                }
-            }
-        } else {
-            for (int j = wid; j < d; j += nw) {
-                const int32_t w = row[j];
-                const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
-                for (int p = e0 + ln; p < e1; p += 64) {
-                    const int32_t v = a.o_adj[p];
+        with_rank([&](auto *bm, auto *bp) {
+            if constexpr (kFlatWalk) {
+                for (int t = tid; t < walk; t += nt) {
+                    int j;
+                    const int32_t v = walk_at(t, j);
                     if (v != x) {
                         const int32_t rk = a.rank[v];
                         const uint32_t li =
-                            bpre[rk >> 6] + (uint32_t)__popcll(bitmap[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
+                            bp[rk >> 6] + (uint32_t)__popcll(bm[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
                         atomicOr(reinterpret_cast<unsigned long long *>(&M[(size_t)li * W + (j >> 6)]), 1ull << (j & 63));
                     }
                 }
+            } else {
+                for (int j = wid; j < d; j += nw) {
+                    const int32_t w = row[j];
+                    const int32_t e0 = a.o_off[w], e1 = a.o_off[w + 1];
+                    for (int p = e0 + ln; p < e1; p += 64) {
+                        const int32_t v = a.o_adj[p];
+                        if (v != x) {
+                            const int32_t rk = a.rank[v];
+                            const uint32_t li =
+                                bp[rk >> 6] + (uint32_t)__popcll(bm[rk >> 6] & ((1ull << (rk & 63)) - 1ull));
+                            atomicOr(reinterpret_cast<unsigned long long *>(&M[(size_t)li * W + (j >> 6)]), 1ull << (j & 63));
+                        }
+                    }
+                }
             }
-        }
+        });
         __syncthreads();
         see_atomics();  // M was built with atomics
 
         // -- the top-level node for x: counts, maximality against earlier ranks, expansion
-        for (int wd = tid; wd < nwords; wd += nt) bitmap[wd] = 0ull;
+        with_rank([&](auto *bm, auto *) {
+            for (int wd = tid; wd < nwords; wd += nt) bm[wd] = 0ull;
+        });
         {
             bool nm = false;
             int pc = 0, nexp = 0;
@@ -1903,12 +1941,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(W <= 8 ? 4 
         const int P1 = uni(sh->pcount);
         if (TB && tid == 0 && !thief) {
             // x's row; its neighbours' offsets (walk set-up, hash and degree terms); both reverse
-            // scans (rows, ranks, bitmap and mask atomics, the universe index lookups); the terms
-            // per position of N(x); bitmap prefix, universe ids and bitmap clear; universe masks
+            // scans (rows, ranks and mask atomics; bitmap atomics and the universe index lookups
+            // unless the bitmap is in LDS); the terms per position of N(x); bitmap prefix,
+            // universe ids and bitmap clear (the bitmap's part unless in LDS); universe masks
             // cleared, then read with the counts and ids
             const uint64_t dd = (uint64_t)d, wk = (uint64_t)sh->rs1 - 2ull * dd, su = (uint64_t)s0;
-            acc.dbytes += 4ull * (dd + 2ull) + 16ull * dd + 44ull * wk + 12ull * BITS + 32ull * (uint64_t)nwords +
-                          8ull * su + 16ull * W * su + 8ull * su;
+            acc.dbytes += 4ull * (dd + 2ull) + 16ull * dd + (rl ? 24ull : 44ull) * wk + 12ull * BITS +
+                          (rl ? 0ull : 32ull * (uint64_t)nwords) + 8ull * su + 16ull * W * su + 8ull * su;
         }
         if (tid == 0 && !thief) {  // a stolen task's top-level node belongs to its owner
             const uint64_t dx = (uint64_t)d;
@@ -3458,13 +3497,15 @@ __global__ __launch_bounds__(512) void wide_kernel(SearchArgs a, int64_t lo, int
     }
 }
 
-size_t lds_bytes(int W, int waves) { return sizeof(WGShared) + hist_region_bytes(64 * W, waves) + (size_t)waves * kWaveLds; }
+size_t lds_bytes(int W, int waves, int nwords) {
+    return sizeof(WGShared) + hist_region_bytes(64 * W, waves) + (size_t)waves * kWaveLds + rank_lds_bytes(nwords);
+}
 
 template <int W>
 hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, bool tb, int64_t lo, int64_t hi, unsigned int *counter,
                     int grid, int waves, hipStream_t s) {
     dim3 g(grid), b(64 * waves);
-    const size_t lds = lds_bytes(W, waves);
+    const size_t lds = lds_bytes(W, waves, a.dims.nwords);
     if (tb && !diag && !enumerate)
         hipLaunchKernelGGL((search_kernel<W, false, false, true>), g, b, lds, s, a, lo, hi, counter);
     else if (diag && enumerate)
@@ -3481,31 +3522,31 @@ hipError_t launch_w(const SearchArgs &a, bool diag, bool enumerate, bool tb, int
 size_t align_up(size_t x, size_t al) { return (x + al - 1) / al * al; }
 
 template <int W, bool DIAG, bool ENUM>
-int occ(int waves) {
+int occ(int waves, int nwords) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search_kernel<W, DIAG, ENUM>, 64 * waves, lds_bytes(W, waves)) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, search_kernel<W, DIAG, ENUM>, 64 * waves,
+                                                      lds_bytes(W, waves, nwords)) != hipSuccess)
         return 2;
     return nb > 0 ? nb : 1;
 }
 
 template <int W>
-int occ_w(bool diag, bool enumerate, int waves) {
-    if (diag && enumerate) return occ<W, true, true>(waves);
-    if (diag) return occ<W, true, false>(waves);
-    if (enumerate) return occ<W, false, true>(waves);
-    return occ<W, false, false>(waves);
+int occ_w(bool diag, bool enumerate, int waves, int nwords) {
+    if (diag && enumerate) return occ<W, true, true>(waves, nwords);
+    if (diag) return occ<W, true, false>(waves, nwords);
+    if (enumerate) return occ<W, false, true>(waves, nwords);
+    return occ<W, false, false>(waves, nwords);
 }
 
 }  // namespace
 
-int search_occupancy(int W, bool diag, bool enumerate, int waves) {
+int search_occupancy(int W, bool diag, bool enumerate, int waves, int nwords) {
     switch (W) {
-        case 1: return occ_w<1>(diag, enumerate, waves);
-        case 2: return occ_w<2>(diag, enumerate, waves);
-        case 4: return occ_w<4>(diag, enumerate, waves);
-        case 8: return occ_w<8>(diag, enumerate, waves);
-        default: return occ_w<16>(diag, enumerate, waves);
+        case 1: return occ_w<1>(diag, enumerate, waves, nwords);
+        case 2: return occ_w<2>(diag, enumerate, waves, nwords);
+        case 4: return occ_w<4>(diag, enumerate, waves, nwords);
+        case 8: return occ_w<8>(diag, enumerate, waves, nwords);
+        default: return occ_w<16>(diag, enumerate, waves, nwords);
     }
 }
 

@@ -201,10 +201,12 @@ def test_dense_small_deep_trees(mbe, orc, seed):
     _check(mbe, orc, g, f"dense{seed}")
 
 
-def test_long_top_level_lists(mbe, orc):
-    """x's top-level list has 40000 earlier-ranked entries, so its bitmaps span more than one
-    word per thread of the workgroup (the prefix over them is split across threads)."""
-    n = 40000
+@pytest.mark.parametrize("n", [40000, 140000])
+def test_long_top_level_lists(mbe, orc, n):
+    """x's top-level list has n earlier-ranked entries, so its bitmaps span more than one word
+    per thread of the workgroup (the prefix over them is split across threads).  With 40000
+    the rank bitmap of the graph's 40002 candidates is held in LDS; with 140000 (2188 words) it
+    is too large for LDS and stays in the workgroup's arena slot."""
     g = gg.hub_lists(n)
     _say("hub lists", n)
     want = gg.hub_lists_bicliques(n)
